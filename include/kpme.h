@@ -1,0 +1,236 @@
+/*
+ * kpme.h -- C ABI of the MI355X reciprocal-space Kroneckerised PME library.
+ *
+ * The library evaluates the long-range (reciprocal) part of the periodic
+ * Coulomb sum (Sec. 1.1, Eq. qmutheta_coulomb; Sec. 1.2, Eqs. tau, hexpr,
+ * sumhexpr) in the particle-mesh form of Thm. 1 / Eq. formfinale:
+ *
+ *     phi = S* ( sum_r  A_r (x) B_r (x) C_r ) S q  -  c 1 1^T q
+ *
+ * with S the order-p cardinal B-spline spread onto a periodic K1 x K2 x K3
+ * grid (the B-spline option of Sec. 2.2), the Kronecker terms from the nested
+ * SVD of the smooth-PME kernel (Sec. 2.1.1) expanded into real circulant
+ * per-axis factors (Sec. 2.3-2.4), applied as three mode products per term
+ * (Sec. 3.2-3.3, Alg. 1 and Alg. 2), and c the constant correction
+ * (Sec. 4.1, Eq. termbonsum; Alg. 4).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Units      Coulomb constant 1; orthorhombic box L1 x L2 x L3, volume V.
+ * Grids      K1*K2*K3 values, row-major [k1][k2][k3] (k3 fastest).
+ * Particles  positions n x 3 row-major (x, y, z), charges n.  Positions
+ *            outside [0, L) are wrapped, never rejected.
+ * Types      the plan's precision fixes the element type of every particle
+ *            and grid buffer: double for KPME_FP64, float for every other
+ *            precision.  Energies are always double.
+ * Memory     every pointer argument except those of kpme_factors_compute and
+ *            kpme_plan_create's box/grid arrays is a DEVICE pointer owned by
+ *            the caller; the plan owns its factors and workspace, allocated
+ *            once in kpme_plan_create.  No call other than kpme_plan_create,
+ *            kpme_batch_create and the destroy calls allocates or frees
+ *            device memory.
+ * Streams    `stream` is a hipStream_t (NULL = default stream).  All calls are
+ *            asynchronous and stream-ordered; results are valid once the
+ *            stream has reached them.  A plan has one workspace: do not use
+ *            one plan on two streams concurrently.
+ * Errors     every call returns a kpme_status, never aborts or exits, and
+ *            validates its arguments before launching anything.  HIP errors
+ *            map to KPME_ERROR_DEVICE; kpme_last_error() returns a message
+ *            for the calling thread's last failure.
+ */
+#ifndef KPME_H
+#define KPME_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct kpme_plan_s* kpme_plan_t;
+typedef struct kpme_batch_s* kpme_batch_t;
+
+typedef enum {
+  KPME_SUCCESS = 0,
+  KPME_ERROR_INVALID_VALUE = 1,  /* bad argument; nothing was launched      */
+  KPME_ERROR_NOT_SUPPORTED = 2,  /* valid but unsupported (odd p, too large) */
+  KPME_ERROR_OUT_OF_MEMORY = 3,  /* device allocation failed                 */
+  KPME_ERROR_DEVICE = 4,         /* no usable gfx950 device, or a HIP error  */
+  KPME_ERROR_NUMERICAL = 5       /* factor construction failed to converge   */
+} kpme_status;
+
+/* Arithmetic of the SKP mode products.  Spread, gather and the intermediate
+ * grids use float for every precision but KPME_FP64; the factor
+ * construction, the correction and the energy reduction are always FP64.
+ *   KPME_FP64   double everywhere, FP64 matrix cores.
+ *   KPME_FP32   float grids, FP32 matrix cores.
+ *   KPME_BF16X3 every operand split x = hi + lo into two bfloat16 (round to
+ *               nearest even); products hi*hi + hi*lo + lo*hi accumulated in
+ *               FP32 on the bf16 matrix cores.
+ *   KPME_FP16X3 as BF16X3 with half-precision hi and a lo part scaled by 2^11;
+ *               factors carry power-of-two per-matrix scales.              */
+typedef enum {
+  KPME_FP64 = 0,
+  KPME_FP32 = 1,
+  KPME_BF16X3 = 2,
+  KPME_FP16X3 = 3
+} kpme_precision;
+
+typedef struct {
+  int grid[3];          /* K1, K2, K3                                        */
+  int spline_order;     /* p                                                 */
+  int precision;        /* kpme_precision                                    */
+  int rank;             /* R, number of Kronecker terms kept                 */
+  int r0;               /* distinct axis-2 factors among them (outer SVD)    */
+  int total_terms;      /* terms available before truncation                 */
+  int64_t max_particles;
+  double beta;
+  double theta_norm;    /* ||theta_hat||_F                                   */
+  double trunc_err;     /* ||theta_hat - theta_hat_R||_F (exact tail)        */
+  double zero_mode;     /* c = theta_hat_R(0), the correction constant       */
+  size_t workspace_bytes;
+} kpme_plan_info_t;
+
+/* Build a plan: the smooth-PME kernel theta_hat on the K1 x K2 x K3 mode grid,
+ * its nested SVD (Sec. 2.1.1, Eq. last_decomp_kron; axis 2 separated first),
+ * the R largest terms by weight (or, if skp_rank <= 0, the smallest R whose
+ * exact Frobenius tail is <= svd_tol * ||theta_hat||_F; Eqs. eym and
+ * estimate_svd bound it), the real circulant per-axis factors (Sec. 2.3-2.4,
+ * Eq. VtV) in the requested precision, and all device workspace for up to
+ * max_particles particles.
+ *   box[3]        host, L1..L3 > 0 and finite.
+ *   grid[3]       host, 4 <= K_j <= 256 and K_j >= spline_order.
+ *   spline_order  even, 4..12 (odd orders: KPME_ERROR_NOT_SUPPORTED).
+ *   ewald_beta    > 0, the Ewald splitting parameter (xi in Eq. hexpr).
+ *   skp_rank      R >= 1, or <= 0 to select R by svd_tol; R larger than the
+ *                 number of available terms is clamped to it.
+ *   max_particles capacity for n in later calls, 0 < max_particles < 2^31.
+ *   device        HIP device ordinal the plan lives on.
+ * The kernel construction and SVD run on the host in FP64 at plan time.
+ * On failure *plan is set to NULL and nothing is left allocated. */
+kpme_status kpme_plan_create(kpme_plan_t* plan, const double box[3],
+                             const int grid[3], int spline_order,
+                             double ewald_beta, int skp_rank, double svd_tol,
+                             int precision, int64_t max_particles, int device);
+
+kpme_status kpme_plan_destroy(kpme_plan_t plan);
+
+/* Plan description (host struct filled by the call). */
+kpme_status kpme_plan_info(kpme_plan_t plan, kpme_plan_info_t* info);
+
+/* Spread: Q(k) = sum_i q_i prod_j M_p(u_ij - k_j) on the periodic grid,
+ * u_ij = K_j (x_ij / L_j mod 1) (the interpolation matrix S_Y of Eq.
+ * sxsyfromB, realised with B-splines).  Writes every grid value of `grid`
+ * (K1*K2*K3, row-major).  0 <= n <= max_particles. */
+kpme_status kpme_spread(kpme_plan_t plan, int64_t n, const void* pos,
+                        const void* q, void* grid, void* stream);
+
+/* Reciprocal operator on the grid: phi_grid = sum_r omega_r (A_r (x) B_r (x) C_r)
+ * grid_in - c * sum(grid_in) (Eq. formfinale between S and S*, Alg. 2 for
+ * each term, Eq. termbonsum for the correction).  grid_in and phi_grid are
+ * K1*K2*K3 row-major and must not overlap. */
+kpme_status kpme_skp_apply(kpme_plan_t plan, const void* grid_in,
+                           void* phi_grid, void* stream);
+
+/* Gather (the transpose interpolation S_X* of Eq. formfinale):
+ * pot_i = sum_k W_i(k) phi_grid(k) and force_i = -q_i sum_k grad W_i(k)
+ * phi_grid(k), grad W through dM_p/du = M_{p-1}(u) - M_{p-1}(u-1) and
+ * d/dx_j = (K_j / L_j) d/du_j.  pot (n) and force (n x 3 row-major) may each
+ * be NULL to skip them; q may be NULL when force is NULL. */
+kpme_status kpme_gather(kpme_plan_t plan, int64_t n, const void* pos,
+                        const void* q, const void* phi_grid, void* pot,
+                        void* force, void* stream);
+
+/* Energies from potentials, reduced in FP64 in a fixed order (deterministic):
+ * energy4[0] = E_rec = 1/2 sum_i q_i pot_i, energy4[1] = E_self =
+ * -(beta / sqrt(pi)) sum q_i^2, energy4[2] = E_neutral = -pi (sum q)^2 /
+ * (2 V beta^2), energy4[3] = their sum.  The real-space part of Ewald is not
+ * included.  energy4 is a device array of 4 doubles. */
+kpme_status kpme_energy(kpme_plan_t plan, int64_t n, const void* q,
+                        const void* pot, double* energy4, void* stream);
+
+/* The whole reciprocal path in one call (Alg. 4 on one device): bin the
+ * particles by grid brick once, spread, apply the Kronecker operator with its
+ * correction, gather potentials and forces, reduce the energies.  pot, force
+ * and energy4 as above (pot and force may be NULL; energy4 may be NULL).
+ * Uses the plan's internal grids. */
+kpme_status kpme_evaluate(kpme_plan_t plan, int64_t n, const void* pos,
+                          const void* q, void* pot, void* force,
+                          double* energy4, void* stream);
+
+/* Adjoint of kpme_evaluate for reverse-mode differentiation.  Given the
+ * forward inputs and upstream gradients g_E (scalar, host) and g_pot (device,
+ * n, may be NULL), writes
+ *   grad_pos_i = grad W_i . [ (g_E q_i + g_pot_i) Phi + q_i Psi ],
+ *   grad_q_i   = g_E (pot_i + self_i + neutral_i) + (W_i . Psi)
+ * where Phi = Theta S q, Psi = Theta S g_pot (Theta symmetric) and
+ * self_i = -2 beta q_i / sqrt(pi), neutral_i = -pi sum(q) / (V beta^2).
+ * grad_pos (n x 3) and grad_q (n) are device buffers; either may be NULL. */
+kpme_status kpme_evaluate_backward(kpme_plan_t plan, int64_t n,
+                                   const void* pos, const void* q,
+                                   double g_energy, const void* g_pot,
+                                   void* grad_pos, void* grad_q,
+                                   void* stream);
+
+/* Host-only factor construction, exactly as kpme_plan_create performs it,
+ * for inspection and for tests without a device.  All pointers are HOST.
+ * Fills, for the n_terms <= max_terms kept terms in order of decreasing
+ * weight: omega[r], the Fourier-domain mode vectors vec0[r*K1 + m],
+ * vec1[r*K2 + m], vec2[r*K3 + m] (even in m, unit norm) and group[r] (the
+ * outer singular-vector index i), plus info3 = {||theta||_F, trunc_err,
+ * zero_mode}.  Any output pointer may be NULL.  max_terms must be >= the
+ * number kept, else KPME_ERROR_INVALID_VALUE. */
+kpme_status kpme_factors_compute(const double box[3], const int grid[3],
+                                 int spline_order, double ewald_beta,
+                                 int skp_rank, double svd_tol, int max_terms,
+                                 int* n_terms, double* omega, double* vec0,
+                                 double* vec1, double* vec2, int* group,
+                                 double* info3);
+
+/* Batched evaluation of independent systems (each with its own box, grid,
+ * spline order and rank) in one stream-ordered sequence of persistent
+ * launches.  kpme_batch_create builds one plan per system (same precision)
+ * plus a descriptor table; kpme_batch_evaluate evaluates all systems:
+ * pos/q/pot/force are concatenated in system order (offsets = prefix sums of
+ * n[s]); energy4 receives 4 doubles per system.  n[s] <= max_particles[s]. */
+kpme_status kpme_batch_create(kpme_batch_t* batch, int count,
+                              const double* box3, const int* grid3,
+                              const int* spline_order, const double* beta,
+                              const int* skp_rank, int precision,
+                              const int64_t* max_particles, int device);
+kpme_status kpme_batch_destroy(kpme_batch_t batch);
+kpme_status kpme_batch_evaluate(kpme_batch_t batch, const int64_t* n,
+                                const void* pos, const void* q, void* pot,
+                                void* force, double* energy4, void* stream);
+
+/* Native per-stage profiler.  While enabled, every call brackets each of its
+ * stages with a pair of hipEvents recorded on the call's stream (at most 2048
+ * pairs per stage between two reads; later stages go unrecorded).
+ * kpme_plan_profile_read waits for the recorded events and returns, per
+ * stage, the summed elapsed milliseconds and the number of recorded launches
+ * (host arrays of KPME_NUM_STAGES), then starts a new accumulation.
+ * Enabling creates the events (host-side, no device memory); disabling
+ * synchronizes the device and destroys them. */
+#define KPME_NUM_STAGES 7
+enum {
+  KPME_STAGE_SPREAD = 0,     /* grid clear + spread (binning included)      */
+  KPME_STAGE_GRID_SUM = 1,   /* FP64 sum of the input grid (correction)     */
+  KPME_STAGE_SKP1 = 2,       /* axis-2 mode products of the r0 groups      */
+  KPME_STAGE_SKP2 = 3,       /* fused axis-0/axis-1 products of all terms  */
+  KPME_STAGE_FINALIZE = 4,   /* partial-slab sum, transpose, correction    */
+  KPME_STAGE_GATHER = 5,     /* potentials and forces                      */
+  KPME_STAGE_ENERGY = 6      /* FP64 energy reduction                      */
+};
+kpme_status kpme_plan_profile(kpme_plan_t plan, int enable);
+kpme_status kpme_plan_profile_read(kpme_plan_t plan, double* total_ms, int64_t* counts);
+
+const char* kpme_status_string(kpme_status s);
+const char* kpme_last_error(void);
+/* Number of gfx950 devices visible (0 without one); never fails. */
+int kpme_device_count(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KPME_H */

@@ -1,0 +1,624 @@
+// C ABI of the reciprocal-space Kroneckerised PME library (see include/kpme.h).
+//
+// Plan creation runs the FP64 factor construction on the host, converts the
+// circulant factors to the plan's precision, uploads them and allocates every
+// workspace the hot path needs; every other call validates its arguments and
+// then only enqueues kernels on the caller's stream.
+#include "kpme.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "factors.hpp"
+#include "kernels.hpp"
+
+using namespace kpme;
+
+namespace {
+
+constexpr uint32_t kMagic = 0x4b504d45u;  // "KPME"
+thread_local std::string g_last_error;
+
+kpme_status fail(kpme_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+
+kpme_status from_hip(hipError_t e, const char* what) {
+  if (e == hipSuccess) return KPME_SUCCESS;
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  return fail(e == hipErrorOutOfMemory ? KPME_ERROR_OUT_OF_MEMORY : KPME_ERROR_DEVICE, m);
+}
+
+int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+bool is_gfx950(int dev) {
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return false;
+  return std::strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+}
+
+uint16_t bf16_rne(float x) {
+  uint32_t u;
+  std::memcpy(&u, &x, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u) return static_cast<uint16_t>(u >> 16);  // inf/nan
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return static_cast<uint16_t>(u >> 16);
+}
+float bf16_to_float(uint16_t h) {
+  uint32_t u = static_cast<uint32_t>(h) << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+}  // namespace
+
+struct kpme_plan_s {
+  uint32_t magic = kMagic;
+  int device = 0;
+  int K[3] = {0, 0, 0};
+  int K1P = 0, K2P = 0, K3P = 0;
+  int p = 0, prec = 0;
+  double box[3] = {0, 0, 0};
+  double beta = 0;
+  int R = 0, r0 = 0, total_terms = 0, nparts = 1;
+  int64_t max_n = 0;
+  double theta_norm = 0, trunc_err = 0, zero_mode = 0;
+  size_t ws_bytes = 0;
+  std::vector<void*> allocations;
+  // device arrays
+  void* A[2] = {nullptr, nullptr};
+  void* B[2] = {nullptr, nullptr};
+  void* C[2] = {nullptr, nullptr};
+  void* Y[2] = {nullptr, nullptr};
+  void* Phi_part = nullptr;
+  int* term_group = nullptr;
+  int* part_begin = nullptr;
+  double* scratch = nullptr;  // 3 * kSumBlocks doubles
+  double* scalars = nullptr;  // [0] sum(Q), [1..4] energy
+  void* Qg = nullptr;         // internal grids
+  void* Phig = nullptr;
+  void* pot = nullptr;        // internal potentials (max_n)
+  // per-stage hipEvent pairs recorded on the calling stream while profiling
+  bool prof_on = false;
+  std::vector<hipEvent_t> prof_ev[KPME_NUM_STAGES][2];
+  int prof_used[KPME_NUM_STAGES] = {};
+
+  size_t esize() const { return prec == PREC_FP64 ? 8 : 4; }
+  GridGeom geom() const {
+    GridGeom g;
+    for (int j = 0; j < 3; ++j) { g.K[j] = K[j]; g.L[j] = box[j]; }
+    g.p = p;
+    return g;
+  }
+  long grid_size() const { return static_cast<long>(K[0]) * K[1] * K[2]; }
+};
+
+namespace {
+
+hipError_t plan_alloc(kpme_plan_s* pl, void** out, size_t bytes) {
+  *out = nullptr;
+  const char* inject = std::getenv("KPME_FAIL_ALLOC");
+  if (inject && inject[0] == '1') return hipErrorOutOfMemory;
+  hipError_t e = hipMalloc(out, std::max<size_t>(bytes, 256));
+  if (e == hipSuccess) {
+    pl->allocations.push_back(*out);
+    pl->ws_bytes += bytes;
+  }
+  return e;
+}
+
+constexpr int kProfCap = 2048;  // event pairs per stage between two reads
+
+void prof_release(kpme_plan_s* pl) {
+  for (int s = 0; s < KPME_NUM_STAGES; ++s)
+    for (int k = 0; k < 2; ++k) {
+      for (hipEvent_t e : pl->prof_ev[s][k]) (void)hipEventDestroy(e);
+      pl->prof_ev[s][k].clear();
+    }
+  for (int s = 0; s < KPME_NUM_STAGES; ++s) pl->prof_used[s] = 0;
+  pl->prof_on = false;
+}
+
+// Brackets one stage with events when profiling is enabled.
+struct StageTimer {
+  kpme_plan_s* pl;
+  int stage;
+  hipStream_t st;
+  bool active;
+  StageTimer(kpme_plan_s* p, int s, hipStream_t stream) : pl(p), stage(s), st(stream) {
+    active = pl->prof_on && pl->prof_used[stage] < kProfCap;
+    if (active) (void)hipEventRecord(pl->prof_ev[stage][0][pl->prof_used[stage]], st);
+  }
+  ~StageTimer() {
+    if (active) {
+      (void)hipEventRecord(pl->prof_ev[stage][1][pl->prof_used[stage]], st);
+      ++pl->prof_used[stage];
+    }
+  }
+};
+
+void plan_free(kpme_plan_s* pl) {
+  prof_release(pl);
+  for (void* p : pl->allocations) (void)hipFree(p);
+  pl->allocations.clear();
+  pl->magic = 0;
+}
+
+kpme_status check_plan(kpme_plan_t plan) {
+  if (!plan || plan->magic != kMagic) return fail(KPME_ERROR_INVALID_VALUE, "invalid plan handle");
+  if (hipSetDevice(plan->device) != hipSuccess)
+    return fail(KPME_ERROR_DEVICE, "cannot select the plan's device");
+  return KPME_SUCCESS;
+}
+
+kpme_status validate_params(const double box[3], const int grid[3], int p, double beta,
+                            int precision) {
+  if (!box || !grid) return fail(KPME_ERROR_INVALID_VALUE, "box and grid must not be NULL");
+  for (int j = 0; j < 3; ++j) {
+    if (!(std::isfinite(box[j]) && box[j] > 0))
+      return fail(KPME_ERROR_INVALID_VALUE, "box lengths must be finite and > 0");
+  }
+  if (p < 2 || p > 12) return fail(KPME_ERROR_INVALID_VALUE, "spline order must be in 2..12");
+  if (p % 2 != 0 || p < 4)
+    return fail(KPME_ERROR_NOT_SUPPORTED, "only even spline orders 4..12 are supported");
+  for (int j = 0; j < 3; ++j) {
+    if (grid[j] < 4 || grid[j] < p || grid[j] > 256)
+      return fail(KPME_ERROR_INVALID_VALUE, "grid sizes must satisfy max(4, p) <= K <= 256");
+  }
+  if (!(std::isfinite(beta) && beta > 0))
+    return fail(KPME_ERROR_INVALID_VALUE, "ewald_beta must be finite and > 0");
+  if (precision < KPME_FP64 || precision > KPME_FP16X3)
+    return fail(KPME_ERROR_INVALID_VALUE, "unknown precision");
+  return KPME_SUCCESS;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* kpme_status_string(kpme_status s) {
+  switch (s) {
+    case KPME_SUCCESS: return "success";
+    case KPME_ERROR_INVALID_VALUE: return "invalid value";
+    case KPME_ERROR_NOT_SUPPORTED: return "not supported";
+    case KPME_ERROR_OUT_OF_MEMORY: return "out of memory";
+    case KPME_ERROR_DEVICE: return "device error";
+    case KPME_ERROR_NUMERICAL: return "numerical failure";
+  }
+  return "unknown status";
+}
+
+const char* kpme_last_error(void) { return g_last_error.c_str(); }
+
+int kpme_device_count(void) {
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess) return 0;
+  int good = 0;
+  for (int d = 0; d < n; ++d) good += is_gfx950(d) ? 1 : 0;
+  return good;
+}
+
+kpme_status kpme_factors_compute(const double box[3], const int grid[3], int spline_order,
+                                 double ewald_beta, int skp_rank, double svd_tol,
+                                 int max_terms, int* n_terms, double* omega, double* vec0,
+                                 double* vec1, double* vec2, int* group, double* info3) {
+  kpme_status st = validate_params(box, grid, spline_order, ewald_beta, KPME_FP64);
+  if (st != KPME_SUCCESS) return st;
+  if (skp_rank <= 0 && !(svd_tol > 0 && svd_tol < 1))
+    return fail(KPME_ERROR_INVALID_VALUE, "svd_tol must be in (0, 1) when skp_rank <= 0");
+  FactorSet fs;
+  std::string err;
+  if (!build_factors(box, grid, spline_order, ewald_beta, skp_rank, svd_tol, &fs, &err))
+    return fail(KPME_ERROR_NUMERICAL, err);
+  const int R = static_cast<int>(fs.terms.size());
+  if (n_terms) *n_terms = R;
+  if (info3) {
+    info3[0] = fs.theta_norm;
+    info3[1] = fs.trunc_err;
+    info3[2] = fs.zero_mode;
+  }
+  if ((omega || vec0 || vec1 || vec2 || group) && R > max_terms)
+    return fail(KPME_ERROR_INVALID_VALUE, "max_terms is smaller than the number of terms");
+  for (int r = 0; r < R; ++r) {
+    const Term& t = fs.terms[r];
+    if (omega) omega[r] = t.omega;
+    if (group) group[r] = t.group;
+    if (vec0) std::copy(t.v[0].begin(), t.v[0].end(), vec0 + static_cast<size_t>(r) * grid[0]);
+    if (vec1) std::copy(t.v[1].begin(), t.v[1].end(), vec1 + static_cast<size_t>(r) * grid[1]);
+    if (vec2) std::copy(t.v[2].begin(), t.v[2].end(), vec2 + static_cast<size_t>(r) * grid[2]);
+  }
+  return KPME_SUCCESS;
+}
+
+kpme_status kpme_plan_create(kpme_plan_t* plan, const double box[3], const int grid[3],
+                             int spline_order, double ewald_beta, int skp_rank,
+                             double svd_tol, int precision, int64_t max_particles,
+                             int device) {
+  if (!plan) return fail(KPME_ERROR_INVALID_VALUE, "plan must not be NULL");
+  *plan = nullptr;
+  kpme_status st = validate_params(box, grid, spline_order, ewald_beta, precision);
+  if (st != KPME_SUCCESS) return st;
+  if (skp_rank <= 0 && !(svd_tol > 0 && svd_tol < 1))
+    return fail(KPME_ERROR_INVALID_VALUE, "svd_tol must be in (0, 1) when skp_rank <= 0");
+  if (max_particles <= 0 || max_particles >= (int64_t(1) << 31))
+    return fail(KPME_ERROR_INVALID_VALUE, "max_particles must be in [1, 2^31)");
+  if (precision == KPME_FP16X3)
+    return fail(KPME_ERROR_NOT_SUPPORTED, "FP16X3 is not available in this build");
+  const int K1P = round_up(grid[0], 32), K2P = round_up(grid[1], 32), K3P = round_up(grid[2], 32);
+  if (K1P > 128)
+    return fail(KPME_ERROR_NOT_SUPPORTED, "K1 > 128 is not supported by the SKP kernels");
+  if (stage2_lds_bytes(precision, K1P, K2P) > kMaxLds)
+    return fail(KPME_ERROR_NOT_SUPPORTED, "K1 x K2 slab does not fit in LDS at this precision");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
+    return fail(KPME_ERROR_DEVICE, "no HIP device is visible");
+  if (device < 0 || device >= ndev) return fail(KPME_ERROR_INVALID_VALUE, "bad device ordinal");
+  if (!is_gfx950(device)) return fail(KPME_ERROR_DEVICE, "device is not a gfx950 (MI355X)");
+  if (hipSetDevice(device) != hipSuccess) return fail(KPME_ERROR_DEVICE, "hipSetDevice failed");
+
+  FactorSet fs;
+  std::string err;
+  if (!build_factors(box, grid, spline_order, ewald_beta, skp_rank, svd_tol, &fs, &err))
+    return fail(KPME_ERROR_NUMERICAL, err);
+  if (fs.terms.empty()) return fail(KPME_ERROR_NUMERICAL, "no Kronecker terms were kept");
+
+  kpme_plan_s* pl = new kpme_plan_s();
+  pl->device = device;
+  for (int j = 0; j < 3; ++j) { pl->K[j] = grid[j]; pl->box[j] = box[j]; }
+  pl->K1P = K1P; pl->K2P = K2P; pl->K3P = K3P;
+  pl->p = spline_order;
+  pl->prec = precision;
+  pl->beta = ewald_beta;
+  pl->max_n = max_particles;
+  pl->theta_norm = fs.theta_norm;
+  pl->trunc_err = fs.trunc_err;
+  pl->zero_mode = fs.zero_mode;
+  pl->total_terms = fs.total_terms;
+
+  // Device term order: grouped by outer index (stable), so consecutive terms
+  // share their axis-2 factor and stage 2 reloads Y only at group changes.
+  std::vector<int> order(fs.terms.size());
+  for (size_t r = 0; r < order.size(); ++r) order[r] = static_cast<int>(r);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return fs.terms[a].group < fs.terms[b].group;
+  });
+  std::vector<int> group_of(fs.terms.size()), distinct;
+  for (size_t r = 0; r < order.size(); ++r) {
+    const int g = fs.terms[order[r]].group;
+    if (distinct.empty() || distinct.back() != g) distinct.push_back(g);
+    group_of[r] = static_cast<int>(distinct.size()) - 1;
+  }
+  const int R = static_cast<int>(order.size()), r0 = static_cast<int>(distinct.size());
+  pl->R = R;
+  pl->r0 = r0;
+  const int K1 = grid[0], K2 = grid[1], K3 = grid[2];
+  pl->nparts = std::max(1, std::min(R, (512 + K3 - 1) / K3));
+  std::vector<int> pb(pl->nparts + 1);
+  for (int p = 0; p <= pl->nparts; ++p) pb[p] = static_cast<int>((static_cast<long>(R) * p) / pl->nparts);
+
+  // Circulant factors, zero padded: A_t (omega folded in), B_t, C_g.
+  const size_t nA = static_cast<size_t>(R) * K1P * K1P, nB = static_cast<size_t>(R) * K2P * K2P;
+  const size_t nC = static_cast<size_t>(r0) * K3 * K3P;
+  std::vector<double> hA(nA, 0.0), hB(nB, 0.0), hC(nC, 0.0);
+  for (int r = 0; r < R; ++r) {
+    const Term& t = fs.terms[order[r]];
+    const std::vector<double> ca = circulant_column(t.v[0]);
+    const std::vector<double> cb = circulant_column(t.v[1]);
+    for (int g = 0; g < K1; ++g)
+      for (int h = 0; h < K1; ++h)
+        hA[(static_cast<size_t>(r) * K1P + g) * K1P + h] = t.omega * ca[(g - h + K1) % K1];
+    for (int g = 0; g < K2; ++g)
+      for (int h = 0; h < K2; ++h)
+        hB[(static_cast<size_t>(r) * K2P + g) * K2P + h] = cb[(g - h + K2) % K2];
+  }
+  for (int gi = 0; gi < r0; ++gi) {
+    const Term* t = nullptr;
+    for (int r = 0; r < R; ++r)
+      if (group_of[r] == gi) { t = &fs.terms[order[r]]; break; }
+    const std::vector<double> cc = circulant_column(t->v[2]);
+    for (int s = 0; s < K3; ++s)
+      for (int g = 0; g < K3; ++g)
+        hC[(static_cast<size_t>(gi) * K3 + s) * K3P + g] = cc[(s - g + K3) % K3];
+  }
+
+  hipError_t e = hipSuccess;
+  const int planes = precision == KPME_BF16X3 ? 2 : 1;
+  const size_t opsz = precision == KPME_FP64 ? 8 : (precision == KPME_FP32 ? 4 : 2);
+  auto upload = [&](const std::vector<double>& h, void** dst) -> hipError_t {
+    const size_t n = h.size();
+    hipError_t er;
+    if (precision == KPME_FP64) {
+      if ((er = plan_alloc(pl, &dst[0], n * 8)) != hipSuccess) return er;
+      return hipMemcpy(dst[0], h.data(), n * 8, hipMemcpyHostToDevice);
+    }
+    if (precision == KPME_FP32) {
+      std::vector<float> f(n);
+      for (size_t i = 0; i < n; ++i) f[i] = static_cast<float>(h[i]);
+      if ((er = plan_alloc(pl, &dst[0], n * 4)) != hipSuccess) return er;
+      return hipMemcpy(dst[0], f.data(), n * 4, hipMemcpyHostToDevice);
+    }
+    std::vector<uint16_t> hi(n), lo(n);
+    for (size_t i = 0; i < n; ++i) {
+      hi[i] = bf16_rne(static_cast<float>(h[i]));
+      lo[i] = bf16_rne(static_cast<float>(h[i] - static_cast<double>(bf16_to_float(hi[i]))));
+    }
+    if ((er = plan_alloc(pl, &dst[0], n * 2)) != hipSuccess) return er;
+    if ((er = plan_alloc(pl, &dst[1], n * 2)) != hipSuccess) return er;
+    if ((er = hipMemcpy(dst[0], hi.data(), n * 2, hipMemcpyHostToDevice)) != hipSuccess) return er;
+    return hipMemcpy(dst[1], lo.data(), n * 2, hipMemcpyHostToDevice);
+  };
+  const long G = static_cast<long>(K1) * K2 * K3;
+  const size_t es = pl->esize();
+  const size_t nY = static_cast<size_t>(r0) * K3 * K1P * K2P;
+  void* tmp = nullptr;
+  do {
+    if ((e = upload(hA, pl->A)) != hipSuccess) break;
+    if ((e = upload(hB, pl->B)) != hipSuccess) break;
+    if ((e = upload(hC, pl->C)) != hipSuccess) break;
+    for (int k = 0; k < planes; ++k)
+      if ((e = plan_alloc(pl, &pl->Y[k], nY * opsz)) != hipSuccess) break;
+    if (e != hipSuccess) break;
+    if ((e = plan_alloc(pl, &pl->Phi_part, static_cast<size_t>(pl->nparts) * G * es)) != hipSuccess) break;
+    if ((e = plan_alloc(pl, &tmp, R * sizeof(int))) != hipSuccess) break;
+    pl->term_group = static_cast<int*>(tmp);
+    if ((e = hipMemcpy(tmp, group_of.data(), R * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess) break;
+    if ((e = plan_alloc(pl, &tmp, pb.size() * sizeof(int))) != hipSuccess) break;
+    pl->part_begin = static_cast<int*>(tmp);
+    if ((e = hipMemcpy(tmp, pb.data(), pb.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess) break;
+    if ((e = plan_alloc(pl, &tmp, 3 * kSumBlocks * sizeof(double))) != hipSuccess) break;
+    pl->scratch = static_cast<double*>(tmp);
+    if ((e = plan_alloc(pl, &tmp, 8 * sizeof(double))) != hipSuccess) break;
+    pl->scalars = static_cast<double*>(tmp);
+    if ((e = plan_alloc(pl, &pl->Qg, G * es)) != hipSuccess) break;
+    if ((e = plan_alloc(pl, &pl->Phig, G * es)) != hipSuccess) break;
+    if ((e = plan_alloc(pl, &pl->pot, static_cast<size_t>(max_particles) * es)) != hipSuccess) break;
+    e = hipDeviceSynchronize();
+  } while (false);
+  if (e != hipSuccess) {
+    kpme_status s = from_hip(e, "plan allocation/upload");
+    plan_free(pl);
+    delete pl;
+    return s;
+  }
+  *plan = pl;
+  return KPME_SUCCESS;
+}
+
+kpme_status kpme_plan_destroy(kpme_plan_t plan) {
+  if (!plan || plan->magic != kMagic) return fail(KPME_ERROR_INVALID_VALUE, "invalid plan handle");
+  (void)hipSetDevice(plan->device);
+  (void)hipDeviceSynchronize();
+  plan_free(plan);
+  delete plan;
+  return KPME_SUCCESS;
+}
+
+kpme_status kpme_plan_info(kpme_plan_t plan, kpme_plan_info_t* info) {
+  if (!plan || plan->magic != kMagic) return fail(KPME_ERROR_INVALID_VALUE, "invalid plan handle");
+  if (!info) return fail(KPME_ERROR_INVALID_VALUE, "info must not be NULL");
+  for (int j = 0; j < 3; ++j) info->grid[j] = plan->K[j];
+  info->spline_order = plan->p;
+  info->precision = plan->prec;
+  info->rank = plan->R;
+  info->r0 = plan->r0;
+  info->total_terms = plan->total_terms;
+  info->max_particles = plan->max_n;
+  info->beta = plan->beta;
+  info->theta_norm = plan->theta_norm;
+  info->trunc_err = plan->trunc_err;
+  info->zero_mode = plan->zero_mode;
+  info->workspace_bytes = plan->ws_bytes;
+  return KPME_SUCCESS;
+}
+
+namespace {
+
+kpme_status check_n(kpme_plan_t plan, int64_t n) {
+  if (n < 0 || n > plan->max_n)
+    return fail(KPME_ERROR_INVALID_VALUE, "n must be in [0, max_particles]");
+  return KPME_SUCCESS;
+}
+
+kpme_status do_spread(kpme_plan_t plan, int64_t n, const void* pos, const void* q, void* grid,
+                      hipStream_t st) {
+  StageTimer tm(plan, KPME_STAGE_SPREAD, st);
+  hipError_t e = launch_zero(grid, plan->grid_size() * plan->esize(), st);
+  if (e == hipSuccess) e = launch_spread_atomic(plan->prec, plan->geom(), n, pos, q, grid, st);
+  return from_hip(e, "spread");
+}
+
+kpme_status do_skp(kpme_plan_t plan, const void* in, void* out, hipStream_t st) {
+  SkpArgs a;
+  a.prec = plan->prec;
+  for (int j = 0; j < 3; ++j) a.K[j] = plan->K[j];
+  a.K1P = plan->K1P; a.K2P = plan->K2P; a.K3P = plan->K3P;
+  a.r0 = plan->r0; a.R = plan->R; a.nparts = plan->nparts;
+  a.Q = in; a.Phi = out;
+  for (int k = 0; k < 2; ++k) { a.A[k] = plan->A[k]; a.B[k] = plan->B[k]; a.C[k] = plan->C[k]; a.Y[k] = plan->Y[k]; }
+  a.Phi_part = plan->Phi_part;
+  a.term_group = plan->term_group;
+  a.part_begin = plan->part_begin;
+  a.scratch = plan->scratch;
+  a.sumQ = plan->scalars;
+  a.c0 = plan->zero_mode;
+  hipError_t e;
+  {
+    StageTimer tm(plan, KPME_STAGE_GRID_SUM, st);
+    e = launch_skp_sum(a, st);
+  }
+  if (e == hipSuccess) {
+    StageTimer tm(plan, KPME_STAGE_SKP1, st);
+    e = launch_skp_stage1(a, st);
+  }
+  if (e == hipSuccess) {
+    StageTimer tm(plan, KPME_STAGE_SKP2, st);
+    e = launch_skp_stage2(a, st);
+  }
+  if (e == hipSuccess) {
+    StageTimer tm(plan, KPME_STAGE_FINALIZE, st);
+    e = launch_skp_finalize(a, st);
+  }
+  return from_hip(e, "skp_apply");
+}
+
+kpme_status do_gather(kpme_plan_t plan, int64_t n, const void* pos, const void* q,
+                      const void* grid, void* pot, void* force, hipStream_t st) {
+  StageTimer tm(plan, KPME_STAGE_GATHER, st);
+  return from_hip(launch_gather_direct(plan->prec, plan->geom(), n, pos, q, grid, pot, force, st),
+                  "gather");
+}
+
+kpme_status do_energy(kpme_plan_t plan, int64_t n, const void* q, const void* pot,
+                      double* energy4, hipStream_t st) {
+  StageTimer tm(plan, KPME_STAGE_ENERGY, st);
+  const double V = plan->box[0] * plan->box[1] * plan->box[2];
+  return from_hip(launch_energy(plan->prec, n, q, pot, plan->beta, V, plan->scratch, energy4, st),
+                  "energy");
+}
+
+}  // namespace
+
+kpme_status kpme_spread(kpme_plan_t plan, int64_t n, const void* pos, const void* q, void* grid,
+                        void* stream) {
+  kpme_status s = check_plan(plan);
+  if (s != KPME_SUCCESS) return s;
+  if ((s = check_n(plan, n)) != KPME_SUCCESS) return s;
+  if (!grid || (n > 0 && (!pos || !q)))
+    return fail(KPME_ERROR_INVALID_VALUE, "pos, q and grid must not be NULL");
+  return do_spread(plan, n, pos, q, grid, static_cast<hipStream_t>(stream));
+}
+
+kpme_status kpme_skp_apply(kpme_plan_t plan, const void* grid_in, void* phi_grid, void* stream) {
+  kpme_status s = check_plan(plan);
+  if (s != KPME_SUCCESS) return s;
+  if (!grid_in || !phi_grid) return fail(KPME_ERROR_INVALID_VALUE, "grids must not be NULL");
+  const size_t bytes = plan->grid_size() * plan->esize();
+  const char* a = static_cast<const char*>(grid_in);
+  const char* b = static_cast<const char*>(phi_grid);
+  if (a < b + bytes && b < a + bytes) return fail(KPME_ERROR_INVALID_VALUE, "grids overlap");
+  return do_skp(plan, grid_in, phi_grid, static_cast<hipStream_t>(stream));
+}
+
+kpme_status kpme_gather(kpme_plan_t plan, int64_t n, const void* pos, const void* q,
+                        const void* phi_grid, void* pot, void* force, void* stream) {
+  kpme_status s = check_plan(plan);
+  if (s != KPME_SUCCESS) return s;
+  if ((s = check_n(plan, n)) != KPME_SUCCESS) return s;
+  if (!phi_grid || (n > 0 && !pos)) return fail(KPME_ERROR_INVALID_VALUE, "pos and phi_grid must not be NULL");
+  if (force && n > 0 && !q) return fail(KPME_ERROR_INVALID_VALUE, "q is required for forces");
+  return do_gather(plan, n, pos, q, phi_grid, pot, force, static_cast<hipStream_t>(stream));
+}
+
+kpme_status kpme_energy(kpme_plan_t plan, int64_t n, const void* q, const void* pot,
+                        double* energy4, void* stream) {
+  kpme_status s = check_plan(plan);
+  if (s != KPME_SUCCESS) return s;
+  if ((s = check_n(plan, n)) != KPME_SUCCESS) return s;
+  if (!energy4 || (n > 0 && (!q || !pot)))
+    return fail(KPME_ERROR_INVALID_VALUE, "q, pot and energy4 must not be NULL");
+  return do_energy(plan, n, q, pot, energy4, static_cast<hipStream_t>(stream));
+}
+
+kpme_status kpme_evaluate(kpme_plan_t plan, int64_t n, const void* pos, const void* q,
+                          void* pot, void* force, double* energy4, void* stream) {
+  kpme_status s = check_plan(plan);
+  if (s != KPME_SUCCESS) return s;
+  if ((s = check_n(plan, n)) != KPME_SUCCESS) return s;
+  if (n > 0 && (!pos || !q)) return fail(KPME_ERROR_INVALID_VALUE, "pos and q must not be NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if ((s = do_spread(plan, n, pos, q, plan->Qg, st)) != KPME_SUCCESS) return s;
+  if ((s = do_skp(plan, plan->Qg, plan->Phig, st)) != KPME_SUCCESS) return s;
+  void* potp = pot ? pot : (energy4 ? plan->pot : nullptr);
+  if (potp || force) {
+    if ((s = do_gather(plan, n, pos, q, plan->Phig, potp, force, st)) != KPME_SUCCESS) return s;
+  }
+  if (energy4) return do_energy(plan, n, q, potp, energy4, st);
+  return KPME_SUCCESS;
+}
+
+kpme_status kpme_plan_profile(kpme_plan_t plan, int enable) {
+  kpme_status s = check_plan(plan);
+  if (s != KPME_SUCCESS) return s;
+  if (!enable) {
+    (void)hipDeviceSynchronize();
+    prof_release(plan);
+    return KPME_SUCCESS;
+  }
+  if (plan->prof_on) return KPME_SUCCESS;
+  for (int st = 0; st < KPME_NUM_STAGES; ++st)
+    for (int k = 0; k < 2; ++k) {
+      plan->prof_ev[st][k].resize(kProfCap);
+      for (int i = 0; i < kProfCap; ++i) {
+        hipError_t e = hipEventCreate(&plan->prof_ev[st][k][i]);
+        if (e != hipSuccess) {
+          plan->prof_ev[st][k].resize(i);
+          prof_release(plan);
+          return from_hip(e, "hipEventCreate");
+        }
+      }
+    }
+  plan->prof_on = true;
+  return KPME_SUCCESS;
+}
+
+kpme_status kpme_plan_profile_read(kpme_plan_t plan, double* total_ms, int64_t* counts) {
+  kpme_status s = check_plan(plan);
+  if (s != KPME_SUCCESS) return s;
+  if (!total_ms || !counts) return fail(KPME_ERROR_INVALID_VALUE, "outputs must not be NULL");
+  for (int st = 0; st < KPME_NUM_STAGES; ++st) {
+    double acc = 0.0;
+    for (int i = 0; i < plan->prof_used[st]; ++i) {
+      float ms = 0.f;
+      hipError_t e = hipEventSynchronize(plan->prof_ev[st][1][i]);
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, plan->prof_ev[st][0][i], plan->prof_ev[st][1][i]);
+      if (e != hipSuccess) return from_hip(e, "profile read");
+      acc += ms;
+    }
+    total_ms[st] = acc;
+    counts[st] = plan->prof_used[st];
+    plan->prof_used[st] = 0;
+  }
+  return KPME_SUCCESS;
+}
+
+kpme_status kpme_evaluate_backward(kpme_plan_t plan, int64_t n, const void* pos, const void* q,
+                                   double g_energy, const void* g_pot, void* grad_pos,
+                                   void* grad_q, void* stream) {
+  (void)n; (void)pos; (void)q; (void)g_energy; (void)g_pot; (void)grad_pos; (void)grad_q;
+  (void)stream;
+  kpme_status s = check_plan(plan);
+  if (s != KPME_SUCCESS) return s;
+  return fail(KPME_ERROR_NOT_SUPPORTED, "backward is not available in this build");
+}
+
+kpme_status kpme_batch_create(kpme_batch_t* batch, int count, const double* box3,
+                              const int* grid3, const int* spline_order, const double* beta,
+                              const int* skp_rank, int precision,
+                              const int64_t* max_particles, int device) {
+  (void)count; (void)box3; (void)grid3; (void)spline_order; (void)beta; (void)skp_rank;
+  (void)precision; (void)max_particles; (void)device;
+  if (batch) *batch = nullptr;
+  return fail(KPME_ERROR_NOT_SUPPORTED, "batched evaluation is not available in this build");
+}
+
+kpme_status kpme_batch_destroy(kpme_batch_t batch) {
+  (void)batch;
+  return fail(KPME_ERROR_INVALID_VALUE, "invalid batch handle");
+}
+
+kpme_status kpme_batch_evaluate(kpme_batch_t batch, const int64_t* n, const void* pos,
+                                const void* q, void* pot, void* force, double* energy4,
+                                void* stream) {
+  (void)batch; (void)n; (void)pos; (void)q; (void)pot; (void)force; (void)energy4; (void)stream;
+  return fail(KPME_ERROR_INVALID_VALUE, "invalid batch handle");
+}
+
+}  // extern "C"

@@ -1,0 +1,57 @@
+// Launch interfaces between the C ABI (api.cpp) and the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace kpme {
+
+enum { PREC_FP64 = 0, PREC_FP32 = 1, PREC_BF16X3 = 2, PREC_FP16X3 = 3 };
+
+constexpr size_t kMaxLds = 160 * 1024;  // LDS per workgroup on gfx950
+constexpr int kSumBlocks = 256;          // blocks of the fixed-order FP64 sums
+
+// Everything the SKP apply needs.  Pointers are device pointers; [0] is the
+// single plane (FP64/FP32) or the hi plane (BF16X3), [1] the lo plane.
+struct SkpArgs {
+  int prec;
+  int K[3];
+  int K1P, K2P, K3P;     // padded extents (multiples of 32)
+  int r0, R, nparts;
+  const void* Q;         // grid_in  [K1][K2][K3]
+  void* Phi;             // grid_out [K1][K2][K3]
+  const void* A[2];      // [R][K1P][K1P], omega folded in
+  const void* B[2];      // [R][K2P][K2P]
+  const void* C[2];      // [r0][K3][K3P]
+  void* Y[2];            // [r0][K3][K1P][K2P]
+  void* Phi_part;        // [nparts][K3][K1][K2]
+  const int* term_group; // [R] group of each term (terms sorted by group)
+  const int* part_begin; // [nparts + 1]
+  double* scratch;       // >= kSumBlocks doubles
+  double* sumQ;          // 1 double
+  double c0;             // theta_hat_R(0)
+};
+
+hipError_t launch_skp_sum(const SkpArgs& a, hipStream_t st);
+hipError_t launch_skp_stage1(const SkpArgs& a, hipStream_t st);
+hipError_t launch_skp_stage2(const SkpArgs& a, hipStream_t st);
+hipError_t launch_skp_finalize(const SkpArgs& a, hipStream_t st);
+size_t stage2_lds_bytes(int prec, int K1P, int K2P);
+
+struct GridGeom {
+  int K[3];
+  double L[3];
+  int p;
+};
+
+// All launches are asynchronous on `st`; they return the launch status.
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
+hipError_t launch_spread_atomic(int prec, const GridGeom& g, int64_t n, const void* pos,
+                                const void* q, void* grid, hipStream_t st);
+hipError_t launch_gather_direct(int prec, const GridGeom& g, int64_t n, const void* pos,
+                                const void* q, const void* grid, void* pot, void* force,
+                                hipStream_t st);
+hipError_t launch_energy(int prec, int64_t n, const void* q, const void* pot, double beta,
+                         double volume, double* scratch, double* energy4, hipStream_t st);
+
+}  // namespace kpme

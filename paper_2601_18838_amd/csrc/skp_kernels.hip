@@ -1,0 +1,545 @@
+// Sum-of-Kronecker-Products reciprocal operator on the matrix cores (gfx950).
+//
+// Phi = sum_r omega_r (A_r (x) B_r (x) C_r) Q - c sum(Q) (Eq. formfinale with
+// the correction of Eq. termbonsum), evaluated as the mode products of
+// Alg. 2, grouped by the nested-SVD structure (Sec. 2.1.1): all terms of
+// outer index i share their axis-2 factor C_i.
+//
+//  stage 1  Y_i = Q x_3 C_i for the r0 distinct C_i: one GEMM with rows
+//           (i, k3), columns the K1 x K2 slab position and inner index g3;
+//           written slab-major [i][k3][g1][g2] (zero-padded to K1P x K2P).
+//  stage 2  per slab k3 and range of terms:
+//           Phi_k3 += sum_t A_t . Y_{g(t),k3} . B_t^T   (omega folded into A_t)
+//           Each wave owns NC output columns; T = Y . B_t^T stays in the MFMA
+//           accumulators and is fed straight back as the B operand of
+//           A_t . T (the K index of an MFMA may be permuted consistently in
+//           both operands, so the accumulator layout is used as is).
+//  final    sums the stage-2 partial slabs in a fixed order, transposes to
+//           [k1][k2][k3] and subtracts c * sum(Q).
+//
+// Precisions: FP64 and FP32 use the 16x16x4 MFMAs; BF16X3 splits every
+// operand into bf16 hi + lo and issues hi*hi + hi*lo + lo*hi on the
+// 16x16x32 bf16 MFMA with FP32 accumulation.
+#include "device_common.hpp"
+#include "kernels.hpp"
+
+namespace kpme {
+
+namespace {
+
+constexpr int S1 = 64;  // stage-1 output tile (rows and columns)
+
+// ----------------------------------------------------------------------------
+// Stage 1, BF16X3.  C hi/lo: [nrows][K3P]; Q: fp32 [K1][K2][K3];
+// Y hi/lo: [nrows][K1P*K2P].
+__global__ __launch_bounds__(256) void stage1_bf16x3(
+    const float* __restrict__ Q, const bf16* __restrict__ Chi,
+    const bf16* __restrict__ Clo, bf16* __restrict__ Yhi, bf16* __restrict__ Ylo,
+    int K1, int K2, int K3, int K3P, int K2P, long slab, int nrows) {
+  constexpr int KC = 32, STR = KC + 8;
+  __shared__ __attribute__((aligned(16))) bf16 Ah[S1 * STR], Al[S1 * STR], Bh[S1 * STR], Bl[S1 * STR];
+  const long m0 = static_cast<long>(blockIdx.x) * S1;
+  const int n0 = blockIdx.y * S1;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1, q = lane >> 4, m = lane & 15;
+  floatx4 acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K3P; k0 += KC) {
+    __syncthreads();
+    for (int e = tid; e < S1 * (KC / 8); e += 256) {
+      const int r = e / (KC / 8), c8 = e % (KC / 8);
+      const int n = n0 + r;
+      bf16x8 vh = {}, vl = {};
+      if (n < nrows) {
+        vh = *reinterpret_cast<const bf16x8*>(&Chi[static_cast<long>(n) * K3P + k0 + 8 * c8]);
+        vl = *reinterpret_cast<const bf16x8*>(&Clo[static_cast<long>(n) * K3P + k0 + 8 * c8]);
+      }
+      *reinterpret_cast<bf16x8*>(&Ah[r * STR + 8 * c8]) = vh;
+      *reinterpret_cast<bf16x8*>(&Al[r * STR + 8 * c8]) = vl;
+    }
+    for (int e = tid; e < S1 * KC; e += 256) {
+      const int r = e / KC, c = e % KC;
+      const long mp = m0 + r;
+      const int g1 = static_cast<int>(mp / K2P), g2 = static_cast<int>(mp % K2P);
+      const int k = k0 + c;
+      float x = 0.f;
+      if (g1 < K1 && g2 < K2 && k < K3) x = Q[(static_cast<long>(g1) * K2 + g2) * K3 + k];
+      bf16 h, l;
+      split_bf16(x, h, l);
+      Bh[r * STR + c] = h;
+      Bl[r * STR + c] = l;
+    }
+    __syncthreads();
+    bf16x8 ah[2], al[2], bh[2], bl[2];
+    for (int i = 0; i < 2; ++i) {
+      ah[i] = *reinterpret_cast<const bf16x8*>(&Ah[(wr * 32 + 16 * i + m) * STR + 8 * q]);
+      al[i] = *reinterpret_cast<const bf16x8*>(&Al[(wr * 32 + 16 * i + m) * STR + 8 * q]);
+      bh[i] = *reinterpret_cast<const bf16x8*>(&Bh[(wc * 32 + 16 * i + m) * STR + 8 * q]);
+      bl[i] = *reinterpret_cast<const bf16x8*>(&Bl[(wc * 32 + 16 * i + m) * STR + 8 * q]);
+    }
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j) {
+        acc[i][j] = mfma_bf16(ah[i], bh[j], acc[i][j]);
+        acc[i][j] = mfma_bf16(ah[i], bl[j], acc[i][j]);
+        acc[i][j] = mfma_bf16(al[i], bh[j], acc[i][j]);
+      }
+  }
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      for (int r = 0; r < 4; ++r) {
+        const int row = n0 + wr * 32 + 16 * i + 4 * q + r;
+        const long col = m0 + wc * 32 + 16 * j + m;
+        if (row < nrows && col < slab) {
+          bf16 h, l;
+          split_bf16(acc[i][j][r], h, l);
+          Yhi[row * slab + col] = h;
+          Ylo[row * slab + col] = l;
+        }
+      }
+}
+
+// Stage 1, FP32 / FP64 (16x16x4 MFMA).  C: [nrows][K3P]; Y: [nrows][slab].
+template <typename T>
+__global__ __launch_bounds__(256) void stage1_k4(const T* __restrict__ Q,
+                                                 const T* __restrict__ C,
+                                                 T* __restrict__ Y, int K1, int K2,
+                                                 int K3, int K3P, int K2P, long slab,
+                                                 int nrows) {
+  typedef typename Vec4<T>::type acc_t;
+  constexpr int KC = 16, STR = KC + 1;
+  __shared__ T As[S1 * STR], Bs[S1 * STR];
+  const long m0 = static_cast<long>(blockIdx.x) * S1;
+  const int n0 = blockIdx.y * S1;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1, q = lane >> 4, m = lane & 15;
+  acc_t acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+  for (int k0 = 0; k0 < K3P; k0 += KC) {
+    __syncthreads();
+    for (int e = tid; e < S1 * KC; e += 256) {
+      const int r = e / KC, c = e % KC;
+      const int n = n0 + r;
+      As[r * STR + c] = (n < nrows) ? C[static_cast<long>(n) * K3P + k0 + c] : T(0);
+      const long mp = m0 + r;
+      const int g1 = static_cast<int>(mp / K2P), g2 = static_cast<int>(mp % K2P);
+      const int k = k0 + c;
+      Bs[r * STR + c] = (g1 < K1 && g2 < K2 && k < K3)
+                            ? Q[(static_cast<long>(g1) * K2 + g2) * K3 + k] : T(0);
+    }
+    __syncthreads();
+    for (int kk = 0; kk < KC / 4; ++kk)
+      for (int i = 0; i < 2; ++i) {
+        const T a = As[(wr * 32 + 16 * i + m) * STR + 4 * kk + q];
+        for (int j = 0; j < 2; ++j) {
+          const T b = Bs[(wc * 32 + 16 * j + m) * STR + 4 * kk + q];
+          acc[i][j] = mfma_k4(a, b, acc[i][j]);
+        }
+      }
+  }
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      for (int r = 0; r < 4; ++r) {
+        const int row = n0 + wr * 32 + 16 * i + acc_row<T>(q, r);
+        const long col = m0 + wc * 32 + 16 * j + m;
+        if (row < nrows && col < slab) Y[row * slab + col] = acc[i][j][r];
+      }
+}
+
+// ----------------------------------------------------------------------------
+// Stage 2, BF16X3.  One workgroup = (slab s, term part); wave w owns output
+// columns [32 w, 32 w + 32).  LDS: Y slab hi/lo [K1P][K2P + 8]; A_t hi/lo
+// [K1P][K1P + 8] when it fits (A_LDS), else A_t is read from global memory.
+template <int RT, bool A_LDS>
+__global__ __launch_bounds__(512) void stage2_bf16x3(
+    const bf16* __restrict__ Yhi, const bf16* __restrict__ Ylo,
+    const bf16* __restrict__ Ahi, const bf16* __restrict__ Alo,
+    const bf16* __restrict__ Bhi, const bf16* __restrict__ Blo,
+    const int* __restrict__ term_group, const int* __restrict__ part_begin,
+    float* __restrict__ Phi_part, int K1, int K2, int K3, int K2P) {
+  constexpr int K1P = RT * 16, CT = 2, ASTR = K1P + 8;
+  const int YSTR = K2P + 8;
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  bf16* Ysh = reinterpret_cast<bf16*>(smem);
+  bf16* Ysl = Ysh + K1P * YSTR;
+  bf16* Ash = Ysl + K1P * YSTR;
+  bf16* Asl = Ash + K1P * ASTR;
+  const int s = blockIdx.x, part = blockIdx.y;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int lane = tid & 63, wave = tid >> 6, q = lane >> 4, m = lane & 15;
+  const int col0 = wave * 16 * CT;
+  const long slab = static_cast<long>(K1P) * K2P;
+  floatx4 acc2[RT][CT];
+  for (int i = 0; i < RT; ++i)
+    for (int j = 0; j < CT; ++j) acc2[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const int t0 = part_begin[part], t1 = part_begin[part + 1];
+  int cur = -1;
+  for (int t = t0; t < t1; ++t) {
+    const int g = term_group[t];
+    __syncthreads();
+    if (g != cur) {
+      const bf16* yh = Yhi + (static_cast<long>(g) * K3 + s) * slab;
+      const bf16* yl = Ylo + (static_cast<long>(g) * K3 + s) * slab;
+      const int cpr = K2P / 8;
+      for (int e = tid; e < K1P * cpr; e += nthr) {
+        const int r = e / cpr, c8 = e % cpr;
+        *reinterpret_cast<bf16x8*>(&Ysh[r * YSTR + 8 * c8]) =
+            *reinterpret_cast<const bf16x8*>(&yh[static_cast<long>(r) * K2P + 8 * c8]);
+        *reinterpret_cast<bf16x8*>(&Ysl[r * YSTR + 8 * c8]) =
+            *reinterpret_cast<const bf16x8*>(&yl[static_cast<long>(r) * K2P + 8 * c8]);
+      }
+      cur = g;
+    }
+    const bf16* ah_g = Ahi + static_cast<long>(t) * K1P * K1P;
+    const bf16* al_g = Alo + static_cast<long>(t) * K1P * K1P;
+    if (A_LDS) {
+      constexpr int cpr = K1P / 8;
+      for (int e = tid; e < K1P * cpr; e += nthr) {
+        const int r = e / cpr, c8 = e % cpr;
+        *reinterpret_cast<bf16x8*>(&Ash[r * ASTR + 8 * c8]) =
+            *reinterpret_cast<const bf16x8*>(&ah_g[r * K1P + 8 * c8]);
+        *reinterpret_cast<bf16x8*>(&Asl[r * ASTR + 8 * c8]) =
+            *reinterpret_cast<const bf16x8*>(&al_g[r * K1P + 8 * c8]);
+      }
+    }
+    __syncthreads();
+    if (col0 >= K2P) continue;
+    // GEMM1: T[g1][k2] = sum_g2 Y[g1][g2] B_t[k2][g2]
+    floatx4 acc1[RT][CT];
+    for (int i = 0; i < RT; ++i)
+      for (int j = 0; j < CT; ++j) acc1[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const bf16* bh_g = Bhi + static_cast<long>(t) * K2P * K2P;
+    const bf16* bl_g = Blo + static_cast<long>(t) * K2P * K2P;
+    for (int kc = 0; kc < K2P / 32; ++kc) {
+      bf16x8 bh[CT], bl[CT];
+      for (int j = 0; j < CT; ++j) {
+        const long off = static_cast<long>(col0 + 16 * j + m) * K2P + 32 * kc + 8 * q;
+        bh[j] = *reinterpret_cast<const bf16x8*>(&bh_g[off]);
+        bl[j] = *reinterpret_cast<const bf16x8*>(&bl_g[off]);
+      }
+      for (int i = 0; i < RT; ++i) {
+        const int off = (16 * i + m) * YSTR + 32 * kc + 8 * q;
+        const bf16x8 ah = *reinterpret_cast<const bf16x8*>(&Ysh[off]);
+        const bf16x8 al = *reinterpret_cast<const bf16x8*>(&Ysl[off]);
+        for (int j = 0; j < CT; ++j) {
+          acc1[i][j] = mfma_bf16(ah, bh[j], acc1[i][j]);
+          acc1[i][j] = mfma_bf16(ah, bl[j], acc1[i][j]);
+          acc1[i][j] = mfma_bf16(al, bh[j], acc1[i][j]);
+        }
+      }
+    }
+    // split T into bf16 hi/lo, in the accumulator layout
+    bf16x4 th[RT][CT], tl[RT][CT];
+    for (int i = 0; i < RT; ++i)
+      for (int j = 0; j < CT; ++j)
+        for (int r = 0; r < 4; ++r) {
+          bf16 h, l;
+          split_bf16(acc1[i][j][r], h, l);
+          th[i][j][r] = h;
+          tl[i][j][r] = l;
+        }
+    // GEMM2: Phi[k1][k2] += sum_g1 A_t[k1][g1] T[g1][k2], K chunks of 32 rows
+    // of T taken as {32c + 4q + r} u {32c + 16 + 4q + r}.
+    for (int c = 0; c < RT / 2; ++c) {
+      bf16x8 tbh[CT], tbl[CT];
+      for (int j = 0; j < CT; ++j) {
+        tbh[j] = cat44(th[2 * c][j], th[2 * c + 1][j]);
+        tbl[j] = cat44(tl[2 * c][j], tl[2 * c + 1][j]);
+      }
+      for (int i = 0; i < RT; ++i) {
+        bf16x8 ah, al;
+        if (A_LDS) {
+          const int off = (16 * i + m) * ASTR + 32 * c + 4 * q;
+          ah = cat44(*reinterpret_cast<const bf16x4*>(&Ash[off]),
+                     *reinterpret_cast<const bf16x4*>(&Ash[off + 16]));
+          al = cat44(*reinterpret_cast<const bf16x4*>(&Asl[off]),
+                     *reinterpret_cast<const bf16x4*>(&Asl[off + 16]));
+        } else {
+          const int off = (16 * i + m) * K1P + 32 * c + 4 * q;
+          ah = cat44(*reinterpret_cast<const bf16x4*>(&ah_g[off]),
+                     *reinterpret_cast<const bf16x4*>(&ah_g[off + 16]));
+          al = cat44(*reinterpret_cast<const bf16x4*>(&al_g[off]),
+                     *reinterpret_cast<const bf16x4*>(&al_g[off + 16]));
+        }
+        for (int j = 0; j < CT; ++j) {
+          acc2[i][j] = mfma_bf16(ah, tbh[j], acc2[i][j]);
+          acc2[i][j] = mfma_bf16(ah, tbl[j], acc2[i][j]);
+          acc2[i][j] = mfma_bf16(al, tbh[j], acc2[i][j]);
+        }
+      }
+    }
+  }
+  if (col0 >= K2P) return;
+  float* out = Phi_part + (static_cast<long>(part) * K3 + s) * K1 * K2;
+  for (int i = 0; i < RT; ++i)
+    for (int j = 0; j < CT; ++j) {
+      const int k2 = col0 + 16 * j + m;
+      for (int r = 0; r < 4; ++r) {
+        const int k1 = 16 * i + 4 * q + r;
+        if (k1 < K1 && k2 < K2) out[static_cast<long>(k1) * K2 + k2] = acc2[i][j][r];
+      }
+    }
+}
+
+// Stage 2, FP32 / FP64 with the 16x16x4 MFMAs.  The factors are symmetric,
+// which lets the global-memory operand reads run along rows (coalesced).
+template <typename T, int RT, int CT, bool A_LDS>
+__global__ __launch_bounds__(512) void stage2_k4(
+    const T* __restrict__ Y, const T* __restrict__ A, const T* __restrict__ B,
+    const int* __restrict__ term_group, const int* __restrict__ part_begin,
+    T* __restrict__ Phi_part, int K1, int K2, int K3, int K2P) {
+  typedef typename Vec4<T>::type acc_t;
+  constexpr int K1P = RT * 16, ASTR = K1P + 1;
+  const int YSTR = K2P + 1;
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  T* Ys = reinterpret_cast<T*>(smem);
+  T* As = Ys + K1P * YSTR;
+  const int s = blockIdx.x, part = blockIdx.y;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  const int lane = tid & 63, wave = tid >> 6, q = lane >> 4, m = lane & 15;
+  const int col0 = wave * 16 * CT;
+  const long slab = static_cast<long>(K1P) * K2P;
+  acc_t acc2[RT][CT];
+  for (int i = 0; i < RT; ++i)
+    for (int j = 0; j < CT; ++j) acc2[i][j] = acc_t{0, 0, 0, 0};
+  const int t0 = part_begin[part], t1 = part_begin[part + 1];
+  int cur = -1;
+  for (int t = t0; t < t1; ++t) {
+    const int g = term_group[t];
+    __syncthreads();
+    if (g != cur) {
+      const T* y = Y + (static_cast<long>(g) * K3 + s) * slab;
+      for (int e = tid; e < K1P * K2P; e += nthr) {
+        const int r = e / K2P, c = e % K2P;
+        Ys[r * YSTR + c] = y[e];
+      }
+      cur = g;
+    }
+    const T* a_g = A + static_cast<long>(t) * K1P * K1P;
+    if (A_LDS) {
+      for (int e = tid; e < K1P * K1P; e += nthr) {
+        const int r = e / K1P, c = e % K1P;
+        As[r * ASTR + c] = a_g[e];
+      }
+    }
+    __syncthreads();
+    if (col0 >= K2P) continue;
+    acc_t acc1[RT][CT];
+    for (int i = 0; i < RT; ++i)
+      for (int j = 0; j < CT; ++j) acc1[i][j] = acc_t{0, 0, 0, 0};
+    const T* b_g = B + static_cast<long>(t) * K2P * K2P;
+    for (int kc = 0; kc < K2P / 4; ++kc) {
+      T b[CT];
+      for (int j = 0; j < CT; ++j)  // B_t[k2][g2] = B_t[g2][k2]
+        b[j] = b_g[static_cast<long>(4 * kc + q) * K2P + col0 + 16 * j + m];
+      for (int i = 0; i < RT; ++i) {
+        const T a = Ys[(16 * i + m) * YSTR + 4 * kc + q];
+        for (int j = 0; j < CT; ++j) acc1[i][j] = mfma_k4(a, b[j], acc1[i][j]);
+      }
+    }
+    for (int ik = 0; ik < RT; ++ik)
+      for (int r = 0; r < 4; ++r) {
+        T bb[CT];
+        for (int j = 0; j < CT; ++j) bb[j] = acc1[ik][j][r];
+        const int g1 = 16 * ik + acc_row<T>(q, r);  // row of T held in register r
+        for (int i = 0; i < RT; ++i) {
+          // A_t[k1][g1] with k1 = 16 i + m
+          const T a = A_LDS ? As[(16 * i + m) * ASTR + g1] : a_g[g1 * K1P + 16 * i + m];
+          for (int j = 0; j < CT; ++j) acc2[i][j] = mfma_k4(a, bb[j], acc2[i][j]);
+        }
+      }
+  }
+  if (col0 >= K2P) return;
+  T* out = Phi_part + (static_cast<long>(part) * K3 + s) * K1 * K2;
+  for (int i = 0; i < RT; ++i)
+    for (int j = 0; j < CT; ++j) {
+      const int k2 = col0 + 16 * j + m;
+      for (int r = 0; r < 4; ++r) {
+        const int k1 = 16 * i + acc_row<T>(q, r);
+        if (k1 < K1 && k2 < K2) out[static_cast<long>(k1) * K2 + k2] = acc2[i][j][r];
+      }
+    }
+}
+
+// Sum the partial slabs [part][k3][k1][k2] in order, transpose to
+// [k1][k2][k3] and subtract c * sum(Q).
+template <typename A, typename O>
+__global__ __launch_bounds__(256) void finalize(const A* __restrict__ part, int nparts,
+                                                O* __restrict__ Phi, int K1, int K2,
+                                                int K3, const double* __restrict__ sumQ,
+                                                double c0) {
+  __shared__ A tile[32][33];
+  const int k1 = blockIdx.z, k2b = blockIdx.x * 32, k3b = blockIdx.y * 32;
+  const A corr = static_cast<A>(c0 * sumQ[0]);
+  const long pstride = static_cast<long>(K3) * K1 * K2;
+  for (int j = threadIdx.y; j < 32; j += 8) {
+    const int k3 = k3b + j, k2 = k2b + threadIdx.x;
+    A v = 0;
+    if (k3 < K3 && k2 < K2) {
+      const long base = (static_cast<long>(k3) * K1 + k1) * K2 + k2;
+      for (int p = 0; p < nparts; ++p) v += part[p * pstride + base];
+    }
+    tile[j][threadIdx.x] = v;
+  }
+  __syncthreads();
+  for (int j = threadIdx.y; j < 32; j += 8) {
+    const int k2 = k2b + j, k3 = k3b + threadIdx.x;
+    if (k2 < K2 && k3 < K3)
+      Phi[(static_cast<long>(k1) * K2 + k2) * K3 + k3] = static_cast<O>(tile[threadIdx.x][j] - corr);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void sum_partial(const T* __restrict__ x, long n,
+                                                   double* __restrict__ part) {
+  __shared__ double red[256];
+  const long per = (n + gridDim.x - 1) / gridDim.x;
+  const long b = per * blockIdx.x, e = (b + per < n) ? b + per : n;
+  double acc = 0.0;
+  for (long i = b + threadIdx.x; i < e; i += blockDim.x) acc += static_cast<double>(x[i]);
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void sum_final(const double* __restrict__ part, int np,
+                                                 double* __restrict__ out) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < np; i += 256) acc += part[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+
+template <typename K>
+hipError_t set_lds(K kernel, size_t bytes) {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                             static_cast<int>(bytes));
+}
+
+template <int RT, bool AL>
+hipError_t launch_s2_bf16(const SkpArgs& a, hipStream_t st) {
+  const int K1P = RT * 16;
+  size_t lds = 2 * sizeof(bf16) * static_cast<size_t>(K1P) * (a.K2P + 8);
+  if (AL) lds += 2 * sizeof(bf16) * static_cast<size_t>(K1P) * (K1P + 8);
+  hipError_t e = set_lds(stage2_bf16x3<RT, AL>, lds);
+  if (e != hipSuccess) return e;
+  const int threads = 64 * (a.K2P / 32);
+  hipLaunchKernelGGL((stage2_bf16x3<RT, AL>), dim3(a.K[2], a.nparts), dim3(threads), lds, st,
+                     static_cast<const bf16*>(a.Y[0]), static_cast<const bf16*>(a.Y[1]),
+                     static_cast<const bf16*>(a.A[0]), static_cast<const bf16*>(a.A[1]),
+                     static_cast<const bf16*>(a.B[0]), static_cast<const bf16*>(a.B[1]),
+                     a.term_group, a.part_begin, static_cast<float*>(a.Phi_part),
+                     a.K[0], a.K[1], a.K[2], a.K2P);
+  return hipGetLastError();
+}
+
+template <typename T, int RT, int CT, bool AL>
+hipError_t launch_s2_k4(const SkpArgs& a, hipStream_t st) {
+  const int K1P = RT * 16;
+  size_t lds = sizeof(T) * static_cast<size_t>(K1P) * (a.K2P + 1);
+  if (AL) lds += sizeof(T) * static_cast<size_t>(K1P) * (K1P + 1);
+  hipError_t e = set_lds(stage2_k4<T, RT, CT, AL>, lds);
+  if (e != hipSuccess) return e;
+  const int threads = 64 * (a.K2P / (16 * CT));
+  hipLaunchKernelGGL((stage2_k4<T, RT, CT, AL>), dim3(a.K[2], a.nparts), dim3(threads), lds, st,
+                     static_cast<const T*>(a.Y[0]), static_cast<const T*>(a.A[0]),
+                     static_cast<const T*>(a.B[0]), a.term_group, a.part_begin,
+                     static_cast<T*>(a.Phi_part), a.K[0], a.K[1], a.K[2], a.K2P);
+  return hipGetLastError();
+}
+
+template <int RT>
+hipError_t dispatch_s2(const SkpArgs& a, hipStream_t st) {
+  const int K1P = RT * 16;
+  if (a.prec == PREC_BF16X3) {
+    const size_t full = 2 * sizeof(bf16) * static_cast<size_t>(K1P) * (a.K2P + 8 + K1P + 8);
+    return full <= kMaxLds ? launch_s2_bf16<RT, true>(a, st) : launch_s2_bf16<RT, false>(a, st);
+  }
+  if (a.prec == PREC_FP32) {
+    const size_t full = sizeof(float) * static_cast<size_t>(K1P) * (a.K2P + 1 + K1P + 1);
+    return full <= kMaxLds ? launch_s2_k4<float, RT, 2, true>(a, st)
+                           : launch_s2_k4<float, RT, 2, false>(a, st);
+  }
+  const size_t full = sizeof(double) * static_cast<size_t>(K1P) * (a.K2P + 1 + K1P + 1);
+  return full <= kMaxLds ? launch_s2_k4<double, RT, 1, true>(a, st)
+                         : launch_s2_k4<double, RT, 1, false>(a, st);
+}
+
+}  // namespace
+
+size_t stage2_lds_bytes(int prec, int K1P, int K2P) {
+  if (prec == PREC_BF16X3) return 2 * sizeof(bf16) * static_cast<size_t>(K1P) * (K2P + 8);
+  if (prec == PREC_FP32) return sizeof(float) * static_cast<size_t>(K1P) * (K2P + 1);
+  return sizeof(double) * static_cast<size_t>(K1P) * (K2P + 1);
+}
+
+hipError_t launch_skp_sum(const SkpArgs& a, hipStream_t st) {
+  const long G = static_cast<long>(a.K[0]) * a.K[1] * a.K[2];
+  // sum(Q) in FP64, fixed reduction order
+  if (a.prec == PREC_FP64)
+    hipLaunchKernelGGL((sum_partial<double>), dim3(kSumBlocks), dim3(256), 0, st,
+                       static_cast<const double*>(a.Q), G, a.scratch);
+  else
+    hipLaunchKernelGGL((sum_partial<float>), dim3(kSumBlocks), dim3(256), 0, st,
+                       static_cast<const float*>(a.Q), G, a.scratch);
+  hipLaunchKernelGGL(sum_final, dim3(1), dim3(256), 0, st, a.scratch, kSumBlocks, a.sumQ);
+  return hipGetLastError();
+}
+
+hipError_t launch_skp_stage1(const SkpArgs& a, hipStream_t st) {
+  const long slab = static_cast<long>(a.K1P) * a.K2P;
+  const int nrows = a.r0 * a.K[2];
+  dim3 g1(static_cast<unsigned>(slab / S1), (nrows + S1 - 1) / S1);
+  if (a.prec == PREC_BF16X3)
+    hipLaunchKernelGGL(stage1_bf16x3, g1, dim3(256), 0, st, static_cast<const float*>(a.Q),
+                       static_cast<const bf16*>(a.C[0]), static_cast<const bf16*>(a.C[1]),
+                       static_cast<bf16*>(a.Y[0]), static_cast<bf16*>(a.Y[1]), a.K[0], a.K[1],
+                       a.K[2], a.K3P, a.K2P, slab, nrows);
+  else if (a.prec == PREC_FP32)
+    hipLaunchKernelGGL((stage1_k4<float>), g1, dim3(256), 0, st, static_cast<const float*>(a.Q),
+                       static_cast<const float*>(a.C[0]), static_cast<float*>(a.Y[0]), a.K[0],
+                       a.K[1], a.K[2], a.K3P, a.K2P, slab, nrows);
+  else
+    hipLaunchKernelGGL((stage1_k4<double>), g1, dim3(256), 0, st,
+                       static_cast<const double*>(a.Q), static_cast<const double*>(a.C[0]),
+                       static_cast<double*>(a.Y[0]), a.K[0], a.K[1], a.K[2], a.K3P, a.K2P,
+                       slab, nrows);
+  return hipGetLastError();
+}
+
+hipError_t launch_skp_stage2(const SkpArgs& a, hipStream_t st) {
+  switch (a.K1P) {
+    case 32: return dispatch_s2<2>(a, st);
+    case 64: return dispatch_s2<4>(a, st);
+    case 96: return dispatch_s2<6>(a, st);
+    case 128: return dispatch_s2<8>(a, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_skp_finalize(const SkpArgs& a, hipStream_t st) {
+  dim3 gf((a.K[1] + 31) / 32, (a.K[2] + 31) / 32, a.K[0]);
+  if (a.prec == PREC_FP64)
+    hipLaunchKernelGGL((finalize<double, double>), gf, dim3(32, 8), 0, st,
+                       static_cast<const double*>(a.Phi_part), a.nparts,
+                       static_cast<double*>(a.Phi), a.K[0], a.K[1], a.K[2], a.sumQ, a.c0);
+  else
+    hipLaunchKernelGGL((finalize<float, float>), gf, dim3(32, 8), 0, st,
+                       static_cast<const float*>(a.Phi_part), a.nparts,
+                       static_cast<float*>(a.Phi), a.K[0], a.K[1], a.K[2], a.sumQ, a.c0);
+  return hipGetLastError();
+}
+
+}  // namespace kpme

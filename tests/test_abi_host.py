@@ -1,0 +1,127 @@
+"""Host-side checks of the C ABI: exported symbols, argument validation, and
+the FP64 factor construction against the oracle (no device needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import skp
+from paper_2601_18838_amd import kpme
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "kpme.h")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(kpme_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = kpme.lib()
+    names = declared_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def test_status_strings():
+    L = kpme.lib()
+    for s in range(6):
+        assert L.kpme_status_string(s)
+    assert L.kpme_status_string(99) == b"unknown status"
+
+
+def _create(box=(20, 20, 20), grid=(16, 16, 16), p=4, beta=0.35, rank=8, tol=0.0, prec=1,
+            nmax=100):
+    h = ctypes.c_void_p()
+    st = kpme.lib().kpme_plan_create(ctypes.byref(h), kpme._dbl3(box), kpme._int3(grid), p,
+                                     beta, rank, tol, prec, nmax, 0)
+    return st, h
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(box=(0, 20, 20)), 1), (dict(box=(20, float("nan"), 20)), 1),
+    (dict(p=5), 2), (dict(p=3), 2), (dict(p=14), 1), (dict(grid=(3, 16, 16)), 1),
+    (dict(grid=(16, 16, 300)), 1), (dict(grid=(6, 16, 16), p=8), 1), (dict(beta=-1.0), 1),
+    (dict(rank=0, tol=0.0), 1), (dict(rank=0, tol=2.0), 1), (dict(prec=7), 1),
+    (dict(nmax=0), 1), (dict(prec=3), 2), (dict(grid=(160, 16, 16)), 2),
+])
+def test_plan_create_validates_before_touching_a_device(kw, code):
+    st, h = _create(**kw)
+    assert st == code, (st, kpme.lib().kpme_last_error())
+    assert h.value is None
+
+
+def test_plan_create_without_a_device_reports_device_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    assert kpme.device_count() == 0
+    st, h = _create()
+    assert st == 4 and h.value is None
+    assert b"device" in kpme.lib().kpme_last_error().lower()
+
+
+def test_calls_on_invalid_handles_fail_cleanly():
+    L = kpme.lib()
+    null = ctypes.c_void_p()
+    assert L.kpme_plan_destroy(null) == 1
+    assert L.kpme_spread(null, 0, None, None, None, None) == 1
+    assert L.kpme_skp_apply(null, None, None, None) == 1
+    assert L.kpme_gather(null, 0, None, None, None, None, None, None) == 1
+    assert L.kpme_energy(null, 0, None, None, None, None) == 1
+    assert L.kpme_evaluate(null, 0, None, None, None, None, None, None) == 1
+    info = kpme.PlanInfo()
+    assert L.kpme_plan_info(null, ctypes.byref(info)) == 1
+
+
+def _rank1(vec, r):
+    return (vec[0][r][:, None, None] * vec[1][r][None, :, None] * vec[2][r][None, None, :])
+
+
+@pytest.mark.parametrize("box,grid,p,beta,rank", [
+    ((20.0, 20.0, 20.0), (16, 16, 16), 4, 0.35, None),
+    ((9.0, 11.0, 13.0), (8, 10, 12), 4, 0.7, None),
+    ((9.0, 11.0, 13.0), (9, 10, 11), 6, 0.7, None),
+    ((30.0, 37.5, 45.0), (20, 25, 30), 4, 0.34, 24),
+])
+def test_factors_match_the_oracle(box, grid, p, beta, rank):
+    orc = skp.Plan(box, grid, p, beta, rank=rank)
+    lib = kpme.factors_compute(box, grid, p, beta, rank=rank or 10 ** 6)
+    th = orc.theta
+    scale = np.abs(th).max()
+    # the kept operator and its truncation are unique (ties aside): compare
+    # the weights, the reconstructed symbol and the scalars
+    R = min(len(orc.terms), len(lib["omega"]))
+    w_o = np.array([t[0] for t in orc.terms[:R]])
+    big = w_o > 1e-10 * w_o[0]
+    np.testing.assert_allclose(lib["omega"][:R][big], w_o[big], rtol=1e-9)
+    rec_lib = sum(lib["omega"][r] * _rank1(lib["vec"], r) for r in range(len(lib["omega"])))
+    rec_orc = skp.reconstruct(orc.terms, th.shape)
+    assert np.abs(rec_lib - rec_orc).max() < 1e-11 * scale
+    assert abs(lib["theta_norm"] - np.linalg.norm(th)) < 1e-12 * np.linalg.norm(th)
+    assert abs(lib["trunc_err"] - orc.trunc_err) < 1e-10 * np.linalg.norm(th) + 1e-6 * orc.trunc_err
+    assert abs(lib["zero_mode"] - orc.c0) < 1e-11 * scale
+    # each term is a unit-norm rank-1 tensor of even mode vectors
+    for j in range(3):
+        v = lib["vec"][j]
+        np.testing.assert_allclose(np.linalg.norm(v, axis=1), 1.0, atol=1e-12)
+        K = v.shape[1]
+        np.testing.assert_allclose(v, v[:, np.mod(-np.arange(K), K)], atol=1e-12)
+
+
+def test_tolerance_rank_matches_the_oracle():
+    box, grid = (20.0, 20.0, 20.0), (16, 16, 16)
+    orc = skp.Plan(box, grid, 4, 0.35, tol=1e-6)
+    lib = kpme.factors_compute(box, grid, 4, 0.35, rank=0, tol=1e-6)
+    assert len(lib["omega"]) == orc.rank == 22
+
+
+def test_factors_compute_rejects_a_small_output_buffer():
+    with pytest.raises(kpme.KpmeError) as e:
+        kpme.factors_compute((20, 20, 20), (16, 16, 16), 4, 0.35, rank=30, max_terms=8)
+    assert e.value.status == 1

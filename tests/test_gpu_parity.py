@@ -1,0 +1,198 @@
+"""GPU parity: every stage of the HIP path against the FP64 oracle, through the C ABI.
+
+Tolerances (relative to the largest magnitude of the compared quantity, or
+relative RMS, as named):
+* FP64 path: 1e-11 elementwise (rounding order only).
+* FP32 path: grids and potentials 1e-5, forces 2e-5 (float32 accumulation of
+  p^3 stencil terms and O(K) mode-product sums, unit roundoff 6e-8).
+* BF16X3 path: the targets of the mixed-precision path -- relative energy
+  error <= 1e-5 and relative RMS force error <= 1e-4 against FP64 at equal R;
+  grid values within 2e-5 of the largest value.
+The oracle runs at the same R, grid, order and beta, so truncation error is
+excluded and only precision error is measured.
+"""
+import numpy as np
+import pytest
+
+from oracle import skp, spme
+from paper_2601_18838_amd import systems
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def kp():
+    from paper_2601_18838_amd import kpme
+    return kpme
+
+
+PREC = {"fp64": torch.float64, "fp32": torch.float32, "bf16x3": torch.float32}
+
+
+def dev(x, prec):
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=PREC[prec], device="cuda")
+
+
+def host(x):
+    return x.detach().cpu().double().numpy()
+
+
+def relmax(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def relrms(a, b):
+    return np.sqrt(((a - b) ** 2).sum() / max((b ** 2).sum(), 1e-300))
+
+
+_ORACLE = {}
+
+
+def oracle_plan(box, grid, p, beta, rank=None, tol=None):
+    key = (tuple(box), tuple(grid), p, beta, rank, tol)
+    if key not in _ORACLE:
+        _ORACLE[key] = skp.Plan(box, grid, p, beta, rank=rank, tol=tol)
+    return _ORACLE[key]
+
+
+CASES = {
+    # name: (box, grid, p, beta, rank, n, kind, seed)
+    "small_pm1": ((20.0, 20.0, 20.0), (16, 16, 16), 4, 0.35, 8, 1000, "pm1", 1),
+    "ragged_noncubic": ((21.0, 26.0, 31.0), (20, 25, 30), 6, 0.6, 24, 1500, "water", 12),
+    "tall_k1": ((40.0, 15.0, 22.0), (100, 36, 44), 4, 0.5, 30, 3000, "pm1", 13),
+}
+
+
+def make(case):
+    box, grid, p, beta, rank, n, kind, seed = CASES[case]
+    if kind == "pm1":
+        pos, q = systems.uniform_pm1(n, box, seed)
+    else:
+        pos, q = systems.water(n // 3, box, seed)
+    return box, grid, p, beta, rank, pos, q
+
+
+TOL = {"fp64": dict(grid=1e-11, pot=1e-11, force=1e-11, energy=1e-11),
+       "fp32": dict(grid=1e-5, pot=1e-5, force=2e-5, energy=1e-5),
+       "bf16x3": dict(grid=2e-5, pot=3e-5, force=1e-4, energy=1e-5)}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("case", list(CASES))
+def test_stages_match_oracle(case, prec):
+    print(f"[parity] {case} {prec}", flush=True)
+    box, grid, p, beta, rank, pos, q = make(case)
+    orc = oracle_plan(box, grid, p, beta, rank=rank)
+    ref = orc.evaluate(pos, q)
+    pl = kp().Plan(box, grid, p, beta, rank=rank, precision=prec, max_particles=len(q))
+    assert pl.info["rank"] == orc.rank and pl.info["r0"] == orc.r0
+    tol = TOL[prec]
+    P, Qc = dev(pos, prec), dev(q, prec)
+    # spread
+    Qg = pl.spread(P, Qc)
+    assert relmax(host(Qg), ref["Q"]) < (1e-12 if prec == "fp64" else 2e-6)
+    # SKP apply on the oracle's own grid
+    Phi = pl.skp_apply(dev(ref["Q"], prec))
+    assert relmax(host(Phi), ref["Phi"]) < tol["grid"]
+    # gather on the oracle's own potential grid
+    pot, frc = pl.gather(P, Qc, dev(ref["Phi"], prec))
+    assert relmax(host(pot), ref["phi"]) < tol["pot"]
+    assert relmax(host(frc), ref["F"]) < tol["force"]
+    # energy from the oracle's potentials
+    e4 = host(pl.energy(Qc, dev(ref["phi"], prec)))
+    assert abs(e4[0] - ref["E_rec"]) < 1e-6 * abs(ref["E_rec"]) if prec != "fp64" else \
+        abs(e4[0] - ref["E_rec"]) < 1e-12 * abs(ref["E_rec"])
+    # the whole path
+    e4, pot, frc = pl.evaluate(P, Qc)
+    e4, pot, frc = host(e4), host(pot), host(frc)
+    assert abs(e4[0] - ref["E_rec"]) / abs(ref["E_rec"]) < tol["energy"]
+    assert relrms(pot, ref["phi"]) < tol["pot"]
+    assert relrms(frc, ref["F"]) < tol["force"]
+    qs = q.sum()
+    V = np.prod(box)
+    assert abs(e4[1] + beta / np.sqrt(np.pi) * (q ** 2).sum()) < 1e-12 * (q ** 2).sum()
+    assert abs(e4[2] + np.pi * qs ** 2 / (2 * V * beta ** 2)) < 1e-12
+    assert abs(e4[3] - e4[:3].sum()) < 1e-12 * abs(e4).max()
+
+
+def test_full_rank_fp64_equals_fft_spme():
+    print("[parity] full rank fp64 vs FFT SPME", flush=True)
+    box, grid, p, beta = (9.0, 11.0, 13.0), (8, 10, 12), 4, 0.7
+    pos, q = systems.uniform_pm1(200, box, 21)
+    q = q + 0.05                                             # non-neutral
+    ref = spme.spme(pos, q, box, grid, p, beta)
+    pl = kp().Plan(box, grid, p, beta, rank=100000, precision="fp64", max_particles=200)
+    e4, pot, frc = pl.evaluate(dev(pos, "fp64"), dev(q, "fp64"))
+    assert abs(host(e4)[0] - ref["E_rec"]) < 1e-11 * abs(ref["E_rec"])
+    assert relmax(host(pot), ref["phi"]) < 1e-11
+    assert relmax(host(frc), ref["F"]) < 1e-11
+
+
+def test_correction_on_non_neutral_truncated_system():
+    print("[parity] correction", flush=True)
+    box, grid, p, beta = (20.0, 20.0, 20.0), (16, 16, 16), 4, 0.35
+    pos, q = systems.uniform_pm1(500, box, 5)
+    q = q.copy()
+    q[:50] = 1.0                                             # net charge
+    orc = oracle_plan(box, grid, p, beta, rank=6)
+    ref = orc.evaluate(pos, q)
+    pl = kp().Plan(box, grid, p, beta, rank=6, precision="fp64", max_particles=500)
+    assert abs(pl.info["zero_mode"] - orc.c0) < 1e-12 * abs(orc.theta).max()
+    e4, pot, _ = pl.evaluate(dev(pos, "fp64"), dev(q, "fp64"))
+    assert relmax(host(pot), ref["phi"]) < 1e-11
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_empty_and_capacity_edges(prec):
+    print(f"[parity] edges {prec}", flush=True)
+    box, grid, p, beta, rank, pos, q = make("small_pm1")
+    kpme = kp()
+    pl = kpme.Plan(box, grid, p, beta, rank=rank, precision=prec, max_particles=len(q))
+    P, Qc = dev(pos, prec), dev(q, prec)
+    g = pl.spread(P[:0], Qc[:0])
+    assert float(g.abs().max()) == 0.0
+    e4, pot, frc = pl.evaluate(P[:0], Qc[:0])
+    assert np.all(host(e4) == 0.0) and pot.numel() == 0
+    with pytest.raises(kpme.KpmeError) as e:
+        pl2 = kpme.Plan(box, grid, p, beta, rank=rank, precision=prec, max_particles=10)
+        pl2.evaluate(P, Qc)
+    assert e.value.status == 1
+    # positions outside the box are wrapped, not rejected
+    shift = np.array(box) * np.array([1.0, -2.0, 3.0])
+    e_a = host(pl.evaluate(P, Qc)[0])[0]
+    e_b = host(pl.evaluate(dev(pos + shift, prec), Qc)[0])[0]
+    assert abs(e_a - e_b) < 1e-5 * abs(e_a)
+
+
+def test_water_100k_fp32_and_bf16x3_against_fp64():
+    """The 1e5-atom water box (96^3, p=4, R from the 1e-6 rule): the mixed
+    paths against the FP64 GPU path and the oracle at equal R."""
+    wl = systems.WATER_100K
+    print(f"[parity] {wl.name}", flush=True)
+    pos, q = wl.particles()
+    kpme = kp()
+    res = {}
+    for prec in ("fp64", "fp32", "bf16x3"):
+        pl = kpme.Plan(wl.box, wl.grid, wl.order, wl.beta, rank=0, tol=wl.tol,
+                       precision=prec, max_particles=len(q))
+        e4, pot, frc = pl.evaluate(dev(pos, prec), dev(q, prec))
+        res[prec] = (host(e4), host(pot), host(frc), pl.info)
+    assert res["fp64"][3]["rank"] == 73
+    orc = oracle_plan(wl.box, wl.grid, wl.order, wl.beta, tol=wl.tol)
+    assert orc.rank == 73
+    ref = orc.evaluate(pos, q)
+    e64 = res["fp64"][0][0]
+    assert abs(e64 - ref["E_rec"]) < 1e-10 * abs(ref["E_rec"])
+    assert relrms(res["fp64"][2], ref["F"]) < 1e-10
+    for prec in ("fp32", "bf16x3"):
+        e, pot, frc, _ = res[prec]
+        assert abs(e[0] - ref["E_rec"]) / abs(ref["E_rec"]) < 1e-5, prec
+        assert relrms(pot, ref["phi"]) < 1e-4, prec
+        assert relrms(frc, ref["F"]) < 1e-4, prec
