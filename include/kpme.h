@@ -68,8 +68,11 @@ typedef enum {
  *   KPME_BF16X3 every operand split x = hi + lo into two bfloat16 (round to
  *               nearest even); products hi*hi + hi*lo + lo*hi accumulated in
  *               FP32 on the bf16 matrix cores.
- *   KPME_FP16X3 as BF16X3 with half-precision hi and a lo part scaled by 2^11;
- *               factors carry power-of-two per-matrix scales.              */
+ *   KPME_FP16X3 as BF16X3 with IEEE half hi and lo (22 significand bits).
+ *               Every half operand is brought into range by a power of two:
+ *               one plan-time scale per factor kind (A, B, C; uniform over
+ *               terms), bound-derived scales for the intermediates, and a
+ *               run-time scale for the input grid from its largest value. */
 typedef enum {
   KPME_FP64 = 0,
   KPME_FP32 = 1,

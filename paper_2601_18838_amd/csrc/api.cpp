@@ -51,6 +51,27 @@ uint16_t bf16_rne(float x) {
   u += 0x7fffu + ((u >> 16) & 1u);
   return static_cast<uint16_t>(u >> 16);
 }
+// IEEE binary16 with round-to-nearest-even, subnormals and overflow to inf.
+// Returns the bit pattern; *value receives the rounded number.
+uint16_t f16_rne(double x, double* value) {
+  const uint16_t sign = std::signbit(x) ? 0x8000 : 0;
+  if (std::isnan(x)) { *value = x; return 0x7e00; }
+  const double a = std::fabs(x);
+  if (a >= 65520.0) { *value = std::copysign(INFINITY, x); return sign | 0x7c00; }
+  int e = std::ilogb(a > 0 ? a : 1.0);
+  if (a == 0 || e < -14) e = -14;                 // subnormal spacing 2^-24
+  const double ulp = std::ldexp(1.0, e - 10);
+  const double r = std::nearbyint(a / ulp) * ulp; // default mode: nearest even
+  *value = std::copysign(r, x);
+  if (r == 0) return sign;
+  const int er = std::ilogb(r);
+  if (er < -14) return sign | static_cast<uint16_t>(std::ldexp(r, 24));  // subnormal
+  const uint16_t mant = static_cast<uint16_t>(std::ldexp(r, -er) * 1024.0 - 1024.0);
+  return sign | static_cast<uint16_t>((er + 15) << 10) | mant;
+}
+
+double pow2_below(double x) { return std::ldexp(1.0, std::ilogb(x)); }
+
 float bf16_to_float(uint16_t h) {
   uint32_t u = static_cast<uint32_t>(h) << 16;
   float f;
@@ -71,6 +92,8 @@ struct kpme_plan_s {
   int R = 0, r0 = 0, total_terms = 0, nparts = 1;
   int64_t max_n = 0;
   double theta_norm = 0, trunc_err = 0, zero_mode = 0;
+  float sy = 1.f, st = 1.f;   // FP16X3 powers of two for Y and T
+  double const_scale = 1.0;   // FP16X3 product of plan-time scales
   size_t ws_bytes = 0;
   std::vector<void*> allocations;
   // device arrays
@@ -86,6 +109,7 @@ struct kpme_plan_s {
   void* Qg = nullptr;         // internal grids
   void* Phig = nullptr;
   void* pot = nullptr;        // internal potentials (max_n)
+  Bins bins{};                // binned particle layout (evaluate, spread)
   // per-stage hipEvent pairs recorded on the calling stream while profiling
   bool prof_on = false;
   std::vector<hipEvent_t> prof_ev[KPME_NUM_STAGES][2];
@@ -250,8 +274,6 @@ kpme_status kpme_plan_create(kpme_plan_t* plan, const double box[3], const int g
     return fail(KPME_ERROR_INVALID_VALUE, "svd_tol must be in (0, 1) when skp_rank <= 0");
   if (max_particles <= 0 || max_particles >= (int64_t(1) << 31))
     return fail(KPME_ERROR_INVALID_VALUE, "max_particles must be in [1, 2^31)");
-  if (precision == KPME_FP16X3)
-    return fail(KPME_ERROR_NOT_SUPPORTED, "FP16X3 is not available in this build");
   const int K1P = round_up(grid[0], 32), K2P = round_up(grid[1], 32), K3P = round_up(grid[2], 32);
   if (K1P > 128)
     return fail(KPME_ERROR_NOT_SUPPORTED, "K1 > 128 is not supported by the SKP kernels");
@@ -329,12 +351,59 @@ kpme_status kpme_plan_create(kpme_plan_t* plan, const double box[3], const int g
         hC[(static_cast<size_t>(gi) * K3 + s) * K3P + g] = cc[(s - g + K3) % K3];
   }
 
+  // FP16X3: power-of-two scales, uniform over terms, that put the largest
+  // factor entry in [2^13, 2^14); Y and T are scaled from rigorous bounds
+  // (|Q| scaled below 2^14 at run time; row 1-norms of the scaled factors) so
+  // that every stored half value stays below 2^14 (range 65504).
+  double sA = 1, sB = 1, sC = 1;
+  if (precision == KPME_FP16X3) {
+    auto maxabs = [](const std::vector<double>& v) {
+      double m = 0;
+      for (double x : v) m = std::max(m, std::fabs(x));
+      return m;
+    };
+    auto max_row_l1 = [](const std::vector<double>& v, size_t rows, size_t cols, double sc) {
+      double m = 0;
+      for (size_t r = 0; r < rows; ++r) {
+        double acc = 0;
+        for (size_t c = 0; c < cols; ++c) acc += std::fabs(v[r * cols + c]) * sc;
+        m = std::max(m, acc);
+      }
+      return m;
+    };
+    sA = std::ldexp(1.0, 13) / pow2_below(maxabs(hA));
+    sB = std::ldexp(1.0, 13) / pow2_below(maxabs(hB));
+    sC = std::ldexp(1.0, 13) / pow2_below(maxabs(hC));
+    const double nC = max_row_l1(hC, static_cast<size_t>(r0) * K3, K3P, sC);
+    const double nB = max_row_l1(hB, static_cast<size_t>(R) * K2P, K2P, sB);
+    const double y_bound = std::ldexp(1.0, 14) * nC;      // |Q' C'| before sy
+    const double sy = std::ldexp(1.0, 13) / pow2_below(y_bound);
+    const double t_bound = std::ldexp(1.0, 14) * nB;      // |Y'' B'| before st
+    const double st_ = std::ldexp(1.0, 13) / pow2_below(t_bound);
+    pl->sy = static_cast<float>(sy);
+    pl->st = static_cast<float>(st_);
+    pl->const_scale = sA * sB * sC * sy * st_;
+  }
+
   hipError_t e = hipSuccess;
-  const int planes = precision == KPME_BF16X3 ? 2 : 1;
+  const int planes = (precision == KPME_BF16X3 || precision == KPME_FP16X3) ? 2 : 1;
   const size_t opsz = precision == KPME_FP64 ? 8 : (precision == KPME_FP32 ? 4 : 2);
-  auto upload = [&](const std::vector<double>& h, void** dst) -> hipError_t {
+  auto upload = [&](const std::vector<double>& h, void** dst, double scale) -> hipError_t {
     const size_t n = h.size();
     hipError_t er;
+    if (precision == KPME_FP16X3) {
+      std::vector<uint16_t> hi(n), lo(n);
+      for (size_t i = 0; i < n; ++i) {
+        double vh, vl;
+        const double x = h[i] * scale;  // exact: power-of-two scale
+        hi[i] = f16_rne(x, &vh);
+        lo[i] = f16_rne(x - vh, &vl);
+      }
+      if ((er = plan_alloc(pl, &dst[0], n * 2)) != hipSuccess) return er;
+      if ((er = plan_alloc(pl, &dst[1], n * 2)) != hipSuccess) return er;
+      if ((er = hipMemcpy(dst[0], hi.data(), n * 2, hipMemcpyHostToDevice)) != hipSuccess) return er;
+      return hipMemcpy(dst[1], lo.data(), n * 2, hipMemcpyHostToDevice);
+    }
     if (precision == KPME_FP64) {
       if ((er = plan_alloc(pl, &dst[0], n * 8)) != hipSuccess) return er;
       return hipMemcpy(dst[0], h.data(), n * 8, hipMemcpyHostToDevice);
@@ -357,12 +426,47 @@ kpme_status kpme_plan_create(kpme_plan_t* plan, const double box[3], const int g
   };
   const long G = static_cast<long>(K1) * K2 * K3;
   const size_t es = pl->esize();
+
+  // Bricks of (up to) 8^3 grid points; for each owner brick and axis, the
+  // home bricks whose particles' stencils {base - t mod K, t < p} reach it.
+  BinGeom& bg = pl->bins.geom;
+  bg.nbricks = 1;
+  bg.nbmax = 0;
+  for (int j = 0; j < 3; ++j) {
+    bg.edge[j] = std::min(8, grid[j]);
+    bg.nb[j] = (grid[j] + bg.edge[j] - 1) / bg.edge[j];
+    bg.nbricks *= bg.nb[j];
+    bg.nbmax = std::max(bg.nbmax, bg.nb[j]);
+  }
+  std::vector<int> hnbr(static_cast<size_t>(3) * bg.nbmax * kNbrRec, 0);
+  for (int j = 0; j < 3; ++j) {
+    const int K = grid[j], E = bg.edge[j];
+    for (int bo = 0; bo < bg.nb[j]; ++bo) {
+      int* rec = &hnbr[(static_cast<size_t>(j) * bg.nbmax + bo) * kNbrRec];
+      for (int bh = 0; bh < bg.nb[j]; ++bh) {
+        bool reach = false;
+        for (int b = bh * E; b < std::min((bh + 1) * E, K) && !reach; ++b)
+          for (int t = 0; t < spline_order && !reach; ++t) {
+            const int k = ((b - t) % K + K) % K;
+            reach = (k >= bo * E && k < std::min((bo + 1) * E, K));
+          }
+        if (reach) {
+          if (rec[0] >= kNbrRec - 1) {
+            plan_free(pl);
+            delete pl;
+            return fail(KPME_ERROR_NOT_SUPPORTED, "brick neighbour table overflow");
+          }
+          rec[1 + rec[0]++] = bh;
+        }
+      }
+    }
+  }
   const size_t nY = static_cast<size_t>(r0) * K3 * K1P * K2P;
   void* tmp = nullptr;
   do {
-    if ((e = upload(hA, pl->A)) != hipSuccess) break;
-    if ((e = upload(hB, pl->B)) != hipSuccess) break;
-    if ((e = upload(hC, pl->C)) != hipSuccess) break;
+    if ((e = upload(hA, pl->A, sA)) != hipSuccess) break;
+    if ((e = upload(hB, pl->B, sB)) != hipSuccess) break;
+    if ((e = upload(hC, pl->C, sC)) != hipSuccess) break;
     for (int k = 0; k < planes; ++k)
       if ((e = plan_alloc(pl, &pl->Y[k], nY * opsz)) != hipSuccess) break;
     if (e != hipSuccess) break;
@@ -380,6 +484,22 @@ kpme_status kpme_plan_create(kpme_plan_t* plan, const double box[3], const int g
     if ((e = plan_alloc(pl, &pl->Qg, G * es)) != hipSuccess) break;
     if ((e = plan_alloc(pl, &pl->Phig, G * es)) != hipSuccess) break;
     if ((e = plan_alloc(pl, &pl->pot, static_cast<size_t>(max_particles) * es)) != hipSuccess) break;
+    Bins& bn = pl->bins;
+    const size_t nb1 = static_cast<size_t>(bg.nbricks) + 1, nmax = static_cast<size_t>(max_particles);
+    if ((e = plan_alloc(pl, &tmp, nb1 * sizeof(int))) != hipSuccess) break;
+    bn.count = static_cast<int*>(tmp);
+    if ((e = plan_alloc(pl, &tmp, nb1 * sizeof(int))) != hipSuccess) break;
+    bn.offset = static_cast<int*>(tmp);
+    if ((e = plan_alloc(pl, &tmp, nmax * sizeof(int))) != hipSuccess) break;
+    bn.brick_of = static_cast<int*>(tmp);
+    if ((e = plan_alloc(pl, &tmp, nmax * sizeof(int))) != hipSuccess) break;
+    bn.slot = static_cast<int*>(tmp);
+    if ((e = plan_alloc(pl, &tmp, nmax * sizeof(int))) != hipSuccess) break;
+    bn.perm = static_cast<int*>(tmp);
+    if ((e = plan_alloc(pl, &tmp, hnbr.size() * sizeof(int))) != hipSuccess) break;
+    bn.nbr = static_cast<int*>(tmp);
+    if ((e = hipMemcpy(tmp, hnbr.data(), hnbr.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess) break;
+    if ((e = plan_alloc(pl, &bn.sorted, nmax * 4 * es)) != hipSuccess) break;
     e = hipDeviceSynchronize();
   } while (false);
   if (e != hipSuccess) {
@@ -430,8 +550,8 @@ kpme_status check_n(kpme_plan_t plan, int64_t n) {
 kpme_status do_spread(kpme_plan_t plan, int64_t n, const void* pos, const void* q, void* grid,
                       hipStream_t st) {
   StageTimer tm(plan, KPME_STAGE_SPREAD, st);
-  hipError_t e = launch_zero(grid, plan->grid_size() * plan->esize(), st);
-  if (e == hipSuccess) e = launch_spread_atomic(plan->prec, plan->geom(), n, pos, q, grid, st);
+  hipError_t e = launch_bin(plan->prec, plan->geom(), plan->bins, n, pos, q, st);
+  if (e == hipSuccess) e = launch_spread_binned(plan->prec, plan->geom(), plan->bins, grid, st);
   return from_hip(e, "spread");
 }
 
@@ -449,6 +569,9 @@ kpme_status do_skp(kpme_plan_t plan, const void* in, void* out, hipStream_t st) 
   a.scratch = plan->scratch;
   a.sumQ = plan->scalars;
   a.c0 = plan->zero_mode;
+  a.sy = plan->sy;
+  a.st = plan->st;
+  a.const_scale = plan->const_scale;
   hipError_t e;
   {
     StageTimer tm(plan, KPME_STAGE_GRID_SUM, st);
@@ -538,7 +661,11 @@ kpme_status kpme_evaluate(kpme_plan_t plan, int64_t n, const void* pos, const vo
   if ((s = do_skp(plan, plan->Qg, plan->Phig, st)) != KPME_SUCCESS) return s;
   void* potp = pot ? pot : (energy4 ? plan->pot : nullptr);
   if (potp || force) {
-    if ((s = do_gather(plan, n, pos, q, plan->Phig, potp, force, st)) != KPME_SUCCESS) return s;
+    // the particles are still binned from the spread: gather in binned order
+    StageTimer tm(plan, KPME_STAGE_GATHER, st);
+    hipError_t e = launch_gather_binned(plan->prec, plan->geom(), plan->bins, n, plan->Phig,
+                                        potp, force, st);
+    if ((s = from_hip(e, "gather")) != KPME_SUCCESS) return s;
   }
   if (energy4) return do_energy(plan, n, q, potp, energy4, st);
   return KPME_SUCCESS;

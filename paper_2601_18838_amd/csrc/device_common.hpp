@@ -8,23 +8,42 @@ namespace kpme {
 typedef __bf16 bf16;
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+typedef _Float16 f16;
+typedef __attribute__((__vector_size__(8 * sizeof(_Float16)))) _Float16 f16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(_Float16)))) _Float16 f16x4;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4;
 typedef __attribute__((__vector_size__(4 * sizeof(double)))) double doublex4;
 
-// Split x = hi + lo into two round-to-nearest-even bfloat16 values.
-__device__ __forceinline__ void split_bf16(float x, bf16& hi, bf16& lo) {
-  hi = static_cast<bf16>(x);
-  lo = static_cast<bf16>(x - static_cast<float>(hi));
+// Split x = hi + lo into two round-to-nearest-even 16-bit values (bfloat16
+// or IEEE half).
+template <typename H>
+__device__ __forceinline__ void split_h(float x, H& hi, H& lo) {
+  hi = static_cast<H>(x);
+  lo = static_cast<H>(x - static_cast<float>(hi));
 }
+__device__ __forceinline__ void split_bf16(float x, bf16& hi, bf16& lo) { split_h<bf16>(x, hi, lo); }
 
-__device__ __forceinline__ bf16x8 cat44(bf16x4 a, bf16x4 b) {
-  return bf16x8{a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
+// 8- and 4-wide vectors of a 16-bit element type.
+template <typename H> struct HVec;
+template <> struct HVec<bf16> { typedef bf16x8 v8; typedef bf16x4 v4; };
+template <> struct HVec<f16> { typedef f16x8 v8; typedef f16x4 v4; };
+
+template <typename V4, typename V8>
+__device__ __forceinline__ V8 cat44(V4 a, V4 b) {
+  return V8{a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
 }
+__device__ __forceinline__ bf16x8 cat44(bf16x4 a, bf16x4 b) { return cat44<bf16x4, bf16x8>(a, b); }
+__device__ __forceinline__ f16x8 cat44(f16x4 a, f16x4 b) { return cat44<f16x4, f16x8>(a, b); }
 
 // 16x16x32 bf16 product, FP32 accumulation.  Lane l holds A[l%16][8(l/16)..+7],
 // B[8(l/16)..+7][l%16]; D[4(l/16)+r][l%16] in register r.
 __device__ __forceinline__ floatx4 mfma_bf16(bf16x8 a, bf16x8 b, floatx4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+// Same shape and lane layout for IEEE half inputs.
+__device__ __forceinline__ floatx4 mfma_h(bf16x8 a, bf16x8 b, floatx4 c) { return mfma_bf16(a, b, c); }
+__device__ __forceinline__ floatx4 mfma_h(f16x8 a, f16x8 b, floatx4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
 }
 // 16x16x4 products: lane l holds A[l%16][l/16], B[l/16][l%16].  The FP32
 // form returns D[4(l/16)+r][l%16] in register r, the FP64 form returns

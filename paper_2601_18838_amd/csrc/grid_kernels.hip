@@ -149,6 +149,206 @@ __global__ __launch_bounds__(256) void gather_direct(long n, const T* __restrict
   }
 }
 
+// ---------------------------------------------------------------------------
+// Binning: particles are counting-sorted by the grid brick that holds their
+// base index floor(u) (brick edge E_j, NB_j = ceil(K_j / E_j) bricks per axis).
+
+template <typename T>
+__global__ __launch_bounds__(256) void bin_count(long n, const T* __restrict__ pos,
+                                                 GridGeom g, BinGeom bg,
+                                                 int* __restrict__ brick_of,
+                                                 int* __restrict__ slot,
+                                                 int* __restrict__ count) {
+  const long i = blockIdx.x * static_cast<long>(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  int bid = 0;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    int base;
+    (void)scaled(pos[3 * i + j], g.L[j], g.K[j], base);
+    bid = bid * bg.nb[j] + base / bg.edge[j];
+  }
+  brick_of[i] = bid;
+  slot[i] = atomicAdd(&count[bid], 1);
+}
+
+// Exclusive scan of the brick counts in one workgroup of 1024 threads:
+// offset[b] = sum_{c < b} count[c], offset[nbricks] = n.
+__global__ __launch_bounds__(1024) void bin_scan(const int* __restrict__ count, int nbricks,
+                                                 int* __restrict__ offset) {
+  __shared__ int part[1024];
+  const int t = threadIdx.x;
+  const int per = (nbricks + 1023) / 1024;
+  const int b0 = t * per, b1 = min(b0 + per, nbricks);
+  int s = 0;
+  for (int b = b0; b < b1; ++b) s += count[b];
+  part[t] = s;
+  __syncthreads();
+  for (int w = 1; w < 1024; w <<= 1) {  // Hillis-Steele inclusive scan
+    const int v = (t >= w) ? part[t - w] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int run = part[t] - s;
+  for (int b = b0; b < b1; ++b) {
+    offset[b] = run;
+    run += count[b];
+  }
+  if (t == 1023) offset[nbricks] = part[1023];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void bin_scatter(long n, const T* __restrict__ pos,
+                                                   const T* __restrict__ q,
+                                                   const int* __restrict__ brick_of,
+                                                   const int* __restrict__ slot,
+                                                   const int* __restrict__ offset,
+                                                   T* __restrict__ sorted,
+                                                   int* __restrict__ perm) {
+  const long i = blockIdx.x * static_cast<long>(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  const long d = offset[brick_of[i]] + slot[i];
+  sorted[4 * d + 0] = pos[3 * i + 0];
+  sorted[4 * d + 1] = pos[3 * i + 1];
+  sorted[4 * d + 2] = pos[3 * i + 2];
+  sorted[4 * d + 3] = q[i];
+  perm[d] = static_cast<int>(i);
+}
+
+// Owner-computes spread: one workgroup per grid brick.  It visits the
+// particles binned in the home bricks whose stencils reach it (per-axis
+// lists nbr[axis][brick] = {count, b0, b1, ...}), adds the stencil points that
+// fall inside its brick into an LDS tile with LDS atomics, and stores the
+// tile: every grid value is written exactly once, with no global atomics.
+template <typename T, int P>
+__global__ __launch_bounds__(256) void spread_brick(const T* __restrict__ sorted,
+                                                    const int* __restrict__ offset,
+                                                    const int* __restrict__ nbr,
+                                                    T* __restrict__ grid, GridGeom g,
+                                                    BinGeom bg) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  T* tile = reinterpret_cast<T*>(smem);
+  const int E0 = bg.edge[0], E1 = bg.edge[1], E2 = bg.edge[2];
+  int own[3], rest = blockIdx.x;
+  own[2] = rest % bg.nb[2]; rest /= bg.nb[2];
+  own[1] = rest % bg.nb[1];
+  own[0] = rest / bg.nb[1];
+  int lo[3], ext[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    lo[j] = own[j] * bg.edge[j];
+    ext[j] = min(bg.edge[j], g.K[j] - lo[j]);
+  }
+  const int ntile = E0 * E1 * E2;
+  for (int e = threadIdx.x; e < ntile; e += blockDim.x) tile[e] = T(0);
+  __syncthreads();
+  const int* n0 = nbr + kNbrRec * (0 * bg.nbmax + own[0]);
+  const int* n1 = nbr + kNbrRec * (1 * bg.nbmax + own[1]);
+  const int* n2 = nbr + kNbrRec * (2 * bg.nbmax + own[2]);
+  for (int a0 = 0; a0 < n0[0]; ++a0)
+    for (int a1 = 0; a1 < n1[0]; ++a1)
+      for (int a2 = 0; a2 < n2[0]; ++a2) {
+        const int hb = (n0[1 + a0] * bg.nb[1] + n1[1 + a1]) * bg.nb[2] + n2[1 + a2];
+        const int pb = offset[hb], pe = offset[hb + 1];
+        for (int i = pb + threadIdx.x; i < pe; i += blockDim.x) {
+          T w[3][P], dw[P];
+          int d[3][P];
+#pragma unroll
+          for (int j = 0; j < 3; ++j) {
+            int base;
+            const T f = scaled(sorted[4L * i + j], g.L[j], g.K[j], base);
+            bspline<T, P>(f, w[j], dw);
+#pragma unroll
+            for (int t = 0; t < P; ++t) {
+              int k = base - t;
+              if (k < 0) k += g.K[j];
+              const int dd = k - lo[j];
+              d[j][t] = (dd >= 0 && dd < ext[j]) ? dd : -1;
+            }
+          }
+          const T qi = sorted[4L * i + 3];
+          for (int a = 0; a < P; ++a) {
+            if (d[0][a] < 0) continue;
+            const T wa = qi * w[0][a];
+            for (int b = 0; b < P; ++b) {
+              if (d[1][b] < 0) continue;
+              const T wab = wa * w[1][b];
+              T* row = tile + (d[0][a] * E1 + d[1][b]) * E2;
+#pragma unroll
+              for (int c = 0; c < P; ++c)
+                if (d[2][c] >= 0) atomicAdd(&row[d[2][c]], wab * w[2][c]);
+            }
+          }
+        }
+      }
+  __syncthreads();
+  for (int e = threadIdx.x; e < ntile; e += blockDim.x) {
+    const int c = e % E2, b = (e / E2) % E1, a = e / (E1 * E2);
+    if (a < ext[0] && b < ext[1] && c < ext[2])
+      grid[(static_cast<long>(lo[0] + a) * g.K[1] + lo[1] + b) * g.K[2] + lo[2] + c] = tile[e];
+  }
+}
+
+// Gather in binned order (neighbouring threads read neighbouring grid
+// values); results are written back to the caller's order through perm.
+template <typename T, int P>
+__global__ __launch_bounds__(256) void gather_sorted(long n, const T* __restrict__ sorted,
+                                                     const int* __restrict__ perm,
+                                                     const T* __restrict__ grid,
+                                                     T* __restrict__ pot,
+                                                     T* __restrict__ force, GridGeom g) {
+  const long s = blockIdx.x * static_cast<long>(blockDim.x) + threadIdx.x;
+  if (s >= n) return;
+  T w[3][P], dw[3][P];
+  int base[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const T f = scaled(sorted[4 * s + j], g.L[j], g.K[j], base[j]);
+    bspline<T, P>(f, w[j], dw[j]);
+  }
+  const int K1 = g.K[0], K2 = g.K[1], K3 = g.K[2];
+  int kc[P];
+#pragma unroll
+  for (int c = 0; c < P; ++c) {
+    kc[c] = base[2] - c;
+    if (kc[c] < 0) kc[c] += K3;
+  }
+  T phi = 0, g0 = 0, g1 = 0, g2 = 0;
+  for (int a = 0; a < P; ++a) {
+    int ka = base[0] - a;
+    if (ka < 0) ka += K1;
+    T sa = 0, sa1 = 0, sa2 = 0;
+    for (int b = 0; b < P; ++b) {
+      int kb = base[1] - b;
+      if (kb < 0) kb += K2;
+      const T* row = grid + (static_cast<long>(ka) * K2 + kb) * K3;
+      T sv = 0, s2 = 0;
+#pragma unroll
+      for (int c = 0; c < P; ++c) {
+        const T v = row[kc[c]];
+        sv += w[2][c] * v;
+        s2 += dw[2][c] * v;
+      }
+      sa += w[1][b] * sv;
+      sa1 += dw[1][b] * sv;
+      sa2 += w[1][b] * s2;
+    }
+    phi += w[0][a] * sa;
+    g0 += dw[0][a] * sa;
+    g1 += w[0][a] * sa1;
+    g2 += w[0][a] * sa2;
+  }
+  const long i = perm[s];
+  if (pot) pot[i] = phi;
+  if (force) {
+    const T qi = sorted[4 * s + 3];
+    force[3 * i + 0] = -qi * g0 * static_cast<T>(K1 / g.L[0]);
+    force[3 * i + 1] = -qi * g1 * static_cast<T>(K2 / g.L[1]);
+    force[3 * i + 2] = -qi * g2 * static_cast<T>(K3 / g.L[2]);
+  }
+}
+
 // Per-block FP64 partial sums of (q pot, q, q^2), then one block combines
 // them in a fixed order: the result does not depend on scheduling.
 template <typename T>
@@ -269,6 +469,77 @@ hipError_t launch_gather_direct(int prec, const GridGeom& g, int64_t n, const vo
 #undef CALL
   }
 #define CALL(P) gather_p<float, P>(g, n, pos, q, grid, pot, force, st)
+  KPME_ORDER_SWITCH(g.p, CALL)
+#undef CALL
+}
+
+namespace {
+
+template <typename T>
+hipError_t bin_t(const GridGeom& g, const Bins& b, int64_t n, const void* pos, const void* q,
+                 hipStream_t st) {
+  hipError_t e = launch_zero(b.count, sizeof(int) * (b.geom.nbricks + 1), st);
+  if (e != hipSuccess) return e;
+  const unsigned blocks = static_cast<unsigned>((n + 255) / 256);
+  if (n > 0)
+    hipLaunchKernelGGL((bin_count<T>), dim3(blocks), dim3(256), 0, st, static_cast<long>(n),
+                       static_cast<const T*>(pos), g, b.geom, b.brick_of, b.slot, b.count);
+  hipLaunchKernelGGL(bin_scan, dim3(1), dim3(1024), 0, st, b.count, b.geom.nbricks, b.offset);
+  if (n > 0)
+    hipLaunchKernelGGL((bin_scatter<T>), dim3(blocks), dim3(256), 0, st, static_cast<long>(n),
+                       static_cast<const T*>(pos), static_cast<const T*>(q), b.brick_of, b.slot,
+                       b.offset, static_cast<T*>(b.sorted), b.perm);
+  return hipGetLastError();
+}
+
+template <typename T, int P>
+hipError_t spread_brick_p(const GridGeom& g, const Bins& b, void* grid, hipStream_t st) {
+  const size_t lds = sizeof(T) * b.geom.edge[0] * b.geom.edge[1] * b.geom.edge[2];
+  hipLaunchKernelGGL((spread_brick<T, P>), dim3(b.geom.nbricks), dim3(256), lds, st,
+                     static_cast<const T*>(b.sorted), b.offset, b.nbr, static_cast<T*>(grid),
+                     g, b.geom);
+  return hipGetLastError();
+}
+
+template <typename T, int P>
+hipError_t gather_sorted_p(const GridGeom& g, const Bins& b, int64_t n, const void* grid,
+                           void* pot, void* force, hipStream_t st) {
+  const unsigned blocks = static_cast<unsigned>((n + 255) / 256);
+  hipLaunchKernelGGL((gather_sorted<T, P>), dim3(blocks), dim3(256), 0, st,
+                     static_cast<long>(n), static_cast<const T*>(b.sorted), b.perm,
+                     static_cast<const T*>(grid), static_cast<T*>(pot), static_cast<T*>(force),
+                     g);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_bin(int prec, const GridGeom& g, const Bins& b, int64_t n, const void* pos,
+                      const void* q, hipStream_t st) {
+  return prec == PREC_FP64 ? bin_t<double>(g, b, n, pos, q, st) : bin_t<float>(g, b, n, pos, q, st);
+}
+
+hipError_t launch_spread_binned(int prec, const GridGeom& g, const Bins& b, void* grid,
+                                hipStream_t st) {
+  if (prec == PREC_FP64) {
+#define CALL(P) spread_brick_p<double, P>(g, b, grid, st)
+    KPME_ORDER_SWITCH(g.p, CALL)
+#undef CALL
+  }
+#define CALL(P) spread_brick_p<float, P>(g, b, grid, st)
+  KPME_ORDER_SWITCH(g.p, CALL)
+#undef CALL
+}
+
+hipError_t launch_gather_binned(int prec, const GridGeom& g, const Bins& b, int64_t n,
+                                const void* grid, void* pot, void* force, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  if (prec == PREC_FP64) {
+#define CALL(P) gather_sorted_p<double, P>(g, b, n, grid, pot, force, st)
+    KPME_ORDER_SWITCH(g.p, CALL)
+#undef CALL
+  }
+#define CALL(P) gather_sorted_p<float, P>(g, b, n, grid, pot, force, st)
   KPME_ORDER_SWITCH(g.p, CALL)
 #undef CALL
 }

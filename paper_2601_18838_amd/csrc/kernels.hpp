@@ -10,6 +10,7 @@ enum { PREC_FP64 = 0, PREC_FP32 = 1, PREC_BF16X3 = 2, PREC_FP16X3 = 3 };
 
 constexpr size_t kMaxLds = 160 * 1024;  // LDS per workgroup on gfx950
 constexpr int kSumBlocks = 256;          // blocks of the fixed-order FP64 sums
+                                          // (scratch needs 3 * kSumBlocks doubles)
 
 // Everything the SKP apply needs.  Pointers are device pointers; [0] is the
 // single plane (FP64/FP32) or the hi plane (BF16X3), [1] the lo plane.
@@ -28,8 +29,10 @@ struct SkpArgs {
   const int* term_group; // [R] group of each term (terms sorted by group)
   const int* part_begin; // [nparts + 1]
   double* scratch;       // >= kSumBlocks doubles
-  double* sumQ;          // 1 double
+  double* sumQ;          // 2 doubles: sum(Q), then the FP16X3 grid scale
   double c0;             // theta_hat_R(0)
+  float sy, st;          // FP16X3 powers of two applied to Y and T before splits
+  double const_scale;    // FP16X3: product of the plan-time scales
 };
 
 hipError_t launch_skp_sum(const SkpArgs& a, hipStream_t st);
@@ -44,6 +47,29 @@ struct GridGeom {
   int p;
 };
 
+// Record length of the per-axis neighbour table: {count, up to 4 bricks}.
+constexpr int kNbrRec = 5;
+
+// Brick decomposition of the grid used to bin particles.
+struct BinGeom {
+  int edge[3];   // brick edge in grid points
+  int nb[3];     // bricks per axis, ceil(K / edge)
+  int nbricks;
+  int nbmax;     // row stride of the neighbour table
+};
+
+// Device buffers of the binned particle layout.
+struct Bins {
+  BinGeom geom;
+  int* count;     // [nbricks + 1] histogram
+  int* offset;    // [nbricks + 1] exclusive prefix sums
+  int* brick_of;  // [max_n]
+  int* slot;      // [max_n] rank inside the brick
+  int* perm;      // [max_n] sorted position -> caller index
+  int* nbr;       // [3][nbmax][kNbrRec] home bricks reaching each owner brick
+  void* sorted;   // [max_n][4] x, y, z, q in binned order (plan precision)
+};
+
 // All launches are asynchronous on `st`; they return the launch status.
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
 hipError_t launch_spread_atomic(int prec, const GridGeom& g, int64_t n, const void* pos,
@@ -51,6 +77,12 @@ hipError_t launch_spread_atomic(int prec, const GridGeom& g, int64_t n, const vo
 hipError_t launch_gather_direct(int prec, const GridGeom& g, int64_t n, const void* pos,
                                 const void* q, const void* grid, void* pot, void* force,
                                 hipStream_t st);
+hipError_t launch_bin(int prec, const GridGeom& g, const Bins& b, int64_t n, const void* pos,
+                      const void* q, hipStream_t st);
+hipError_t launch_spread_binned(int prec, const GridGeom& g, const Bins& b, void* grid,
+                                hipStream_t st);
+hipError_t launch_gather_binned(int prec, const GridGeom& g, const Bins& b, int64_t n,
+                                const void* grid, void* pot, void* force, hipStream_t st);
 hipError_t launch_energy(int prec, int64_t n, const void* q, const void* pot, double beta,
                          double volume, double* scratch, double* energy4, hipStream_t st);
 

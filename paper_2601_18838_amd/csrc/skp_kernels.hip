@@ -30,18 +30,23 @@ namespace {
 constexpr int S1 = 64;  // stage-1 output tile (rows and columns)
 
 // ----------------------------------------------------------------------------
-// Stage 1, BF16X3.  C hi/lo: [nrows][K3P]; Q: fp32 [K1][K2][K3];
-// Y hi/lo: [nrows][K1P*K2P].
-__global__ __launch_bounds__(256) void stage1_bf16x3(
-    const float* __restrict__ Q, const bf16* __restrict__ Chi,
-    const bf16* __restrict__ Clo, bf16* __restrict__ Yhi, bf16* __restrict__ Ylo,
-    int K1, int K2, int K3, int K3P, int K2P, long slab, int nrows) {
+// Stage 1, split precision (BF16X3 / FP16X3).  C hi/lo: [nrows][K3P]
+// (pre-scaled); Q: fp32 [K1][K2][K3], multiplied by *qscale (a power of two,
+// FP16X3 only) before the split; the FP32 accumulator is multiplied by sy
+// (a power of two) before Y is split and stored.  Y hi/lo: [nrows][K1P*K2P].
+template <typename H>
+__global__ __launch_bounds__(256) void stage1_x3(
+    const float* __restrict__ Q, const H* __restrict__ Chi, const H* __restrict__ Clo,
+    H* __restrict__ Yhi, H* __restrict__ Ylo, int K1, int K2, int K3, int K3P, int K2P,
+    long slab, int nrows, const double* __restrict__ qscale, float sy) {
+  typedef typename HVec<H>::v8 v8;
   constexpr int KC = 32, STR = KC + 8;
-  __shared__ __attribute__((aligned(16))) bf16 Ah[S1 * STR], Al[S1 * STR], Bh[S1 * STR], Bl[S1 * STR];
+  __shared__ __attribute__((aligned(16))) H Ah[S1 * STR], Al[S1 * STR], Bh[S1 * STR], Bl[S1 * STR];
   const long m0 = static_cast<long>(blockIdx.x) * S1;
   const int n0 = blockIdx.y * S1;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1, q = lane >> 4, m = lane & 15;
+  const float sq = qscale ? static_cast<float>(*qscale) : 1.0f;
   floatx4 acc[2][2];
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
@@ -50,13 +55,13 @@ __global__ __launch_bounds__(256) void stage1_bf16x3(
     for (int e = tid; e < S1 * (KC / 8); e += 256) {
       const int r = e / (KC / 8), c8 = e % (KC / 8);
       const int n = n0 + r;
-      bf16x8 vh = {}, vl = {};
+      v8 vh = {}, vl = {};
       if (n < nrows) {
-        vh = *reinterpret_cast<const bf16x8*>(&Chi[static_cast<long>(n) * K3P + k0 + 8 * c8]);
-        vl = *reinterpret_cast<const bf16x8*>(&Clo[static_cast<long>(n) * K3P + k0 + 8 * c8]);
+        vh = *reinterpret_cast<const v8*>(&Chi[static_cast<long>(n) * K3P + k0 + 8 * c8]);
+        vl = *reinterpret_cast<const v8*>(&Clo[static_cast<long>(n) * K3P + k0 + 8 * c8]);
       }
-      *reinterpret_cast<bf16x8*>(&Ah[r * STR + 8 * c8]) = vh;
-      *reinterpret_cast<bf16x8*>(&Al[r * STR + 8 * c8]) = vl;
+      *reinterpret_cast<v8*>(&Ah[r * STR + 8 * c8]) = vh;
+      *reinterpret_cast<v8*>(&Al[r * STR + 8 * c8]) = vl;
     }
     for (int e = tid; e < S1 * KC; e += 256) {
       const int r = e / KC, c = e % KC;
@@ -64,25 +69,25 @@ __global__ __launch_bounds__(256) void stage1_bf16x3(
       const int g1 = static_cast<int>(mp / K2P), g2 = static_cast<int>(mp % K2P);
       const int k = k0 + c;
       float x = 0.f;
-      if (g1 < K1 && g2 < K2 && k < K3) x = Q[(static_cast<long>(g1) * K2 + g2) * K3 + k];
-      bf16 h, l;
-      split_bf16(x, h, l);
+      if (g1 < K1 && g2 < K2 && k < K3) x = sq * Q[(static_cast<long>(g1) * K2 + g2) * K3 + k];
+      H h, l;
+      split_h<H>(x, h, l);
       Bh[r * STR + c] = h;
       Bl[r * STR + c] = l;
     }
     __syncthreads();
-    bf16x8 ah[2], al[2], bh[2], bl[2];
+    v8 ah[2], al[2], bh[2], bl[2];
     for (int i = 0; i < 2; ++i) {
-      ah[i] = *reinterpret_cast<const bf16x8*>(&Ah[(wr * 32 + 16 * i + m) * STR + 8 * q]);
-      al[i] = *reinterpret_cast<const bf16x8*>(&Al[(wr * 32 + 16 * i + m) * STR + 8 * q]);
-      bh[i] = *reinterpret_cast<const bf16x8*>(&Bh[(wc * 32 + 16 * i + m) * STR + 8 * q]);
-      bl[i] = *reinterpret_cast<const bf16x8*>(&Bl[(wc * 32 + 16 * i + m) * STR + 8 * q]);
+      ah[i] = *reinterpret_cast<const v8*>(&Ah[(wr * 32 + 16 * i + m) * STR + 8 * q]);
+      al[i] = *reinterpret_cast<const v8*>(&Al[(wr * 32 + 16 * i + m) * STR + 8 * q]);
+      bh[i] = *reinterpret_cast<const v8*>(&Bh[(wc * 32 + 16 * i + m) * STR + 8 * q]);
+      bl[i] = *reinterpret_cast<const v8*>(&Bl[(wc * 32 + 16 * i + m) * STR + 8 * q]);
     }
     for (int i = 0; i < 2; ++i)
       for (int j = 0; j < 2; ++j) {
-        acc[i][j] = mfma_bf16(ah[i], bh[j], acc[i][j]);
-        acc[i][j] = mfma_bf16(ah[i], bl[j], acc[i][j]);
-        acc[i][j] = mfma_bf16(al[i], bh[j], acc[i][j]);
+        acc[i][j] = mfma_h(ah[i], bh[j], acc[i][j]);
+        acc[i][j] = mfma_h(ah[i], bl[j], acc[i][j]);
+        acc[i][j] = mfma_h(al[i], bh[j], acc[i][j]);
       }
   }
   for (int i = 0; i < 2; ++i)
@@ -91,8 +96,8 @@ __global__ __launch_bounds__(256) void stage1_bf16x3(
         const int row = n0 + wr * 32 + 16 * i + 4 * q + r;
         const long col = m0 + wc * 32 + 16 * j + m;
         if (row < nrows && col < slab) {
-          bf16 h, l;
-          split_bf16(acc[i][j][r], h, l);
+          H h, l;
+          split_h<H>(sy * acc[i][j][r], h, l);
           Yhi[row * slab + col] = h;
           Ylo[row * slab + col] = l;
         }
@@ -148,23 +153,26 @@ __global__ __launch_bounds__(256) void stage1_k4(const T* __restrict__ Q,
 }
 
 // ----------------------------------------------------------------------------
-// Stage 2, BF16X3.  One workgroup = (slab s, term part); wave w owns output
-// columns [32 w, 32 w + 32).  LDS: Y slab hi/lo [K1P][K2P + 8]; A_t hi/lo
-// [K1P][K1P + 8] when it fits (A_LDS), else A_t is read from global memory.
-template <int RT, bool A_LDS>
-__global__ __launch_bounds__(512) void stage2_bf16x3(
-    const bf16* __restrict__ Yhi, const bf16* __restrict__ Ylo,
-    const bf16* __restrict__ Ahi, const bf16* __restrict__ Alo,
-    const bf16* __restrict__ Bhi, const bf16* __restrict__ Blo,
+// Stage 2, split precision.  One workgroup = (slab s, term part); wave w owns
+// output columns [32 w, 32 w + 32).  LDS: Y slab hi/lo [K1P][K2P + 8]; A_t
+// hi/lo [K1P][K1P + 8] when it fits (A_LDS), else A_t is read from global
+// memory.  T is multiplied by st (a power of two, FP16X3) before its split.
+template <typename H, int RT, bool A_LDS>
+__global__ __launch_bounds__(512) void stage2_x3(
+    const H* __restrict__ Yhi, const H* __restrict__ Ylo,
+    const H* __restrict__ Ahi, const H* __restrict__ Alo,
+    const H* __restrict__ Bhi, const H* __restrict__ Blo,
     const int* __restrict__ term_group, const int* __restrict__ part_begin,
-    float* __restrict__ Phi_part, int K1, int K2, int K3, int K2P) {
+    float* __restrict__ Phi_part, int K1, int K2, int K3, int K2P, float st) {
+  typedef typename HVec<H>::v8 v8;
+  typedef typename HVec<H>::v4 v4;
   constexpr int K1P = RT * 16, CT = 2, ASTR = K1P + 8;
   const int YSTR = K2P + 8;
   extern __shared__ __attribute__((aligned(16))) char smem[];
-  bf16* Ysh = reinterpret_cast<bf16*>(smem);
-  bf16* Ysl = Ysh + K1P * YSTR;
-  bf16* Ash = Ysl + K1P * YSTR;
-  bf16* Asl = Ash + K1P * ASTR;
+  H* Ysh = reinterpret_cast<H*>(smem);
+  H* Ysl = Ysh + K1P * YSTR;
+  H* Ash = Ysl + K1P * YSTR;
+  H* Asl = Ash + K1P * ASTR;
   const int s = blockIdx.x, part = blockIdx.y;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int lane = tid & 63, wave = tid >> 6, q = lane >> 4, m = lane & 15;
@@ -179,28 +187,28 @@ __global__ __launch_bounds__(512) void stage2_bf16x3(
     const int g = term_group[t];
     __syncthreads();
     if (g != cur) {
-      const bf16* yh = Yhi + (static_cast<long>(g) * K3 + s) * slab;
-      const bf16* yl = Ylo + (static_cast<long>(g) * K3 + s) * slab;
+      const H* yh = Yhi + (static_cast<long>(g) * K3 + s) * slab;
+      const H* yl = Ylo + (static_cast<long>(g) * K3 + s) * slab;
       const int cpr = K2P / 8;
       for (int e = tid; e < K1P * cpr; e += nthr) {
         const int r = e / cpr, c8 = e % cpr;
-        *reinterpret_cast<bf16x8*>(&Ysh[r * YSTR + 8 * c8]) =
-            *reinterpret_cast<const bf16x8*>(&yh[static_cast<long>(r) * K2P + 8 * c8]);
-        *reinterpret_cast<bf16x8*>(&Ysl[r * YSTR + 8 * c8]) =
-            *reinterpret_cast<const bf16x8*>(&yl[static_cast<long>(r) * K2P + 8 * c8]);
+        *reinterpret_cast<v8*>(&Ysh[r * YSTR + 8 * c8]) =
+            *reinterpret_cast<const v8*>(&yh[static_cast<long>(r) * K2P + 8 * c8]);
+        *reinterpret_cast<v8*>(&Ysl[r * YSTR + 8 * c8]) =
+            *reinterpret_cast<const v8*>(&yl[static_cast<long>(r) * K2P + 8 * c8]);
       }
       cur = g;
     }
-    const bf16* ah_g = Ahi + static_cast<long>(t) * K1P * K1P;
-    const bf16* al_g = Alo + static_cast<long>(t) * K1P * K1P;
+    const H* ah_g = Ahi + static_cast<long>(t) * K1P * K1P;
+    const H* al_g = Alo + static_cast<long>(t) * K1P * K1P;
     if (A_LDS) {
       constexpr int cpr = K1P / 8;
       for (int e = tid; e < K1P * cpr; e += nthr) {
         const int r = e / cpr, c8 = e % cpr;
-        *reinterpret_cast<bf16x8*>(&Ash[r * ASTR + 8 * c8]) =
-            *reinterpret_cast<const bf16x8*>(&ah_g[r * K1P + 8 * c8]);
-        *reinterpret_cast<bf16x8*>(&Asl[r * ASTR + 8 * c8]) =
-            *reinterpret_cast<const bf16x8*>(&al_g[r * K1P + 8 * c8]);
+        *reinterpret_cast<v8*>(&Ash[r * ASTR + 8 * c8]) =
+            *reinterpret_cast<const v8*>(&ah_g[r * K1P + 8 * c8]);
+        *reinterpret_cast<v8*>(&Asl[r * ASTR + 8 * c8]) =
+            *reinterpret_cast<const v8*>(&al_g[r * K1P + 8 * c8]);
       }
     }
     __syncthreads();
@@ -209,63 +217,63 @@ __global__ __launch_bounds__(512) void stage2_bf16x3(
     floatx4 acc1[RT][CT];
     for (int i = 0; i < RT; ++i)
       for (int j = 0; j < CT; ++j) acc1[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    const bf16* bh_g = Bhi + static_cast<long>(t) * K2P * K2P;
-    const bf16* bl_g = Blo + static_cast<long>(t) * K2P * K2P;
+    const H* bh_g = Bhi + static_cast<long>(t) * K2P * K2P;
+    const H* bl_g = Blo + static_cast<long>(t) * K2P * K2P;
     for (int kc = 0; kc < K2P / 32; ++kc) {
-      bf16x8 bh[CT], bl[CT];
+      v8 bh[CT], bl[CT];
       for (int j = 0; j < CT; ++j) {
         const long off = static_cast<long>(col0 + 16 * j + m) * K2P + 32 * kc + 8 * q;
-        bh[j] = *reinterpret_cast<const bf16x8*>(&bh_g[off]);
-        bl[j] = *reinterpret_cast<const bf16x8*>(&bl_g[off]);
+        bh[j] = *reinterpret_cast<const v8*>(&bh_g[off]);
+        bl[j] = *reinterpret_cast<const v8*>(&bl_g[off]);
       }
       for (int i = 0; i < RT; ++i) {
         const int off = (16 * i + m) * YSTR + 32 * kc + 8 * q;
-        const bf16x8 ah = *reinterpret_cast<const bf16x8*>(&Ysh[off]);
-        const bf16x8 al = *reinterpret_cast<const bf16x8*>(&Ysl[off]);
+        const v8 ah = *reinterpret_cast<const v8*>(&Ysh[off]);
+        const v8 al = *reinterpret_cast<const v8*>(&Ysl[off]);
         for (int j = 0; j < CT; ++j) {
-          acc1[i][j] = mfma_bf16(ah, bh[j], acc1[i][j]);
-          acc1[i][j] = mfma_bf16(ah, bl[j], acc1[i][j]);
-          acc1[i][j] = mfma_bf16(al, bh[j], acc1[i][j]);
+          acc1[i][j] = mfma_h(ah, bh[j], acc1[i][j]);
+          acc1[i][j] = mfma_h(ah, bl[j], acc1[i][j]);
+          acc1[i][j] = mfma_h(al, bh[j], acc1[i][j]);
         }
       }
     }
-    // split T into bf16 hi/lo, in the accumulator layout
-    bf16x4 th[RT][CT], tl[RT][CT];
+    // split T into 16-bit hi/lo, in the accumulator layout
+    v4 th[RT][CT], tl[RT][CT];
     for (int i = 0; i < RT; ++i)
       for (int j = 0; j < CT; ++j)
         for (int r = 0; r < 4; ++r) {
-          bf16 h, l;
-          split_bf16(acc1[i][j][r], h, l);
+          H h, l;
+          split_h<H>(st * acc1[i][j][r], h, l);
           th[i][j][r] = h;
           tl[i][j][r] = l;
         }
     // GEMM2: Phi[k1][k2] += sum_g1 A_t[k1][g1] T[g1][k2], K chunks of 32 rows
     // of T taken as {32c + 4q + r} u {32c + 16 + 4q + r}.
     for (int c = 0; c < RT / 2; ++c) {
-      bf16x8 tbh[CT], tbl[CT];
+      v8 tbh[CT], tbl[CT];
       for (int j = 0; j < CT; ++j) {
-        tbh[j] = cat44(th[2 * c][j], th[2 * c + 1][j]);
-        tbl[j] = cat44(tl[2 * c][j], tl[2 * c + 1][j]);
+        tbh[j] = cat44<v4, v8>(th[2 * c][j], th[2 * c + 1][j]);
+        tbl[j] = cat44<v4, v8>(tl[2 * c][j], tl[2 * c + 1][j]);
       }
       for (int i = 0; i < RT; ++i) {
-        bf16x8 ah, al;
+        v8 ah, al;
         if (A_LDS) {
           const int off = (16 * i + m) * ASTR + 32 * c + 4 * q;
-          ah = cat44(*reinterpret_cast<const bf16x4*>(&Ash[off]),
-                     *reinterpret_cast<const bf16x4*>(&Ash[off + 16]));
-          al = cat44(*reinterpret_cast<const bf16x4*>(&Asl[off]),
-                     *reinterpret_cast<const bf16x4*>(&Asl[off + 16]));
+          ah = cat44<v4, v8>(*reinterpret_cast<const v4*>(&Ash[off]),
+                     *reinterpret_cast<const v4*>(&Ash[off + 16]));
+          al = cat44<v4, v8>(*reinterpret_cast<const v4*>(&Asl[off]),
+                     *reinterpret_cast<const v4*>(&Asl[off + 16]));
         } else {
           const int off = (16 * i + m) * K1P + 32 * c + 4 * q;
-          ah = cat44(*reinterpret_cast<const bf16x4*>(&ah_g[off]),
-                     *reinterpret_cast<const bf16x4*>(&ah_g[off + 16]));
-          al = cat44(*reinterpret_cast<const bf16x4*>(&al_g[off]),
-                     *reinterpret_cast<const bf16x4*>(&al_g[off + 16]));
+          ah = cat44<v4, v8>(*reinterpret_cast<const v4*>(&ah_g[off]),
+                     *reinterpret_cast<const v4*>(&ah_g[off + 16]));
+          al = cat44<v4, v8>(*reinterpret_cast<const v4*>(&al_g[off]),
+                     *reinterpret_cast<const v4*>(&al_g[off + 16]));
         }
         for (int j = 0; j < CT; ++j) {
-          acc2[i][j] = mfma_bf16(ah, tbh[j], acc2[i][j]);
-          acc2[i][j] = mfma_bf16(ah, tbl[j], acc2[i][j]);
-          acc2[i][j] = mfma_bf16(al, tbh[j], acc2[i][j]);
+          acc2[i][j] = mfma_h(ah, tbh[j], acc2[i][j]);
+          acc2[i][j] = mfma_h(ah, tbl[j], acc2[i][j]);
+          acc2[i][j] = mfma_h(al, tbh[j], acc2[i][j]);
         }
       }
     }
@@ -368,10 +376,13 @@ template <typename A, typename O>
 __global__ __launch_bounds__(256) void finalize(const A* __restrict__ part, int nparts,
                                                 O* __restrict__ Phi, int K1, int K2,
                                                 int K3, const double* __restrict__ sumQ,
-                                                double c0) {
+                                                double c0, const double* __restrict__ qscale,
+                                                double const_scale) {
   __shared__ A tile[32][33];
   const int k1 = blockIdx.z, k2b = blockIdx.x * 32, k3b = blockIdx.y * 32;
   const A corr = static_cast<A>(c0 * sumQ[0]);
+  // the partial slabs carry the product of the split-precision scales
+  const A unscale = qscale ? static_cast<A>(1.0 / (qscale[0] * const_scale)) : A(1);
   const long pstride = static_cast<long>(K3) * K1 * K2;
   for (int j = threadIdx.y; j < 32; j += 8) {
     const int k3 = k3b + j, k2 = k2b + threadIdx.x;
@@ -386,39 +397,67 @@ __global__ __launch_bounds__(256) void finalize(const A* __restrict__ part, int 
   for (int j = threadIdx.y; j < 32; j += 8) {
     const int k2 = k2b + j, k3 = k3b + threadIdx.x;
     if (k2 < K2 && k3 < K3)
-      Phi[(static_cast<long>(k1) * K2 + k2) * K3 + k3] = static_cast<O>(tile[threadIdx.x][j] - corr);
+      Phi[(static_cast<long>(k1) * K2 + k2) * K3 + k3] =
+          static_cast<O>(unscale * tile[threadIdx.x][j] - corr);
   }
 }
 
+// Fixed-order FP64 sum and max |x| of a grid: per-block partials, then one
+// block combines them.
 template <typename T>
 __global__ __launch_bounds__(256) void sum_partial(const T* __restrict__ x, long n,
                                                    double* __restrict__ part) {
-  __shared__ double red[256];
+  __shared__ double red[256], mx[256];
   const long per = (n + gridDim.x - 1) / gridDim.x;
   const long b = per * blockIdx.x, e = (b + per < n) ? b + per : n;
-  double acc = 0.0;
-  for (long i = b + threadIdx.x; i < e; i += blockDim.x) acc += static_cast<double>(x[i]);
+  double acc = 0.0, amax = 0.0;
+  for (long i = b + threadIdx.x; i < e; i += blockDim.x) {
+    const double v = static_cast<double>(x[i]);
+    acc += v;
+    amax = fmax(amax, fabs(v));
+  }
   red[threadIdx.x] = acc;
+  mx[threadIdx.x] = amax;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    if (threadIdx.x < w) {
+      red[threadIdx.x] += red[threadIdx.x + w];
+      mx[threadIdx.x] = fmax(mx[threadIdx.x], mx[threadIdx.x + w]);
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = red[0];
+    part[2 * blockIdx.x + 1] = mx[0];
+  }
 }
 
+// out[0] = sum; out[1] = 2^(13 - floor(log2 max|x|)), the power of two that
+// brings the largest grid value into [2^13, 2^14) for the FP16X3 split
+// (1 for an all-zero or non-finite grid).
 __global__ __launch_bounds__(256) void sum_final(const double* __restrict__ part, int np,
                                                  double* __restrict__ out) {
-  __shared__ double red[256];
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < np; i += 256) acc += part[i];
+  __shared__ double red[256], mx[256];
+  double acc = 0.0, amax = 0.0;
+  for (int i = threadIdx.x; i < np; i += 256) {
+    acc += part[2 * i];
+    amax = fmax(amax, part[2 * i + 1]);
+  }
   red[threadIdx.x] = acc;
+  mx[threadIdx.x] = amax;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    if (threadIdx.x < w) {
+      red[threadIdx.x] += red[threadIdx.x + w];
+      mx[threadIdx.x] = fmax(mx[threadIdx.x], mx[threadIdx.x + w]);
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[0] = red[0];
+  if (threadIdx.x == 0) {
+    out[0] = red[0];
+    const double m = mx[0];
+    out[1] = (m > 0.0 && m < 1e300) ? ldexp(1.0, 13 - ilogb(m)) : 1.0;
+  }
 }
 
 template <typename K>
@@ -428,20 +467,20 @@ hipError_t set_lds(K kernel, size_t bytes) {
                              static_cast<int>(bytes));
 }
 
-template <int RT, bool AL>
-hipError_t launch_s2_bf16(const SkpArgs& a, hipStream_t st) {
+template <typename H, int RT, bool AL>
+hipError_t launch_s2_x3(const SkpArgs& a, hipStream_t st) {
   const int K1P = RT * 16;
-  size_t lds = 2 * sizeof(bf16) * static_cast<size_t>(K1P) * (a.K2P + 8);
-  if (AL) lds += 2 * sizeof(bf16) * static_cast<size_t>(K1P) * (K1P + 8);
-  hipError_t e = set_lds(stage2_bf16x3<RT, AL>, lds);
+  size_t lds = 2 * sizeof(H) * static_cast<size_t>(K1P) * (a.K2P + 8);
+  if (AL) lds += 2 * sizeof(H) * static_cast<size_t>(K1P) * (K1P + 8);
+  hipError_t e = set_lds(stage2_x3<H, RT, AL>, lds);
   if (e != hipSuccess) return e;
   const int threads = 64 * (a.K2P / 32);
-  hipLaunchKernelGGL((stage2_bf16x3<RT, AL>), dim3(a.K[2], a.nparts), dim3(threads), lds, st,
-                     static_cast<const bf16*>(a.Y[0]), static_cast<const bf16*>(a.Y[1]),
-                     static_cast<const bf16*>(a.A[0]), static_cast<const bf16*>(a.A[1]),
-                     static_cast<const bf16*>(a.B[0]), static_cast<const bf16*>(a.B[1]),
+  hipLaunchKernelGGL((stage2_x3<H, RT, AL>), dim3(a.K[2], a.nparts), dim3(threads), lds, st,
+                     static_cast<const H*>(a.Y[0]), static_cast<const H*>(a.Y[1]),
+                     static_cast<const H*>(a.A[0]), static_cast<const H*>(a.A[1]),
+                     static_cast<const H*>(a.B[0]), static_cast<const H*>(a.B[1]),
                      a.term_group, a.part_begin, static_cast<float*>(a.Phi_part),
-                     a.K[0], a.K[1], a.K[2], a.K2P);
+                     a.K[0], a.K[1], a.K[2], a.K2P, a.st);
   return hipGetLastError();
 }
 
@@ -463,9 +502,13 @@ hipError_t launch_s2_k4(const SkpArgs& a, hipStream_t st) {
 template <int RT>
 hipError_t dispatch_s2(const SkpArgs& a, hipStream_t st) {
   const int K1P = RT * 16;
-  if (a.prec == PREC_BF16X3) {
+  if (a.prec == PREC_BF16X3 || a.prec == PREC_FP16X3) {
     const size_t full = 2 * sizeof(bf16) * static_cast<size_t>(K1P) * (a.K2P + 8 + K1P + 8);
-    return full <= kMaxLds ? launch_s2_bf16<RT, true>(a, st) : launch_s2_bf16<RT, false>(a, st);
+    if (a.prec == PREC_BF16X3)
+      return full <= kMaxLds ? launch_s2_x3<bf16, RT, true>(a, st)
+                             : launch_s2_x3<bf16, RT, false>(a, st);
+    return full <= kMaxLds ? launch_s2_x3<f16, RT, true>(a, st)
+                           : launch_s2_x3<f16, RT, false>(a, st);
   }
   if (a.prec == PREC_FP32) {
     const size_t full = sizeof(float) * static_cast<size_t>(K1P) * (a.K2P + 1 + K1P + 1);
@@ -480,7 +523,7 @@ hipError_t dispatch_s2(const SkpArgs& a, hipStream_t st) {
 }  // namespace
 
 size_t stage2_lds_bytes(int prec, int K1P, int K2P) {
-  if (prec == PREC_BF16X3) return 2 * sizeof(bf16) * static_cast<size_t>(K1P) * (K2P + 8);
+  if (prec == PREC_BF16X3 || prec == PREC_FP16X3) return 2 * sizeof(bf16) * static_cast<size_t>(K1P) * (K2P + 8);
   if (prec == PREC_FP32) return sizeof(float) * static_cast<size_t>(K1P) * (K2P + 1);
   return sizeof(double) * static_cast<size_t>(K1P) * (K2P + 1);
 }
@@ -503,10 +546,15 @@ hipError_t launch_skp_stage1(const SkpArgs& a, hipStream_t st) {
   const int nrows = a.r0 * a.K[2];
   dim3 g1(static_cast<unsigned>(slab / S1), (nrows + S1 - 1) / S1);
   if (a.prec == PREC_BF16X3)
-    hipLaunchKernelGGL(stage1_bf16x3, g1, dim3(256), 0, st, static_cast<const float*>(a.Q),
+    hipLaunchKernelGGL((stage1_x3<bf16>), g1, dim3(256), 0, st, static_cast<const float*>(a.Q),
                        static_cast<const bf16*>(a.C[0]), static_cast<const bf16*>(a.C[1]),
                        static_cast<bf16*>(a.Y[0]), static_cast<bf16*>(a.Y[1]), a.K[0], a.K[1],
-                       a.K[2], a.K3P, a.K2P, slab, nrows);
+                       a.K[2], a.K3P, a.K2P, slab, nrows, nullptr, 1.0f);
+  else if (a.prec == PREC_FP16X3)
+    hipLaunchKernelGGL((stage1_x3<f16>), g1, dim3(256), 0, st, static_cast<const float*>(a.Q),
+                       static_cast<const f16*>(a.C[0]), static_cast<const f16*>(a.C[1]),
+                       static_cast<f16*>(a.Y[0]), static_cast<f16*>(a.Y[1]), a.K[0], a.K[1],
+                       a.K[2], a.K3P, a.K2P, slab, nrows, a.sumQ + 1, a.sy);
   else if (a.prec == PREC_FP32)
     hipLaunchKernelGGL((stage1_k4<float>), g1, dim3(256), 0, st, static_cast<const float*>(a.Q),
                        static_cast<const float*>(a.C[0]), static_cast<float*>(a.Y[0]), a.K[0],
@@ -534,11 +582,13 @@ hipError_t launch_skp_finalize(const SkpArgs& a, hipStream_t st) {
   if (a.prec == PREC_FP64)
     hipLaunchKernelGGL((finalize<double, double>), gf, dim3(32, 8), 0, st,
                        static_cast<const double*>(a.Phi_part), a.nparts,
-                       static_cast<double*>(a.Phi), a.K[0], a.K[1], a.K[2], a.sumQ, a.c0);
+                       static_cast<double*>(a.Phi), a.K[0], a.K[1], a.K[2], a.sumQ, a.c0,
+                       nullptr, 1.0);
   else
     hipLaunchKernelGGL((finalize<float, float>), gf, dim3(32, 8), 0, st,
                        static_cast<const float*>(a.Phi_part), a.nparts,
-                       static_cast<float*>(a.Phi), a.K[0], a.K[1], a.K[2], a.sumQ, a.c0);
+                       static_cast<float*>(a.Phi), a.K[0], a.K[1], a.K[2], a.sumQ, a.c0,
+                       a.prec == PREC_FP16X3 ? a.sumQ + 1 : nullptr, a.const_scale);
   return hipGetLastError();
 }
 

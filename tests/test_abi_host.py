@@ -48,7 +48,7 @@ def _create(box=(20, 20, 20), grid=(16, 16, 16), p=4, beta=0.35, rank=8, tol=0.0
     (dict(p=5), 2), (dict(p=3), 2), (dict(p=14), 1), (dict(grid=(3, 16, 16)), 1),
     (dict(grid=(16, 16, 300)), 1), (dict(grid=(6, 16, 16), p=8), 1), (dict(beta=-1.0), 1),
     (dict(rank=0, tol=0.0), 1), (dict(rank=0, tol=2.0), 1), (dict(prec=7), 1),
-    (dict(nmax=0), 1), (dict(prec=3), 2), (dict(grid=(160, 16, 16)), 2),
+    (dict(nmax=0), 1), (dict(grid=(160, 16, 16)), 2),
 ])
 def test_plan_create_validates_before_touching_a_device(kw, code):
     st, h = _create(**kw)
