@@ -35,7 +35,24 @@ def parse():
     ap.add_argument("--workload", default="water_100k", choices=["water_100k", "water_1m"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-evals", type=int, default=5)
+    ap.add_argument("--mixed-only", action="store_true",
+                    help="time only the mixed path (short profiler runs)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="run 5 device copies of MIB MiB and exit (byte-counter calibration)")
     return ap.parse_args()
+
+
+def copy_calibration(mib):
+    """Five plain device-to-device copies of a known size, for scaling HBM byte counters."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read": n * 4, "bytes_written": n * 4,
+                      "dispatches": 5}), flush=True)
 
 
 def time_steps(plan, P, Q, out, steps, warmup):
@@ -82,6 +99,9 @@ def main():
         sys.exit(2)
     import torch
     from paper_2601_18838_amd import kpme, systems
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
 
     wl = systems.WATER_100K if args.workload == "water_100k" else systems.WATER_1M
     pos, q = wl.particles()
@@ -112,8 +132,11 @@ def main():
 
     t_mixed, st_mixed = time_steps(plans[mixed], *tensors[mixed], outs[mixed], args.steps,
                                    args.warmup)
-    t_ref, st_ref = time_steps(plans[ref], *tensors[ref], outs[ref], max(5, args.steps // 5),
-                               min(args.warmup, 2))
+    if args.mixed_only:
+        t_ref, st_ref = float("nan"), {k: (float("nan"), 1) for k in st_mixed}
+    else:
+        t_ref, st_ref = time_steps(plans[ref], *tensors[ref], outs[ref],
+                                   max(5, args.steps // 5), min(args.warmup, 2))
 
     K1, K2, K3 = wl.grid
     G = K1 * K2 * K3
