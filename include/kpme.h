@@ -162,17 +162,23 @@ kpme_status kpme_evaluate(kpme_plan_t plan, int64_t n, const void* pos,
                           const void* q, void* pot, void* force,
                           double* energy4, void* stream);
 
-/* Adjoint of kpme_evaluate for reverse-mode differentiation.  Given the
- * forward inputs and upstream gradients g_E (scalar, host) and g_pot (device,
- * n, may be NULL), writes
+/* Adjoint of kpme_evaluate for reverse-mode differentiation of
+ *   L = g_E * energy4[3] + sum_i g_pot_i * pot_i,
+ * the chain rule through the spread, the symmetric corrected operator Theta
+ * (Eq. formfinale with Eq. termbonsum) and the gather:
  *   grad_pos_i = grad W_i . [ (g_E q_i + g_pot_i) Phi + q_i Psi ],
- *   grad_q_i   = g_E (pot_i + self_i + neutral_i) + (W_i . Psi)
- * where Phi = Theta S q, Psi = Theta S g_pot (Theta symmetric) and
- * self_i = -2 beta q_i / sqrt(pi), neutral_i = -pi sum(q) / (V beta^2).
- * grad_pos (n x 3) and grad_q (n) are device buffers; either may be NULL. */
+ *   grad_q_i   = g_E (pot_i - 2 beta q_i / sqrt(pi) - pi sum(q) / (V beta^2))
+ *                + W_i . Psi,
+ * with Phi = Theta S q and Psi = Theta S g_pot.
+ *   g_energy  DEVICE pointer to one double (NULL: 0).
+ *   g_pot     device, n values (NULL: 0).
+ *   grad_pos  device, n x 3 (NULL: not computed); grad_q device, n (NULL: not
+ *             computed).
+ * Costs two spreads, two operator applications and one gather over both
+ * grids; allocates nothing. */
 kpme_status kpme_evaluate_backward(kpme_plan_t plan, int64_t n,
                                    const void* pos, const void* q,
-                                   double g_energy, const void* g_pot,
+                                   const double* g_energy, const void* g_pot,
                                    void* grad_pos, void* grad_q,
                                    void* stream);
 

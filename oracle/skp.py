@@ -179,3 +179,29 @@ class Plan:
         phi, F = spme.gather(pos, q, self.box, self.K, self.p, Phi)
         return {"E_rec": 0.5 * float(q @ phi), "phi": phi, "F": F, "Q": Q,
                 "Phi": Phi}
+
+
+def backward(plan, pos, q, g_energy, g_pot):
+    """Gradients of L = g_energy * (E_rec + E_self + E_neutral) + sum_i g_pot_i phi_i.
+
+    phi = S* Theta S q with Theta the corrected (symmetric) operator; with
+    Phi = Theta S q and Psi = Theta S g_pot:
+      dL/dr_i = grad W_i . [(g_energy q_i + g_pot_i) Phi + q_i Psi]
+      dL/dq_i = g_energy (phi_i - 2 beta q_i / sqrt(pi) - pi sum(q) / (V beta^2)) + W_i . Psi
+    Written from the chain rule of the definitions above; pinned by central
+    finite differences of `Plan.evaluate` (tests/test_oracle_backward.py).
+    """
+    q = np.asarray(q, np.float64)
+    n = len(q)
+    g_pot = np.zeros(n) if g_pot is None else np.asarray(g_pot, np.float64)
+    ones = np.ones(n)
+    Phi = plan.apply(spme.spread(pos, q, plan.box, plan.K, plan.p))
+    Psi = plan.apply(spme.spread(pos, g_pot, plan.box, plan.K, plan.p))
+    phi, f_phi = spme.gather(pos, ones, plan.box, plan.K, plan.p, Phi)
+    psi, f_psi = spme.gather(pos, ones, plan.box, plan.K, plan.p, Psi)
+    grad_w_phi, grad_w_psi = -f_phi, -f_psi        # gradient of W_i . grid
+    V = float(np.prod(plan.box))
+    grad_pos = (g_energy * q + g_pot)[:, None] * grad_w_phi + q[:, None] * grad_w_psi
+    grad_q = g_energy * (phi - 2.0 * plan.beta * q / np.sqrt(np.pi)
+                         - np.pi * q.sum() / (V * plan.beta ** 2)) + psi
+    return grad_pos, grad_q

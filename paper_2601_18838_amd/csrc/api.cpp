@@ -97,6 +97,8 @@ struct kpme_plan_s {
   size_t ws_bytes = 0;
   std::vector<void*> allocations;
   // device arrays
+  void* vec = nullptr;        // split paths: per-term circulant vector copies
+  int blen = 0, alen = 0;
   void* A[2] = {nullptr, nullptr};
   void* B[2] = {nullptr, nullptr};
   void* C[2] = {nullptr, nullptr};
@@ -110,6 +112,12 @@ struct kpme_plan_s {
   void* Phig = nullptr;
   void* pot = nullptr;        // internal potentials (max_n)
   Bins bins{};                // binned particle layout (evaluate, spread)
+  double* part2 = nullptr;    // per-brick (sum, max) of the spread grid
+  void* Q2g = nullptr;        // adjoint: spread of the upstream potential gradient
+  void* Psig = nullptr;       // adjoint: Theta applied to it
+  void* sorted2 = nullptr;    // adjoint: binned (x, y, z, g_pot)
+  double* part3 = nullptr;    // per-256-particle energy partial sums
+  int gather_blocks = 0;
   // per-stage hipEvent pairs recorded on the calling stream while profiling
   bool prof_on = false;
   std::vector<hipEvent_t> prof_ev[KPME_NUM_STAGES][2];
@@ -277,6 +285,8 @@ kpme_status kpme_plan_create(kpme_plan_t* plan, const double box[3], const int g
   const int K1P = round_up(grid[0], 32), K2P = round_up(grid[1], 32), K3P = round_up(grid[2], 32);
   if (K1P > 128)
     return fail(KPME_ERROR_NOT_SUPPORTED, "K1 > 128 is not supported by the SKP kernels");
+  if ((precision == KPME_BF16X3 || precision == KPME_FP16X3) && K1P == 128 && K2P > 128)
+    return fail(KPME_ERROR_NOT_SUPPORTED, "split precisions need K2 <= 128 when K1 > 96");
   if (stage2_lds_bytes(precision, K1P, K2P) > kMaxLds)
     return fail(KPME_ERROR_NOT_SUPPORTED, "K1 x K2 slab does not fit in LDS at this precision");
   int ndev = 0;
@@ -323,6 +333,11 @@ kpme_status kpme_plan_create(kpme_plan_t* plan, const double box[3], const int g
   pl->r0 = r0;
   const int K1 = grid[0], K2 = grid[1], K3 = grid[2];
   pl->nparts = std::max(1, std::min(R, (512 + K3 - 1) / K3));
+  // tuning override: number of term ranges per slab in stage 2
+  if (const char* env = std::getenv("KPME_STAGE2_PARTS")) {
+    const int v = std::atoi(env);
+    if (v >= 1) pl->nparts = std::min(R, v);
+  }
   std::vector<int> pb(pl->nparts + 1);
   for (int p = 0; p <= pl->nparts; ++p) pb[p] = static_cast<int>((static_cast<long>(R) * p) / pl->nparts);
 
@@ -385,8 +400,55 @@ kpme_status kpme_plan_create(kpme_plan_t* plan, const double box[3], const int g
     pl->const_scale = sA * sB * sC * sy * st_;
   }
 
+  // Split paths: per term, [hi plane | lo plane], each plane holding 8 shifted
+  // copies of the reversed axis-1 generating vector (length blen) and 4 of the
+  // reversed, omega-weighted axis-0 vector (length alen); see stage 2.
+  const bool split = (precision == KPME_BF16X3 || precision == KPME_FP16X3);
+  std::vector<uint16_t> hvec;
+  if (split) {
+    pl->blen = x3_blen(K2P);
+    pl->alen = x3_alen(K1P);
+    const size_t plane = 8 * static_cast<size_t>(pl->blen) + 4 * pl->alen;
+    hvec.assign(2 * plane * R, 0);
+    auto put = [&](size_t idx, double x) {
+      uint16_t h, l;
+      if (precision == KPME_FP16X3) {
+        double vh, vl;
+        h = f16_rne(x, &vh);
+        l = f16_rne(x - vh, &vl);
+      } else {
+        h = bf16_rne(static_cast<float>(x));
+        l = bf16_rne(static_cast<float>(x - static_cast<double>(bf16_to_float(h))));
+      }
+      hvec[idx] = h;
+      hvec[idx + plane] = l;
+    };
+    for (int r = 0; r < R; ++r) {
+      const Term& t = fs.terms[order[r]];
+      const std::vector<double> ca = circulant_column(t.v[0]);
+      const std::vector<double> cb = circulant_column(t.v[1]);
+      const size_t base = 2 * plane * r;
+      for (int sh = 0; sh < 8; ++sh)
+        for (int x = 0; x < pl->blen; ++x) {
+          const int idx = ((-(x + sh)) % K2 + K2) % K2;
+          put(base + static_cast<size_t>(sh) * pl->blen + x, sB * cb[idx]);
+        }
+      for (int sh = 0; sh < 4; ++sh)
+        for (int x = 0; x < pl->alen; ++x) {
+          const int idx = ((-(x + sh)) % K1 + K1) % K1;
+          put(base + 8 * static_cast<size_t>(pl->blen) + static_cast<size_t>(sh) * pl->alen + x,
+              sA * t.omega * ca[idx]);
+        }
+    }
+    if ((2 * plane) / 8 > static_cast<size_t>(4 * 2 * K2P)) {
+      plan_free(pl);
+      delete pl;
+      return fail(KPME_ERROR_NOT_SUPPORTED, "term vectors exceed the stage-2 prefetch buffer");
+    }
+  }
+
   hipError_t e = hipSuccess;
-  const int planes = (precision == KPME_BF16X3 || precision == KPME_FP16X3) ? 2 : 1;
+  const int planes = split ? 2 : 1;
   const size_t opsz = precision == KPME_FP64 ? 8 : (precision == KPME_FP32 ? 4 : 2);
   auto upload = [&](const std::vector<double>& h, void** dst, double scale) -> hipError_t {
     const size_t n = h.size();
@@ -464,8 +526,13 @@ kpme_status kpme_plan_create(kpme_plan_t* plan, const double box[3], const int g
   const size_t nY = static_cast<size_t>(r0) * K3 * K1P * K2P;
   void* tmp = nullptr;
   do {
-    if ((e = upload(hA, pl->A, sA)) != hipSuccess) break;
-    if ((e = upload(hB, pl->B, sB)) != hipSuccess) break;
+    if (split) {
+      if ((e = plan_alloc(pl, &pl->vec, hvec.size() * 2)) != hipSuccess) break;
+      if ((e = hipMemcpy(pl->vec, hvec.data(), hvec.size() * 2, hipMemcpyHostToDevice)) != hipSuccess) break;
+    } else {
+      if ((e = upload(hA, pl->A, sA)) != hipSuccess) break;
+      if ((e = upload(hB, pl->B, sB)) != hipSuccess) break;
+    }
     if ((e = upload(hC, pl->C, sC)) != hipSuccess) break;
     for (int k = 0; k < planes; ++k)
       if ((e = plan_alloc(pl, &pl->Y[k], nY * opsz)) != hipSuccess) break;
@@ -500,6 +567,15 @@ kpme_status kpme_plan_create(kpme_plan_t* plan, const double box[3], const int g
     bn.nbr = static_cast<int*>(tmp);
     if ((e = hipMemcpy(tmp, hnbr.data(), hnbr.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess) break;
     if ((e = plan_alloc(pl, &bn.sorted, nmax * 4 * es)) != hipSuccess) break;
+    if ((e = hipMemset(bn.count, 0, nb1 * sizeof(int))) != hipSuccess) break;
+    if ((e = plan_alloc(pl, &tmp, 4 * static_cast<size_t>(bg.nbricks) * sizeof(double))) != hipSuccess) break;
+    pl->part2 = static_cast<double*>(tmp);  // two (sum, max) sets: forward, adjoint
+    pl->gather_blocks = static_cast<int>((max_particles + 255) / 256);
+    if ((e = plan_alloc(pl, &tmp, 3 * static_cast<size_t>(pl->gather_blocks) * sizeof(double))) != hipSuccess) break;
+    pl->part3 = static_cast<double*>(tmp);
+    if ((e = plan_alloc(pl, &pl->Q2g, G * es)) != hipSuccess) break;
+    if ((e = plan_alloc(pl, &pl->Psig, G * es)) != hipSuccess) break;
+    if ((e = plan_alloc(pl, &pl->sorted2, nmax * 4 * es)) != hipSuccess) break;
     e = hipDeviceSynchronize();
   } while (false);
   if (e != hipSuccess) {
@@ -551,11 +627,17 @@ kpme_status do_spread(kpme_plan_t plan, int64_t n, const void* pos, const void* 
                       hipStream_t st) {
   StageTimer tm(plan, KPME_STAGE_SPREAD, st);
   hipError_t e = launch_bin(plan->prec, plan->geom(), plan->bins, n, pos, q, st);
-  if (e == hipSuccess) e = launch_spread_binned(plan->prec, plan->geom(), plan->bins, grid, st);
+  if (e == hipSuccess)
+    e = launch_spread_binned(plan->prec, plan->geom(), plan->bins, grid, plan->part2, st);
   return from_hip(e, "spread");
 }
 
-kpme_status do_skp(kpme_plan_t plan, const void* in, void* out, hipStream_t st) {
+// sum_ready: the spread has already left (sum, scale) of `in` in scalars[0..1].
+kpme_status do_skp(kpme_plan_t plan, const void* in, void* out, hipStream_t st,
+                   bool sum_ready = false, double* scalars = nullptr,
+                   const double* part2 = nullptr) {
+  if (!scalars) scalars = plan->scalars;
+  if (!part2) part2 = plan->part2;
   SkpArgs a;
   a.prec = plan->prec;
   for (int j = 0; j < 3; ++j) a.K[j] = plan->K[j];
@@ -564,10 +646,13 @@ kpme_status do_skp(kpme_plan_t plan, const void* in, void* out, hipStream_t st) 
   a.Q = in; a.Phi = out;
   for (int k = 0; k < 2; ++k) { a.A[k] = plan->A[k]; a.B[k] = plan->B[k]; a.C[k] = plan->C[k]; a.Y[k] = plan->Y[k]; }
   a.Phi_part = plan->Phi_part;
+  a.vec = plan->vec;
+  a.blen = plan->blen;
+  a.alen = plan->alen;
   a.term_group = plan->term_group;
   a.part_begin = plan->part_begin;
   a.scratch = plan->scratch;
-  a.sumQ = plan->scalars;
+  a.sumQ = scalars;
   a.c0 = plan->zero_mode;
   a.sy = plan->sy;
   a.st = plan->st;
@@ -575,7 +660,8 @@ kpme_status do_skp(kpme_plan_t plan, const void* in, void* out, hipStream_t st) 
   hipError_t e;
   {
     StageTimer tm(plan, KPME_STAGE_GRID_SUM, st);
-    e = launch_skp_sum(a, st);
+    e = sum_ready ? launch_sum_final(part2, plan->bins.geom.nbricks, scalars, st)
+                  : launch_skp_sum(a, st);
   }
   if (e == hipSuccess) {
     StageTimer tm(plan, KPME_STAGE_SKP1, st);
@@ -658,16 +744,21 @@ kpme_status kpme_evaluate(kpme_plan_t plan, int64_t n, const void* pos, const vo
   if (n > 0 && (!pos || !q)) return fail(KPME_ERROR_INVALID_VALUE, "pos and q must not be NULL");
   hipStream_t st = static_cast<hipStream_t>(stream);
   if ((s = do_spread(plan, n, pos, q, plan->Qg, st)) != KPME_SUCCESS) return s;
-  if ((s = do_skp(plan, plan->Qg, plan->Phig, st)) != KPME_SUCCESS) return s;
-  void* potp = pot ? pot : (energy4 ? plan->pot : nullptr);
-  if (potp || force) {
-    // the particles are still binned from the spread: gather in binned order
+  if ((s = do_skp(plan, plan->Qg, plan->Phig, st, true)) != KPME_SUCCESS) return s;
+  const int nblk = static_cast<int>((n + 255) / 256);
+  if (pot || force || energy4) {
+    // the particles are still binned from the spread: gather in binned order,
+    // with the energy partial sums of each workgroup
     StageTimer tm(plan, KPME_STAGE_GATHER, st);
     hipError_t e = launch_gather_binned(plan->prec, plan->geom(), plan->bins, n, plan->Phig,
-                                        potp, force, st);
+                                        pot, force, energy4 ? plan->part3 : nullptr, st);
     if ((s = from_hip(e, "gather")) != KPME_SUCCESS) return s;
   }
-  if (energy4) return do_energy(plan, n, q, potp, energy4, st);
+  if (energy4) {
+    StageTimer tm(plan, KPME_STAGE_ENERGY, st);
+    const double V = plan->box[0] * plan->box[1] * plan->box[2];
+    return from_hip(launch_energy_final(plan->part3, nblk, plan->beta, V, energy4, st), "energy");
+  }
   return KPME_SUCCESS;
 }
 
@@ -717,13 +808,41 @@ kpme_status kpme_plan_profile_read(kpme_plan_t plan, double* total_ms, int64_t* 
 }
 
 kpme_status kpme_evaluate_backward(kpme_plan_t plan, int64_t n, const void* pos, const void* q,
-                                   double g_energy, const void* g_pot, void* grad_pos,
+                                   const double* g_energy, const void* g_pot, void* grad_pos,
                                    void* grad_q, void* stream) {
-  (void)n; (void)pos; (void)q; (void)g_energy; (void)g_pot; (void)grad_pos; (void)grad_q;
-  (void)stream;
   kpme_status s = check_plan(plan);
   if (s != KPME_SUCCESS) return s;
-  return fail(KPME_ERROR_NOT_SUPPORTED, "backward is not available in this build");
+  if ((s = check_n(plan, n)) != KPME_SUCCESS) return s;
+  if (n > 0 && (!pos || !q)) return fail(KPME_ERROR_INVALID_VALUE, "pos and q must not be NULL");
+  if (!grad_pos && !grad_q) return KPME_SUCCESS;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  // Phi = Theta S q (the forward potential grid)
+  if ((s = do_spread(plan, n, pos, q, plan->Qg, st)) != KPME_SUCCESS) return s;
+  if ((s = do_skp(plan, plan->Qg, plan->Phig, st, true)) != KPME_SUCCESS) return s;
+  // Psi = Theta S g_pot, spread from the same bins with g_pot as the charges
+  const void* psi = nullptr;
+  double* scal2 = plan->scalars + 4;
+  double* part2b = plan->part2 + 2 * static_cast<size_t>(plan->bins.geom.nbricks);
+  if (g_pot) {
+    hipError_t e;
+    {
+      StageTimer tm(plan, KPME_STAGE_SPREAD, st);
+      e = launch_resort_charges(plan->prec, plan->bins, n, g_pot, plan->sorted2, st);
+      if (e == hipSuccess)
+        e = launch_spread_binned(plan->prec, plan->geom(), plan->bins, plan->Q2g, part2b, st,
+                                 plan->sorted2);
+    }
+    if ((s = from_hip(e, "adjoint spread")) != KPME_SUCCESS) return s;
+    if ((s = do_skp(plan, plan->Q2g, plan->Psig, st, true, scal2, part2b)) != KPME_SUCCESS)
+      return s;
+    psi = plan->Psig;
+  }
+  StageTimer tm(plan, KPME_STAGE_GATHER, st);
+  const double V = plan->box[0] * plan->box[1] * plan->box[2];
+  return from_hip(launch_gather_backward(plan->prec, plan->geom(), plan->bins, n, plan->Phig,
+                                         psi, g_energy, g_pot, plan->scalars, plan->beta, V,
+                                         grad_pos, grad_q, st),
+                  "adjoint gather");
 }
 
 kpme_status kpme_batch_create(kpme_batch_t* batch, int count, const double* box3,

@@ -154,13 +154,8 @@ __global__ __launch_bounds__(256) void gather_direct(long n, const T* __restrict
 // base index floor(u) (brick edge E_j, NB_j = ceil(K_j / E_j) bricks per axis).
 
 template <typename T>
-__global__ __launch_bounds__(256) void bin_count(long n, const T* __restrict__ pos,
-                                                 GridGeom g, BinGeom bg,
-                                                 int* __restrict__ brick_of,
-                                                 int* __restrict__ slot,
-                                                 int* __restrict__ count) {
-  const long i = blockIdx.x * static_cast<long>(blockDim.x) + threadIdx.x;
-  if (i >= n) return;
+__device__ __forceinline__ int brick_of_particle(const T* __restrict__ pos, long i,
+                                                 const GridGeom& g, const BinGeom& bg) {
   int bid = 0;
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
@@ -168,13 +163,69 @@ __global__ __launch_bounds__(256) void bin_count(long n, const T* __restrict__ p
     (void)scaled(pos[3 * i + j], g.L[j], g.K[j], base);
     bid = bid * bg.nb[j] + base / bg.edge[j];
   }
+  return bid;
+}
+
+// Histogram with a per-workgroup LDS copy (up to kLdsHist bricks): each
+// workgroup ranks its particles inside the bricks in LDS, then reserves one
+// range per brick with a single global atomic.  count[] must be zero on entry.
+constexpr int kBinPer = 8;        // particles per thread
+constexpr int kLdsHist = 8192;    // bricks handled with an LDS histogram
+
+template <typename T>
+__global__ __launch_bounds__(256) void bin_count_lds(long n, const T* __restrict__ pos,
+                                                     GridGeom g, BinGeom bg,
+                                                     int* __restrict__ brick_of,
+                                                     int* __restrict__ slot,
+                                                     int* __restrict__ count) {
+  __shared__ int hist[kLdsHist];
+  const int nb = bg.nbricks;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) hist[b] = 0;
+  __syncthreads();
+  const long base = static_cast<long>(blockIdx.x) * blockDim.x * kBinPer;
+  int bid[kBinPer], loc[kBinPer];
+#pragma unroll
+  for (int k = 0; k < kBinPer; ++k) {
+    const long i = base + static_cast<long>(k) * blockDim.x + threadIdx.x;
+    bid[k] = -1;
+    if (i < n) {
+      bid[k] = brick_of_particle(pos, i, g, bg);
+      loc[k] = atomicAdd(&hist[bid[k]], 1);
+    }
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+    const int c = hist[b];
+    hist[b] = c ? atomicAdd(&count[b], c) : 0;  // hist now holds this block's base
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kBinPer; ++k) {
+    const long i = base + static_cast<long>(k) * blockDim.x + threadIdx.x;
+    if (bid[k] >= 0) {
+      brick_of[i] = bid[k];
+      slot[i] = hist[bid[k]] + loc[k];
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void bin_count(long n, const T* __restrict__ pos,
+                                                 GridGeom g, BinGeom bg,
+                                                 int* __restrict__ brick_of,
+                                                 int* __restrict__ slot,
+                                                 int* __restrict__ count) {
+  const long i = blockIdx.x * static_cast<long>(blockDim.x) + threadIdx.x;
+  if (i >= n) return;
+  const int bid = brick_of_particle(pos, i, g, bg);
   brick_of[i] = bid;
   slot[i] = atomicAdd(&count[bid], 1);
 }
 
 // Exclusive scan of the brick counts in one workgroup of 1024 threads:
-// offset[b] = sum_{c < b} count[c], offset[nbricks] = n.
-__global__ __launch_bounds__(1024) void bin_scan(const int* __restrict__ count, int nbricks,
+// offset[b] = sum_{c < b} count[c], offset[nbricks] = n; count[] is reset to
+// zero for the next binning.
+__global__ __launch_bounds__(1024) void bin_scan(int* __restrict__ count, int nbricks,
                                                  int* __restrict__ offset) {
   __shared__ int part[1024];
   const int t = threadIdx.x;
@@ -194,6 +245,7 @@ __global__ __launch_bounds__(1024) void bin_scan(const int* __restrict__ count, 
   for (int b = b0; b < b1; ++b) {
     offset[b] = run;
     run += count[b];
+    count[b] = 0;
   }
   if (t == 1023) offset[nbricks] = part[1023];
 }
@@ -218,17 +270,25 @@ __global__ __launch_bounds__(256) void bin_scatter(long n, const T* __restrict__
 
 // Owner-computes spread: one workgroup per grid brick.  It visits the
 // particles binned in the home bricks whose stencils reach it (per-axis
-// lists nbr[axis][brick] = {count, b0, b1, ...}), adds the stencil points that
-// fall inside its brick into an LDS tile with LDS atomics, and stores the
-// tile: every grid value is written exactly once, with no global atomics.
+// lists nbr[axis][brick] = {count, b0, b1, ...}, at most 4^3 combinations,
+// flattened into one index range so that every thread stays busy), adds the
+// stencil points that fall inside its brick into an LDS tile with LDS
+// atomics, and stores the tile: every grid value is written exactly once,
+// with no global atomics.  It also writes the tile's FP64 sum and largest
+// magnitude (part2[brick] = {sum, max}) for the correction and the FP16X3
+// grid scale.  The tile accumulates in FP64 for every precision (the LDS FP64
+// add is also the faster one on gfx950).
 template <typename T, int P>
 __global__ __launch_bounds__(256) void spread_brick(const T* __restrict__ sorted,
                                                     const int* __restrict__ offset,
                                                     const int* __restrict__ nbr,
-                                                    T* __restrict__ grid, GridGeom g,
+                                                    T* __restrict__ grid,
+                                                    double* __restrict__ part2, GridGeom g,
                                                     BinGeom bg) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
-  T* tile = reinterpret_cast<T*>(smem);
+  double* tile = reinterpret_cast<double*>(smem);
+  __shared__ int hstart[64], hpre[65];
+  __shared__ double red[256], mx[256];
   const int E0 = bg.edge[0], E1 = bg.edge[1], E2 = bg.edge[2];
   int own[3], rest = blockIdx.x;
   own[2] = rest % bg.nb[2]; rest /= bg.nb[2];
@@ -241,63 +301,191 @@ __global__ __launch_bounds__(256) void spread_brick(const T* __restrict__ sorted
     ext[j] = min(bg.edge[j], g.K[j] - lo[j]);
   }
   const int ntile = E0 * E1 * E2;
-  for (int e = threadIdx.x; e < ntile; e += blockDim.x) tile[e] = T(0);
-  __syncthreads();
+  for (int e = threadIdx.x; e < ntile; e += blockDim.x) tile[e] = 0.0;
   const int* n0 = nbr + kNbrRec * (0 * bg.nbmax + own[0]);
   const int* n1 = nbr + kNbrRec * (1 * bg.nbmax + own[1]);
   const int* n2 = nbr + kNbrRec * (2 * bg.nbmax + own[2]);
-  for (int a0 = 0; a0 < n0[0]; ++a0)
-    for (int a1 = 0; a1 < n1[0]; ++a1)
-      for (int a2 = 0; a2 < n2[0]; ++a2) {
-        const int hb = (n0[1 + a0] * bg.nb[1] + n1[1 + a1]) * bg.nb[2] + n2[1 + a2];
-        const int pb = offset[hb], pe = offset[hb + 1];
-        for (int i = pb + threadIdx.x; i < pe; i += blockDim.x) {
-          T w[3][P], dw[P];
-          int d[3][P];
-#pragma unroll
-          for (int j = 0; j < 3; ++j) {
-            int base;
-            const T f = scaled(sorted[4L * i + j], g.L[j], g.K[j], base);
-            bspline<T, P>(f, w[j], dw);
-#pragma unroll
-            for (int t = 0; t < P; ++t) {
-              int k = base - t;
-              if (k < 0) k += g.K[j];
-              const int dd = k - lo[j];
-              d[j][t] = (dd >= 0 && dd < ext[j]) ? dd : -1;
-            }
-          }
-          const T qi = sorted[4L * i + 3];
-          for (int a = 0; a < P; ++a) {
-            if (d[0][a] < 0) continue;
-            const T wa = qi * w[0][a];
-            for (int b = 0; b < P; ++b) {
-              if (d[1][b] < 0) continue;
-              const T wab = wa * w[1][b];
-              T* row = tile + (d[0][a] * E1 + d[1][b]) * E2;
-#pragma unroll
-              for (int c = 0; c < P; ++c)
-                if (d[2][c] >= 0) atomicAdd(&row[d[2][c]], wab * w[2][c]);
-            }
-          }
-        }
-      }
+  const int nh = n0[0] * n1[0] * n2[0];
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int c = 0; c < nh; ++c) {
+      const int a2 = c % n2[0], a1 = (c / n2[0]) % n1[0], a0 = c / (n1[0] * n2[0]);
+      const int hb = (n0[1 + a0] * bg.nb[1] + n1[1 + a1]) * bg.nb[2] + n2[1 + a2];
+      hstart[c] = offset[hb];
+      hpre[c] = acc;
+      acc += offset[hb + 1] - offset[hb];
+    }
+    hpre[nh] = acc;
+  }
   __syncthreads();
+  const int total = hpre[nh];
+  for (int v = threadIdx.x; v < total; v += blockDim.x) {
+    int c = 0;
+    while (hpre[c + 1] <= v) ++c;
+    const long i = hstart[c] + (v - hpre[c]);
+    T w[3][P], dw[P];
+    int d[3][P];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      int base;
+      const T f = scaled(sorted[4 * i + j], g.L[j], g.K[j], base);
+      bspline<T, P>(f, w[j], dw);
+#pragma unroll
+      for (int t = 0; t < P; ++t) {
+        int k = base - t;
+        if (k < 0) k += g.K[j];
+        const int dd = k - lo[j];
+        d[j][t] = (dd >= 0 && dd < ext[j]) ? dd : -1;
+      }
+    }
+    const T qi = sorted[4 * i + 3];
+    for (int a = 0; a < P; ++a) {
+      if (d[0][a] < 0) continue;
+      const T wa = qi * w[0][a];
+      for (int b = 0; b < P; ++b) {
+        if (d[1][b] < 0) continue;
+        const T wab = wa * w[1][b];
+        double* row = tile + (d[0][a] * E1 + d[1][b]) * E2;
+#pragma unroll
+        for (int cc = 0; cc < P; ++cc)
+          if (d[2][cc] >= 0) atomicAdd(&row[d[2][cc]], static_cast<double>(wab * w[2][cc]));
+      }
+    }
+  }
+  __syncthreads();
+  double s = 0.0, m = 0.0;
   for (int e = threadIdx.x; e < ntile; e += blockDim.x) {
     const int c = e % E2, b = (e / E2) % E1, a = e / (E1 * E2);
-    if (a < ext[0] && b < ext[1] && c < ext[2])
-      grid[(static_cast<long>(lo[0] + a) * g.K[1] + lo[1] + b) * g.K[2] + lo[2] + c] = tile[e];
+    if (a < ext[0] && b < ext[1] && c < ext[2]) {
+      const T v = static_cast<T>(tile[e]);
+      grid[(static_cast<long>(lo[0] + a) * g.K[1] + lo[1] + b) * g.K[2] + lo[2] + c] = v;
+      s += static_cast<double>(v);
+      m = fmax(m, fabs(static_cast<double>(v)));
+    }
+  }
+  red[threadIdx.x] = s;
+  mx[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      red[threadIdx.x] += red[threadIdx.x + w];
+      mx[threadIdx.x] = fmax(mx[threadIdx.x], mx[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part2[2 * blockIdx.x] = red[0];
+    part2[2 * blockIdx.x + 1] = mx[0];
   }
 }
 
 // Gather in binned order (neighbouring threads read neighbouring grid
 // values); results are written back to the caller's order through perm.
+// Each workgroup also writes its FP64 partial sums (q pot, q, q^2) to
+// part3[block] for the energy reduction.
 template <typename T, int P>
 __global__ __launch_bounds__(256) void gather_sorted(long n, const T* __restrict__ sorted,
                                                      const int* __restrict__ perm,
                                                      const T* __restrict__ grid,
                                                      T* __restrict__ pot,
-                                                     T* __restrict__ force, GridGeom g) {
+                                                     T* __restrict__ force,
+                                                     double* __restrict__ part3, GridGeom g) {
+  __shared__ double red[3][256];
+  const long s = blockIdx.x * static_cast<long>(blockDim.x) + threadIdx.x;
+  double e0 = 0, e1 = 0, e2 = 0;
+  if (s < n) {
+    T w[3][P], dw[3][P];
+    int base[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const T f = scaled(sorted[4 * s + j], g.L[j], g.K[j], base[j]);
+      bspline<T, P>(f, w[j], dw[j]);
+    }
+    const int K1 = g.K[0], K2 = g.K[1], K3 = g.K[2];
+    int kc[P];
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+      kc[c] = base[2] - c;
+      if (kc[c] < 0) kc[c] += K3;
+    }
+    T phi = 0, g0 = 0, g1 = 0, g2 = 0;
+    for (int a = 0; a < P; ++a) {
+      int ka = base[0] - a;
+      if (ka < 0) ka += K1;
+      T sa = 0, sa1 = 0, sa2 = 0;
+      for (int b = 0; b < P; ++b) {
+        int kb = base[1] - b;
+        if (kb < 0) kb += K2;
+        const T* row = grid + (static_cast<long>(ka) * K2 + kb) * K3;
+        T sv = 0, s2 = 0;
+#pragma unroll
+        for (int c = 0; c < P; ++c) {
+          const T v = row[kc[c]];
+          sv += w[2][c] * v;
+          s2 += dw[2][c] * v;
+        }
+        sa += w[1][b] * sv;
+        sa1 += dw[1][b] * sv;
+        sa2 += w[1][b] * s2;
+      }
+      phi += w[0][a] * sa;
+      g0 += dw[0][a] * sa;
+      g1 += w[0][a] * sa1;
+      g2 += w[0][a] * sa2;
+    }
+    const long i = perm[s];
+    const T qi = sorted[4 * s + 3];
+    if (pot) pot[i] = phi;
+    if (force) {
+      force[3 * i + 0] = -qi * g0 * static_cast<T>(K1 / g.L[0]);
+      force[3 * i + 1] = -qi * g1 * static_cast<T>(K2 / g.L[1]);
+      force[3 * i + 2] = -qi * g2 * static_cast<T>(K3 / g.L[2]);
+    }
+    const double qd = static_cast<double>(qi);
+    e0 = qd * static_cast<double>(phi);
+    e1 = qd;
+    e2 = qd * qd;
+  }
+  if (part3) {
+    red[0][threadIdx.x] = e0;
+    red[1][threadIdx.x] = e1;
+    red[2][threadIdx.x] = e2;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (threadIdx.x < w)
+        for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0)
+      for (int k = 0; k < 3; ++k) part3[3 * blockIdx.x + k] = red[k][0];
+  }
+}
+
+// sorted2[d] = (x, y, z, g[perm[d]]): the binned positions with a second
+// per-particle value (the adjoint's upstream potential gradient) as charge.
+template <typename T>
+__global__ __launch_bounds__(256) void resort_charges(long n, const T* __restrict__ sorted,
+                                                      const int* __restrict__ perm,
+                                                      const T* __restrict__ gval,
+                                                      T* __restrict__ sorted2) {
+  const long d = blockIdx.x * static_cast<long>(blockDim.x) + threadIdx.x;
+  if (d >= n) return;
+  sorted2[4 * d + 0] = sorted[4 * d + 0];
+  sorted2[4 * d + 1] = sorted[4 * d + 1];
+  sorted2[4 * d + 2] = sorted[4 * d + 2];
+  sorted2[4 * d + 3] = gval ? gval[perm[d]] : T(0);
+}
+
+// Adjoint gather (binned order): with Phi = Theta S q and Psi = Theta S g,
+//   grad_pos_i = grad W_i . [(gE q_i + g_i) Phi + q_i Psi]
+//   grad_q_i   = gE (W_i . Phi + self_i + neutral) + W_i . Psi
+// self_i = -2 beta q_i / sqrt(pi), neutral = -pi sum(q) / (V beta^2).
+template <typename T, int P>
+__global__ __launch_bounds__(256) void gather_backward(
+    long n, const T* __restrict__ sorted, const int* __restrict__ perm,
+    const T* __restrict__ Phi, const T* __restrict__ Psi, const double* __restrict__ g_energy,
+    const T* __restrict__ g_pot, const double* __restrict__ sumq, double beta, double volume,
+    T* __restrict__ grad_pos, T* __restrict__ grad_q, GridGeom g) {
   const long s = blockIdx.x * static_cast<long>(blockDim.x) + threadIdx.x;
   if (s >= n) return;
   T w[3][P], dw[3][P];
@@ -314,38 +502,53 @@ __global__ __launch_bounds__(256) void gather_sorted(long n, const T* __restrict
     kc[c] = base[2] - c;
     if (kc[c] < 0) kc[c] += K3;
   }
-  T phi = 0, g0 = 0, g1 = 0, g2 = 0;
+  // v[0]: W.grid, v[1..3]: derivatives along the three axes (in u units)
+  T vf[4] = {0, 0, 0, 0}, vs[4] = {0, 0, 0, 0};
   for (int a = 0; a < P; ++a) {
     int ka = base[0] - a;
     if (ka < 0) ka += K1;
-    T sa = 0, sa1 = 0, sa2 = 0;
     for (int b = 0; b < P; ++b) {
       int kb = base[1] - b;
       if (kb < 0) kb += K2;
-      const T* row = grid + (static_cast<long>(ka) * K2 + kb) * K3;
-      T sv = 0, s2 = 0;
+      const long row = (static_cast<long>(ka) * K2 + kb) * K3;
+      T sf = 0, sf2 = 0, ss = 0, ss2 = 0;
 #pragma unroll
       for (int c = 0; c < P; ++c) {
-        const T v = row[kc[c]];
-        sv += w[2][c] * v;
-        s2 += dw[2][c] * v;
+        const T x = Phi[row + kc[c]];
+        sf += w[2][c] * x;
+        sf2 += dw[2][c] * x;
+        if (Psi) {
+          const T y = Psi[row + kc[c]];
+          ss += w[2][c] * y;
+          ss2 += dw[2][c] * y;
+        }
       }
-      sa += w[1][b] * sv;
-      sa1 += dw[1][b] * sv;
-      sa2 += w[1][b] * s2;
+      const T wab = w[0][a] * w[1][b];
+      vf[0] += wab * sf;
+      vf[1] += dw[0][a] * w[1][b] * sf;
+      vf[2] += w[0][a] * dw[1][b] * sf;
+      vf[3] += wab * sf2;
+      vs[0] += wab * ss;
+      vs[1] += dw[0][a] * w[1][b] * ss;
+      vs[2] += w[0][a] * dw[1][b] * ss;
+      vs[3] += wab * ss2;
     }
-    phi += w[0][a] * sa;
-    g0 += dw[0][a] * sa;
-    g1 += w[0][a] * sa1;
-    g2 += w[0][a] * sa2;
   }
   const long i = perm[s];
-  if (pot) pot[i] = phi;
-  if (force) {
-    const T qi = sorted[4 * s + 3];
-    force[3 * i + 0] = -qi * g0 * static_cast<T>(K1 / g.L[0]);
-    force[3 * i + 1] = -qi * g1 * static_cast<T>(K2 / g.L[1]);
-    force[3 * i + 2] = -qi * g2 * static_cast<T>(K3 / g.L[2]);
+  const T qi = sorted[4 * s + 3];
+  const T ge = g_energy ? static_cast<T>(*g_energy) : T(0);
+  const T gp = g_pot ? g_pot[i] : T(0);
+  if (grad_pos) {
+    const T cf = ge * qi + gp;
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      grad_pos[3 * i + j] = (cf * vf[1 + j] + qi * vs[1 + j]) * static_cast<T>(g.K[j] / g.L[j]);
+  }
+  if (grad_q) {
+    const double pi = 3.141592653589793238462643383279502884;
+    const double self_i = -2.0 * beta * static_cast<double>(qi) / sqrt(pi);
+    const double neutral = -pi * sumq[0] / (volume * beta * beta);
+    grad_q[i] = ge * (vf[0] + static_cast<T>(self_i + neutral)) + vs[0];
   }
 }
 
@@ -476,39 +679,52 @@ hipError_t launch_gather_direct(int prec, const GridGeom& g, int64_t n, const vo
 namespace {
 
 template <typename T>
-hipError_t bin_t(const GridGeom& g, const Bins& b, int64_t n, const void* pos, const void* q,
-                 hipStream_t st) {
-  hipError_t e = launch_zero(b.count, sizeof(int) * (b.geom.nbricks + 1), st);
-  if (e != hipSuccess) return e;
-  const unsigned blocks = static_cast<unsigned>((n + 255) / 256);
-  if (n > 0)
-    hipLaunchKernelGGL((bin_count<T>), dim3(blocks), dim3(256), 0, st, static_cast<long>(n),
-                       static_cast<const T*>(pos), g, b.geom, b.brick_of, b.slot, b.count);
+hipError_t bin_t(const GridGeom& g, const Bins& b, int64_t n, const void* pos, hipStream_t st) {
+  if (n > 0) {
+    if (b.geom.nbricks <= kLdsHist) {
+      const long per = 256L * kBinPer;
+      const unsigned blocks = static_cast<unsigned>((n + per - 1) / per);
+      hipLaunchKernelGGL((bin_count_lds<T>), dim3(blocks), dim3(256), 0, st,
+                         static_cast<long>(n), static_cast<const T*>(pos), g, b.geom,
+                         b.brick_of, b.slot, b.count);
+    } else {
+      const unsigned blocks = static_cast<unsigned>((n + 255) / 256);
+      hipLaunchKernelGGL((bin_count<T>), dim3(blocks), dim3(256), 0, st, static_cast<long>(n),
+                         static_cast<const T*>(pos), g, b.geom, b.brick_of, b.slot, b.count);
+    }
+  }
   hipLaunchKernelGGL(bin_scan, dim3(1), dim3(1024), 0, st, b.count, b.geom.nbricks, b.offset);
-  if (n > 0)
-    hipLaunchKernelGGL((bin_scatter<T>), dim3(blocks), dim3(256), 0, st, static_cast<long>(n),
-                       static_cast<const T*>(pos), static_cast<const T*>(q), b.brick_of, b.slot,
-                       b.offset, static_cast<T*>(b.sorted), b.perm);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t scatter_t(const Bins& b, int64_t n, const void* pos, const void* q, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const unsigned blocks = static_cast<unsigned>((n + 255) / 256);
+  hipLaunchKernelGGL((bin_scatter<T>), dim3(blocks), dim3(256), 0, st, static_cast<long>(n),
+                     static_cast<const T*>(pos), static_cast<const T*>(q), b.brick_of, b.slot,
+                     b.offset, static_cast<T*>(b.sorted), b.perm);
   return hipGetLastError();
 }
 
 template <typename T, int P>
-hipError_t spread_brick_p(const GridGeom& g, const Bins& b, void* grid, hipStream_t st) {
-  const size_t lds = sizeof(T) * b.geom.edge[0] * b.geom.edge[1] * b.geom.edge[2];
+hipError_t spread_brick_p(const GridGeom& g, const Bins& b, const void* src, void* grid,
+                          double* part2, hipStream_t st) {
+  const size_t lds = sizeof(double) * b.geom.edge[0] * b.geom.edge[1] * b.geom.edge[2];
   hipLaunchKernelGGL((spread_brick<T, P>), dim3(b.geom.nbricks), dim3(256), lds, st,
-                     static_cast<const T*>(b.sorted), b.offset, b.nbr, static_cast<T*>(grid),
-                     g, b.geom);
+                     static_cast<const T*>(src ? src : b.sorted), b.offset, b.nbr,
+                     static_cast<T*>(grid), part2, g, b.geom);
   return hipGetLastError();
 }
 
 template <typename T, int P>
 hipError_t gather_sorted_p(const GridGeom& g, const Bins& b, int64_t n, const void* grid,
-                           void* pot, void* force, hipStream_t st) {
+                           void* pot, void* force, double* part3, hipStream_t st) {
   const unsigned blocks = static_cast<unsigned>((n + 255) / 256);
   hipLaunchKernelGGL((gather_sorted<T, P>), dim3(blocks), dim3(256), 0, st,
                      static_cast<long>(n), static_cast<const T*>(b.sorted), b.perm,
                      static_cast<const T*>(grid), static_cast<T*>(pot), static_cast<T*>(force),
-                     g);
+                     part3, g);
   return hipGetLastError();
 }
 
@@ -516,32 +732,89 @@ hipError_t gather_sorted_p(const GridGeom& g, const Bins& b, int64_t n, const vo
 
 hipError_t launch_bin(int prec, const GridGeom& g, const Bins& b, int64_t n, const void* pos,
                       const void* q, hipStream_t st) {
-  return prec == PREC_FP64 ? bin_t<double>(g, b, n, pos, q, st) : bin_t<float>(g, b, n, pos, q, st);
+  hipError_t e = prec == PREC_FP64 ? bin_t<double>(g, b, n, pos, st) : bin_t<float>(g, b, n, pos, st);
+  if (e != hipSuccess) return e;
+  return prec == PREC_FP64 ? scatter_t<double>(b, n, pos, q, st) : scatter_t<float>(b, n, pos, q, st);
 }
 
 hipError_t launch_spread_binned(int prec, const GridGeom& g, const Bins& b, void* grid,
-                                hipStream_t st) {
+                                double* part2, hipStream_t st, const void* src) {
   if (prec == PREC_FP64) {
-#define CALL(P) spread_brick_p<double, P>(g, b, grid, st)
+#define CALL(P) spread_brick_p<double, P>(g, b, src, grid, part2, st)
     KPME_ORDER_SWITCH(g.p, CALL)
 #undef CALL
   }
-#define CALL(P) spread_brick_p<float, P>(g, b, grid, st)
+#define CALL(P) spread_brick_p<float, P>(g, b, src, grid, part2, st)
   KPME_ORDER_SWITCH(g.p, CALL)
 #undef CALL
 }
 
 hipError_t launch_gather_binned(int prec, const GridGeom& g, const Bins& b, int64_t n,
-                                const void* grid, void* pot, void* force, hipStream_t st) {
+                                const void* grid, void* pot, void* force, double* part3,
+                                hipStream_t st) {
   if (n == 0) return hipSuccess;
   if (prec == PREC_FP64) {
-#define CALL(P) gather_sorted_p<double, P>(g, b, n, grid, pot, force, st)
+#define CALL(P) gather_sorted_p<double, P>(g, b, n, grid, pot, force, part3, st)
     KPME_ORDER_SWITCH(g.p, CALL)
 #undef CALL
   }
-#define CALL(P) gather_sorted_p<float, P>(g, b, n, grid, pot, force, st)
+#define CALL(P) gather_sorted_p<float, P>(g, b, n, grid, pot, force, part3, st)
   KPME_ORDER_SWITCH(g.p, CALL)
 #undef CALL
+}
+
+template <typename T, int P>
+hipError_t gather_backward_p(const GridGeom& g, const Bins& b, int64_t n, const void* Phi,
+                             const void* Psi, const double* g_energy, const void* g_pot,
+                             const double* sumq, double beta, double volume, void* grad_pos,
+                             void* grad_q, hipStream_t st) {
+  const unsigned blocks = static_cast<unsigned>((n + 255) / 256);
+  hipLaunchKernelGGL((gather_backward<T, P>), dim3(blocks), dim3(256), 0, st,
+                     static_cast<long>(n), static_cast<const T*>(b.sorted), b.perm,
+                     static_cast<const T*>(Phi), static_cast<const T*>(Psi), g_energy,
+                     static_cast<const T*>(g_pot), sumq, beta, volume,
+                     static_cast<T*>(grad_pos), static_cast<T*>(grad_q), g);
+  return hipGetLastError();
+}
+
+hipError_t launch_resort_charges(int prec, const Bins& b, int64_t n, const void* gval,
+                                 void* sorted2, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const unsigned blocks = static_cast<unsigned>((n + 255) / 256);
+  if (prec == PREC_FP64)
+    hipLaunchKernelGGL((resort_charges<double>), dim3(blocks), dim3(256), 0, st,
+                       static_cast<long>(n), static_cast<const double*>(b.sorted), b.perm,
+                       static_cast<const double*>(gval), static_cast<double*>(sorted2));
+  else
+    hipLaunchKernelGGL((resort_charges<float>), dim3(blocks), dim3(256), 0, st,
+                       static_cast<long>(n), static_cast<const float*>(b.sorted), b.perm,
+                       static_cast<const float*>(gval), static_cast<float*>(sorted2));
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_backward(int prec, const GridGeom& g, const Bins& b, int64_t n,
+                                  const void* Phi, const void* Psi, const double* g_energy,
+                                  const void* g_pot, const double* sumq, double beta,
+                                  double volume, void* grad_pos, void* grad_q,
+                                  hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  if (prec == PREC_FP64) {
+#define CALL(P) gather_backward_p<double, P>(g, b, n, Phi, Psi, g_energy, g_pot, sumq, beta, \
+                                             volume, grad_pos, grad_q, st)
+    KPME_ORDER_SWITCH(g.p, CALL)
+#undef CALL
+  }
+#define CALL(P) gather_backward_p<float, P>(g, b, n, Phi, Psi, g_energy, g_pot, sumq, beta, \
+                                            volume, grad_pos, grad_q, st)
+  KPME_ORDER_SWITCH(g.p, CALL)
+#undef CALL
+}
+
+hipError_t launch_energy_final(const double* part3, int nblocks, double beta, double volume,
+                               double* energy4, hipStream_t st) {
+  hipLaunchKernelGGL(energy_final, dim3(1), dim3(256), 0, st, part3, nblocks, beta, volume,
+                     energy4);
+  return hipGetLastError();
 }
 
 hipError_t launch_energy(int prec, int64_t n, const void* q, const void* pot, double beta,

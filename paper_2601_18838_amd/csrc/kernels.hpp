@@ -21,6 +21,8 @@ struct SkpArgs {
   int r0, R, nparts;
   const void* Q;         // grid_in  [K1][K2][K3]
   void* Phi;             // grid_out [K1][K2][K3]
+  const void* vec;       // split paths: per-term circulant vector copies (see stage 2)
+  int blen, alen;        // lengths of one B / A vector copy (halves)
   const void* A[2];      // [R][K1P][K1P], omega folded in
   const void* B[2];      // [R][K2P][K2P]
   const void* C[2];      // [r0][K3][K3P]
@@ -34,6 +36,12 @@ struct SkpArgs {
   float sy, st;          // FP16X3 powers of two applied to Y and T before splits
   double const_scale;    // FP16X3: product of the plan-time scales
 };
+
+// Lengths of one shifted copy of the reversed circulant vectors (split
+// precisions), rounded to 8 halves so that every copy starts 16-byte aligned;
+// bounds use the padded extents, which are >= K.
+inline int x3_blen(int K2P) { return (K2P + 8 + 7) / 8 * 8; }
+inline int x3_alen(int K1P) { return (K1P + 4 + 7) / 8 * 8; }
 
 hipError_t launch_skp_sum(const SkpArgs& a, hipStream_t st);
 hipError_t launch_skp_stage1(const SkpArgs& a, hipStream_t st);
@@ -79,10 +87,25 @@ hipError_t launch_gather_direct(int prec, const GridGeom& g, int64_t n, const vo
                                 hipStream_t st);
 hipError_t launch_bin(int prec, const GridGeom& g, const Bins& b, int64_t n, const void* pos,
                       const void* q, hipStream_t st);
+// part2 (2 doubles per brick): the tile's sum and largest magnitude.  src:
+// binned (x, y, z, charge) records to spread (NULL: the plan's own bins).
 hipError_t launch_spread_binned(int prec, const GridGeom& g, const Bins& b, void* grid,
-                                hipStream_t st);
+                                double* part2, hipStream_t st, const void* src = nullptr);
+// part3 (3 doubles per 256 particles, may be NULL): energy partial sums.
 hipError_t launch_gather_binned(int prec, const GridGeom& g, const Bins& b, int64_t n,
-                                const void* grid, void* pot, void* force, hipStream_t st);
+                                const void* grid, void* pot, void* force, double* part3,
+                                hipStream_t st);
+hipError_t launch_resort_charges(int prec, const Bins& b, int64_t n, const void* gval,
+                                 void* sorted2, hipStream_t st);
+hipError_t launch_gather_backward(int prec, const GridGeom& g, const Bins& b, int64_t n,
+                                  const void* Phi, const void* Psi, const double* g_energy,
+                                  const void* g_pot, const double* sumq, double beta,
+                                  double volume, void* grad_pos, void* grad_q,
+                                  hipStream_t st);
+hipError_t launch_energy_final(const double* part3, int nblocks, double beta, double volume,
+                               double* energy4, hipStream_t st);
+// Combines np (sum, max) pairs: out[0] = sum, out[1] = FP16X3 grid scale.
+hipError_t launch_sum_final(const double* part2, int np, double* out, hipStream_t st);
 hipError_t launch_energy(int prec, int64_t n, const void* q, const void* pot, double beta,
                          double volume, double* scratch, double* energy4, hipStream_t st);
 

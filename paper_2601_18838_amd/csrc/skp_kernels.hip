@@ -154,37 +154,59 @@ __global__ __launch_bounds__(256) void stage1_k4(const T* __restrict__ Q,
 
 // ----------------------------------------------------------------------------
 // Stage 2, split precision.  One workgroup = (slab s, term part); wave w owns
-// output columns [32 w, 32 w + 32).  LDS: Y slab hi/lo [K1P][K2P + 8]; A_t
-// hi/lo [K1P][K1P + 8] when it fits (A_LDS), else A_t is read from global
-// memory.  T is multiplied by st (a power of two, FP16X3) before its split.
-template <typename H, int RT, bool A_LDS>
-__global__ __launch_bounds__(512) void stage2_x3(
-    const H* __restrict__ Yhi, const H* __restrict__ Ylo,
-    const H* __restrict__ Ahi, const H* __restrict__ Alo,
-    const H* __restrict__ Bhi, const H* __restrict__ Blo,
+// output columns [32 w, 32 w + 32).
+//
+// A_t and B_t are circulant: A_t[k1][g1] = a_t((k1 - g1) mod K1).  Each term
+// is stored as shifted copies of its reversed generating vectors,
+//   Bv[s][x] = b((-(x + s)) mod K2), s < 8,  Av[s][x] = a((-(x + s)) mod K1), s < 4,
+// so that the 8 (resp. 4) consecutive factor entries an MFMA fragment needs
+// start at an aligned position of one copy: a term costs a few KB of LDS
+// instead of two K x K tiles.  The next term's vectors are fetched into
+// registers while the current term computes (double-buffered LDS).  The Y
+// slab of the current outer-SVD group stays in LDS.  T is multiplied by st
+// (a power of two, FP16X3) before its split.
+// K1P = 128 runs with at most 256 threads (K2P <= 128) so that one wave per
+// SIMD may use the full register file without spilling.
+template <typename H, int RT>
+__global__ __launch_bounds__(RT >= 8 ? 256 : 512) void stage2_x3(
+    const H* __restrict__ Yhi, const H* __restrict__ Ylo, const H* __restrict__ vec,
     const int* __restrict__ term_group, const int* __restrict__ part_begin,
-    float* __restrict__ Phi_part, int K1, int K2, int K3, int K2P, float st) {
+    float* __restrict__ Phi_part, int K1, int K2, int K3, int K2P, int blen, int alen,
+    float st) {
   typedef typename HVec<H>::v8 v8;
   typedef typename HVec<H>::v4 v4;
-  constexpr int K1P = RT * 16, CT = 2, ASTR = K1P + 8;
+  constexpr int K1P = RT * 16, CT = 2, PF = 4;  // PF: 16-byte prefetch chunks per thread
   const int YSTR = K2P + 8;
+  const int plane = 8 * blen + 4 * alen;        // halves per plane of one term
+  const int tsz = 2 * plane;                    // halves per term (hi plane, lo plane)
   extern __shared__ __attribute__((aligned(16))) char smem[];
   H* Ysh = reinterpret_cast<H*>(smem);
   H* Ysl = Ysh + K1P * YSTR;
-  H* Ash = Ysl + K1P * YSTR;
-  H* Asl = Ash + K1P * ASTR;
+  H* vbuf = Ysl + K1P * YSTR;                   // [2][tsz]
   const int s = blockIdx.x, part = blockIdx.y;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int lane = tid & 63, wave = tid >> 6, q = lane >> 4, m = lane & 15;
   const int col0 = wave * 16 * CT;
   const long slab = static_cast<long>(K1P) * K2P;
+  const int nchunk = tsz / 8;
   floatx4 acc2[RT][CT];
   for (int i = 0; i < RT; ++i)
     for (int j = 0; j < CT; ++j) acc2[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
   const int t0 = part_begin[part], t1 = part_begin[part + 1];
+  // fragment start offsets that do not depend on the term
+  //   B: y = (32 kc + 8 q - col0 - 16 j - m) mod K2;  A: y = (32 c + 4 q - 16 i - m) mod K1
+  auto md = [](int x, int k) { x %= k; return x < 0 ? x + k : x; };
+  const int yb0 = md(8 * q - col0 - m, K2);
+  const int ya0 = md(4 * q - m, K1);
+  // prologue: term t0's vectors into buffer 0
+  for (int c = tid; c < nchunk; c += nthr)
+    if (t0 < t1)
+      *reinterpret_cast<v8*>(&vbuf[8 * c]) =
+          *reinterpret_cast<const v8*>(&vec[static_cast<long>(t0) * tsz + 8 * c]);
   int cur = -1;
   for (int t = t0; t < t1; ++t) {
     const int g = term_group[t];
+    const int buf = (t - t0) & 1;
     __syncthreads();
     if (g != cur) {
       const H* yh = Yhi + (static_cast<long>(g) * K3 + s) * slab;
@@ -198,33 +220,33 @@ __global__ __launch_bounds__(512) void stage2_x3(
             *reinterpret_cast<const v8*>(&yl[static_cast<long>(r) * K2P + 8 * c8]);
       }
       cur = g;
+      __syncthreads();
     }
-    const H* ah_g = Ahi + static_cast<long>(t) * K1P * K1P;
-    const H* al_g = Alo + static_cast<long>(t) * K1P * K1P;
-    if (A_LDS) {
-      constexpr int cpr = K1P / 8;
-      for (int e = tid; e < K1P * cpr; e += nthr) {
-        const int r = e / cpr, c8 = e % cpr;
-        *reinterpret_cast<v8*>(&Ash[r * ASTR + 8 * c8]) =
-            *reinterpret_cast<const v8*>(&ah_g[r * K1P + 8 * c8]);
-        *reinterpret_cast<v8*>(&Asl[r * ASTR + 8 * c8]) =
-            *reinterpret_cast<const v8*>(&al_g[r * K1P + 8 * c8]);
+    // prefetch the next term's vectors into registers
+    v8 pre[PF];
+    if (t + 1 < t1) {
+      const H* src = vec + static_cast<long>(t + 1) * tsz;
+#pragma unroll
+      for (int k = 0; k < PF; ++k) {
+        const int c = tid + k * nthr;
+        if (c < nchunk) pre[k] = *reinterpret_cast<const v8*>(&src[8 * c]);
       }
     }
-    __syncthreads();
-    if (col0 >= K2P) continue;
+    const H* Bvh = vbuf + buf * tsz;
+    const H* Avh = Bvh + 8 * blen;
+    const H* Bvl = Bvh + plane;
+    const H* Avl = Bvl + 8 * blen;
     // GEMM1: T[g1][k2] = sum_g2 Y[g1][g2] B_t[k2][g2]
     floatx4 acc1[RT][CT];
     for (int i = 0; i < RT; ++i)
       for (int j = 0; j < CT; ++j) acc1[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    const H* bh_g = Bhi + static_cast<long>(t) * K2P * K2P;
-    const H* bl_g = Blo + static_cast<long>(t) * K2P * K2P;
     for (int kc = 0; kc < K2P / 32; ++kc) {
       v8 bh[CT], bl[CT];
       for (int j = 0; j < CT; ++j) {
-        const long off = static_cast<long>(col0 + 16 * j + m) * K2P + 32 * kc + 8 * q;
-        bh[j] = *reinterpret_cast<const v8*>(&bh_g[off]);
-        bl[j] = *reinterpret_cast<const v8*>(&bl_g[off]);
+        const int y = md(yb0 + 32 * kc - 16 * j, K2);
+        const int off = (y & 7) * blen + (y & ~7);
+        bh[j] = *reinterpret_cast<const v8*>(&Bvh[off]);
+        bl[j] = *reinterpret_cast<const v8*>(&Bvl[off]);
       }
       for (int i = 0; i < RT; ++i) {
         const int off = (16 * i + m) * YSTR + 32 * kc + 8 * q;
@@ -238,7 +260,7 @@ __global__ __launch_bounds__(512) void stage2_x3(
       }
     }
     // split T into 16-bit hi/lo, in the accumulator layout
-    v4 th[RT][CT], tl[RT][CT];
+    typename HVec<H>::v4 th[RT][CT], tl[RT][CT];
     for (int i = 0; i < RT; ++i)
       for (int j = 0; j < CT; ++j)
         for (int r = 0; r < 4; ++r) {
@@ -256,20 +278,13 @@ __global__ __launch_bounds__(512) void stage2_x3(
         tbl[j] = cat44<v4, v8>(tl[2 * c][j], tl[2 * c + 1][j]);
       }
       for (int i = 0; i < RT; ++i) {
-        v8 ah, al;
-        if (A_LDS) {
-          const int off = (16 * i + m) * ASTR + 32 * c + 4 * q;
-          ah = cat44<v4, v8>(*reinterpret_cast<const v4*>(&Ash[off]),
-                     *reinterpret_cast<const v4*>(&Ash[off + 16]));
-          al = cat44<v4, v8>(*reinterpret_cast<const v4*>(&Asl[off]),
-                     *reinterpret_cast<const v4*>(&Asl[off + 16]));
-        } else {
-          const int off = (16 * i + m) * K1P + 32 * c + 4 * q;
-          ah = cat44<v4, v8>(*reinterpret_cast<const v4*>(&ah_g[off]),
-                     *reinterpret_cast<const v4*>(&ah_g[off + 16]));
-          al = cat44<v4, v8>(*reinterpret_cast<const v4*>(&al_g[off]),
-                     *reinterpret_cast<const v4*>(&al_g[off + 16]));
-        }
+        const int y0 = md(ya0 + 32 * c - 16 * i, K1);
+        const int y1 = md(y0 + 16, K1);
+        const int o0 = (y0 & 3) * alen + (y0 & ~3), o1 = (y1 & 3) * alen + (y1 & ~3);
+        const v8 ah = cat44<v4, v8>(*reinterpret_cast<const v4*>(&Avh[o0]),
+                                    *reinterpret_cast<const v4*>(&Avh[o1]));
+        const v8 al = cat44<v4, v8>(*reinterpret_cast<const v4*>(&Avl[o0]),
+                                    *reinterpret_cast<const v4*>(&Avl[o1]));
         for (int j = 0; j < CT; ++j) {
           acc2[i][j] = mfma_h(ah, tbh[j], acc2[i][j]);
           acc2[i][j] = mfma_h(ah, tbl[j], acc2[i][j]);
@@ -277,8 +292,17 @@ __global__ __launch_bounds__(512) void stage2_x3(
         }
       }
     }
+    // publish the prefetched vectors into the other buffer (read after the
+    // barrier at the top of the next iteration)
+    if (t + 1 < t1) {
+      H* dst = vbuf + (buf ^ 1) * tsz;
+#pragma unroll
+      for (int k = 0; k < PF; ++k) {
+        const int c = tid + k * nthr;
+        if (c < nchunk) *reinterpret_cast<v8*>(&dst[8 * c]) = pre[k];
+      }
+    }
   }
-  if (col0 >= K2P) return;
   float* out = Phi_part + (static_cast<long>(part) * K3 + s) * K1 * K2;
   for (int i = 0; i < RT; ++i)
     for (int j = 0; j < CT; ++j) {
@@ -467,20 +491,20 @@ hipError_t set_lds(K kernel, size_t bytes) {
                              static_cast<int>(bytes));
 }
 
-template <typename H, int RT, bool AL>
+template <typename H, int RT>
 hipError_t launch_s2_x3(const SkpArgs& a, hipStream_t st) {
   const int K1P = RT * 16;
-  size_t lds = 2 * sizeof(H) * static_cast<size_t>(K1P) * (a.K2P + 8);
-  if (AL) lds += 2 * sizeof(H) * static_cast<size_t>(K1P) * (K1P + 8);
-  hipError_t e = set_lds(stage2_x3<H, RT, AL>, lds);
+  const size_t tsz = 2 * (8 * static_cast<size_t>(a.blen) + 4 * a.alen);
+  const size_t lds = sizeof(H) * (2 * static_cast<size_t>(K1P) * (a.K2P + 8) + 2 * tsz);
+  hipError_t e = set_lds(stage2_x3<H, RT>, lds);
   if (e != hipSuccess) return e;
   const int threads = 64 * (a.K2P / 32);
-  hipLaunchKernelGGL((stage2_x3<H, RT, AL>), dim3(a.K[2], a.nparts), dim3(threads), lds, st,
+  if (threads > (RT >= 8 ? 256 : 512)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((stage2_x3<H, RT>), dim3(a.K[2], a.nparts), dim3(threads), lds, st,
                      static_cast<const H*>(a.Y[0]), static_cast<const H*>(a.Y[1]),
-                     static_cast<const H*>(a.A[0]), static_cast<const H*>(a.A[1]),
-                     static_cast<const H*>(a.B[0]), static_cast<const H*>(a.B[1]),
-                     a.term_group, a.part_begin, static_cast<float*>(a.Phi_part),
-                     a.K[0], a.K[1], a.K[2], a.K2P, a.st);
+                     static_cast<const H*>(a.vec), a.term_group, a.part_begin,
+                     static_cast<float*>(a.Phi_part), a.K[0], a.K[1], a.K[2], a.K2P, a.blen,
+                     a.alen, a.st);
   return hipGetLastError();
 }
 
@@ -502,14 +526,8 @@ hipError_t launch_s2_k4(const SkpArgs& a, hipStream_t st) {
 template <int RT>
 hipError_t dispatch_s2(const SkpArgs& a, hipStream_t st) {
   const int K1P = RT * 16;
-  if (a.prec == PREC_BF16X3 || a.prec == PREC_FP16X3) {
-    const size_t full = 2 * sizeof(bf16) * static_cast<size_t>(K1P) * (a.K2P + 8 + K1P + 8);
-    if (a.prec == PREC_BF16X3)
-      return full <= kMaxLds ? launch_s2_x3<bf16, RT, true>(a, st)
-                             : launch_s2_x3<bf16, RT, false>(a, st);
-    return full <= kMaxLds ? launch_s2_x3<f16, RT, true>(a, st)
-                           : launch_s2_x3<f16, RT, false>(a, st);
-  }
+  if (a.prec == PREC_BF16X3) return launch_s2_x3<bf16, RT>(a, st);
+  if (a.prec == PREC_FP16X3) return launch_s2_x3<f16, RT>(a, st);
   if (a.prec == PREC_FP32) {
     const size_t full = sizeof(float) * static_cast<size_t>(K1P) * (a.K2P + 1 + K1P + 1);
     return full <= kMaxLds ? launch_s2_k4<float, RT, 2, true>(a, st)
@@ -523,7 +541,11 @@ hipError_t dispatch_s2(const SkpArgs& a, hipStream_t st) {
 }  // namespace
 
 size_t stage2_lds_bytes(int prec, int K1P, int K2P) {
-  if (prec == PREC_BF16X3 || prec == PREC_FP16X3) return 2 * sizeof(bf16) * static_cast<size_t>(K1P) * (K2P + 8);
+  if (prec == PREC_BF16X3 || prec == PREC_FP16X3) {
+    // Y slab (two planes) + two buffers of circulant vectors
+    const size_t tsz = 2 * (8 * static_cast<size_t>(x3_blen(K2P)) + 4 * x3_alen(K1P));
+    return 2 * (2 * static_cast<size_t>(K1P) * (K2P + 8) + 2 * tsz);
+  }
   if (prec == PREC_FP32) return sizeof(float) * static_cast<size_t>(K1P) * (K2P + 1);
   return sizeof(double) * static_cast<size_t>(K1P) * (K2P + 1);
 }
@@ -538,6 +560,11 @@ hipError_t launch_skp_sum(const SkpArgs& a, hipStream_t st) {
     hipLaunchKernelGGL((sum_partial<float>), dim3(kSumBlocks), dim3(256), 0, st,
                        static_cast<const float*>(a.Q), G, a.scratch);
   hipLaunchKernelGGL(sum_final, dim3(1), dim3(256), 0, st, a.scratch, kSumBlocks, a.sumQ);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_final(const double* part2, int np, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(sum_final, dim3(1), dim3(256), 0, st, part2, np, out);
   return hipGetLastError();
 }
 

@@ -52,7 +52,7 @@ _SIGNATURES = {
     "kpme_gather": [_P, _I64, _P, _P, _P, _P, _P, _P],
     "kpme_energy": [_P, _I64, _P, _P, _P, _P],
     "kpme_evaluate": [_P, _I64, _P, _P, _P, _P, _P, _P],
-    "kpme_evaluate_backward": [_P, _I64, _P, _P, _D, _P, _P, _P, _P],
+    "kpme_evaluate_backward": [_P, _I64, _P, _P, _P, _P, _P, _P, _P],
     "kpme_factors_compute": [_DP, _IP, _INT, _D, _INT, _D, _INT, _IP, _DP, _DP, _DP, _DP,
                              _IP, _DP],
     "kpme_batch_create": [ctypes.POINTER(_P), _INT, _DP, _IP, _IP, _DP, _IP, _INT,
@@ -237,15 +237,61 @@ class Plan:
         _check(lib().kpme_plan_profile_read(self._h, ms, cnt))
         return {name: (ms[i], cnt[i]) for i, name in enumerate(STAGES)}
 
-    def evaluate_backward(self, pos, q, g_energy, g_pot=None, want_pos=True, want_q=True):
+    def evaluate_backward(self, pos, q, g_energy=None, g_pot=None, want_pos=True, want_q=True):
+        """Gradients of g_energy * energy4[3] + g_pot . pot (see include/kpme.h).
+
+        g_energy: None, a Python number, or a one-element float64 device tensor."""
         import torch
         n = q.shape[0]
         self._t(pos, (n, 3)); self._t(q, (n,))
         if g_pot is not None:
             self._t(g_pot, (n,))
+        if g_energy is not None and not isinstance(g_energy, torch.Tensor):
+            g_energy = torch.tensor([float(g_energy)], dtype=torch.float64, device=self.device)
+        if g_energy is not None:
+            g_energy = g_energy.reshape(1).to(device=self.device, dtype=torch.float64).contiguous()
         gp = torch.empty((n, 3), dtype=self.dtype, device=self.device) if want_pos else None
         gq = torch.empty(n, dtype=self.dtype, device=self.device) if want_q else None
         _check(lib().kpme_evaluate_backward(self._h, n, self._p(pos), self._p(q),
-                                            float(g_energy), self._p(g_pot), self._p(gp),
+                                            self._p(g_energy), self._p(g_pot), self._p(gp),
                                             self._p(gq), _stream()))
         return gp, gq
+
+
+def _autograd_function():
+    import torch
+
+    class KPMEFunction(torch.autograd.Function):
+        """(pos, q) -> (E, pot): E = E_rec + E_self + E_neutral (float64, 0-d),
+        pot the reciprocal potentials; backward runs the library's adjoint."""
+
+        @staticmethod
+        def forward(ctx, pos, q, plan):
+            e4, pot, _ = plan.evaluate(pos.contiguous(), q.contiguous(), forces=False)
+            ctx.plan = plan
+            ctx.save_for_backward(pos, q)
+            return e4[3], pot
+
+        @staticmethod
+        def backward(ctx, g_e, g_pot):
+            pos, q = ctx.saved_tensors
+            plan = ctx.plan
+            gp, gq = plan.evaluate_backward(
+                pos.contiguous(), q.contiguous(),
+                g_energy=None if g_e is None else g_e.detach(),
+                g_pot=None if g_pot is None else g_pot.detach().to(plan.dtype).contiguous(),
+                want_pos=ctx.needs_input_grad[0], want_q=ctx.needs_input_grad[1])
+            return gp, gq, None
+
+    return KPMEFunction
+
+
+_KPME_FN = None
+
+
+def kpme_energy_and_potentials(pos, q, plan):
+    """Differentiable reciprocal evaluation: returns (E, pot); see KPMEFunction."""
+    global _KPME_FN
+    if _KPME_FN is None:
+        _KPME_FN = _autograd_function()
+    return _KPME_FN.apply(pos, q, plan)
