@@ -32,7 +32,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--precision", default="fp16x3", choices=["fp16x3", "bf16x3", "fp32"])
-    ap.add_argument("--workload", default="water_100k", choices=["water_100k", "water_1m"])
+    ap.add_argument("--workload", default="water_100k",
+                    choices=["water_100k", "water_1m", "water_200k_noncubic", "batch64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-evals", type=int, default=5)
     ap.add_argument("--mixed-only", action="store_true",
@@ -73,6 +74,61 @@ def time_steps(plan, P, Q, out, steps, warmup):
     return dt / steps, stages
 
 
+def bench_batch(args):
+    """64 independent +-1 systems in one replayed graph vs a per-system FP64 loop."""
+    import torch
+    from paper_2601_18838_amd import kpme, systems
+    batch = systems.batch_systems(count=64)
+    wls = [b[0] for b in batch]
+    n = [w.n for w in wls]
+    mixed = args.precision
+    res = {}
+    for prec in (mixed, "fp64"):
+        dt = torch.float64 if prec == "fp64" else torch.float32
+        pos = torch.tensor(np.concatenate([b[1] for b in batch]), dtype=dt, device="cuda")
+        q = torch.tensor(np.concatenate([b[2] for b in batch]), dtype=dt, device="cuda")
+        t0 = time.perf_counter()
+        if prec == mixed:
+            bp = kpme.BatchPlan([w.box for w in wls], [w.grid for w in wls],
+                                [w.order for w in wls], [w.beta for w in wls],
+                                [w.rank for w in wls], precision=prec, max_particles=n)
+            run = lambda: bp.evaluate(n, pos, q)
+        else:
+            plans = [kpme.Plan(w.box, w.grid, w.order, w.beta, rank=w.rank, precision=prec,
+                               max_particles=w.n) for w in wls]
+            offs = np.concatenate([[0], np.cumsum(n)])
+            views = [(pos[offs[k]:offs[k + 1]], q[offs[k]:offs[k + 1]]) for k in range(64)]
+
+            def run():
+                return [pl.evaluate(*v) for pl, v in zip(plans, views)]
+        t_plan = time.perf_counter() - t0
+        for _ in range(args.warmup):
+            out = run()
+        torch.cuda.synchronize()
+        steps = args.steps if prec == mixed else max(3, args.steps // 10)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            out = run()
+        torch.cuda.synchronize()
+        res[prec] = ((time.perf_counter() - t0) / steps, t_plan, out)
+    e_mixed = res[mixed][2][0][:, 0].cpu().numpy()
+    e_ref = np.array([o[0][0].item() for o in res["fp64"][2]])
+    rel = np.abs(e_mixed - e_ref) / np.abs(e_ref)
+    t = res[mixed][0]
+    out = {"metric": "batched reciprocal PME: systems/s for 64 independent systems in one graph",
+           "value": 64.0 / t, "unit": "systems/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": t * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": mixed, "data": "synthetic",
+           "config": {"workload": "batch64_pm1", "systems": 64, "N_total": int(sum(n)),
+                      "grids": sorted({str(w.grid) for w in wls}), "ranks": [6, 24]},
+           "ns_per_particle": t * 1e9 / sum(n),
+           "fp64_loop_ms": res["fp64"][0] * 1e3,
+           "speedup_vs_fp64_loop": res["fp64"][0] / t,
+           "max_rel_energy_err": float(rel.max()),
+           "plan_seconds": {mixed: res[mixed][1], "fp64": res["fp64"][1]}}
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(wl, pos, q, evals):
     """The FP64 oracle on the host cores: `evals` full evaluations."""
     from oracle import skp, spme
@@ -102,8 +158,12 @@ def main():
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
         return
+    if args.workload == "batch64":
+        bench_batch(args)
+        return
 
-    wl = systems.WATER_100K if args.workload == "water_100k" else systems.WATER_1M
+    wl = {"water_100k": systems.WATER_100K, "water_1m": systems.WATER_1M,
+          "water_200k_noncubic": systems.WATER_200K_NONCUBIC}[args.workload]
     pos, q = wl.particles()
     n = len(q)
     mixed, ref = args.precision, "fp64"

@@ -198,11 +198,19 @@ kpme_status kpme_factors_compute(const double box[3], const int grid[3],
                                  double* info3);
 
 /* Batched evaluation of independent systems (each with its own box, grid,
- * spline order and rank) in one stream-ordered sequence of persistent
- * launches.  kpme_batch_create builds one plan per system (same precision)
- * plus a descriptor table; kpme_batch_evaluate evaluates all systems:
- * pos/q/pot/force are concatenated in system order (offsets = prefix sums of
- * n[s]); energy4 receives 4 doubles per system.  n[s] <= max_particles[s]. */
+ * spline order and rank R = skp_rank[s] >= 1).  kpme_batch_create builds one
+ * plan per system (one precision for all; host arrays box3[3*count],
+ * grid3[3*count], spline_order, beta, skp_rank, max_particles), autotunes
+ * every distinct (grid, order, R, precision) class once, and assigns the
+ * systems to parallel branches by longest-processing-time on an estimated
+ * cost.  kpme_batch_evaluate records, for a new argument signature (n[] and
+ * the five pointers), every system's kpme_evaluate launch sequence into one
+ * HIP graph with parallel branches, and replays it as a single launch on
+ * `stream`; an unchanged signature only replays.  pos/q/pot/force are device
+ * arrays concatenated in system order (offsets = prefix sums of n[s]);
+ * energy4 (device) receives 4 doubles per system; pot/force/energy4 may be
+ * NULL.  n[s] <= max_particles[s] (host array).  Errors as for the single
+ * calls; creation failures name the system. */
 kpme_status kpme_batch_create(kpme_batch_t* batch, int count,
                               const double* box3, const int* grid3,
                               const int* spline_order, const double* beta,
@@ -233,6 +241,17 @@ enum {
 };
 kpme_status kpme_plan_profile(kpme_plan_t plan, int enable);
 kpme_status kpme_plan_profile_read(kpme_plan_t plan, double* total_ms, int64_t* counts);
+
+/* Project autotuner for the stage-2 work split of the Kronecker operator
+ * (the number of term ranges per k3 slab, 1..8): times every candidate on
+ * `stream` with hipEvents, keeps the fastest, and records it in a process-wide
+ * cache and, when the environment variable KPME_TUNE_CACHE names a file, on
+ * disk ("key value" lines keyed by grid, order, R, r0 and precision), which
+ * later plans of the same class read at creation.  Synchronizes the stream.
+ * The contents of the plan's internal grids are overwritten. */
+kpme_status kpme_plan_autotune(kpme_plan_t plan, void* stream);
+/* The stage-2 work split in use (-1 for an invalid handle). */
+int kpme_plan_stage2_parts(kpme_plan_t plan);
 
 const char* kpme_status_string(kpme_status s);
 const char* kpme_last_error(void);

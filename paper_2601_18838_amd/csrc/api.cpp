@@ -12,6 +12,10 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <cstdio>
+#include <fstream>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -89,7 +93,7 @@ struct kpme_plan_s {
   int p = 0, prec = 0;
   double box[3] = {0, 0, 0};
   double beta = 0;
-  int R = 0, r0 = 0, total_terms = 0, nparts = 1;
+  int R = 0, r0 = 0, total_terms = 0, nparts = 1, max_parts = 1;
   int64_t max_n = 0;
   double theta_norm = 0, trunc_err = 0, zero_mode = 0;
   float sy = 1.f, st = 1.f;   // FP16X3 powers of two for Y and T
@@ -131,6 +135,23 @@ struct kpme_plan_s {
     return g;
   }
   long grid_size() const { return static_cast<long>(K[0]) * K[1] * K[2]; }
+};
+
+constexpr int kBatchBranches = 4;  // parallel branches of the batch graph
+constexpr uint32_t kBatchMagic = 0x4b42544eu;
+
+struct kpme_batch_s {
+  uint32_t magic = kBatchMagic;
+  int device = 0;
+  std::vector<kpme_plan_t> plans;
+  std::vector<int> branch_of;          // graph branch of each system
+  hipStream_t capture = nullptr;       // stream the graph is recorded on
+  hipStream_t branch[kBatchBranches] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[kBatchBranches] = {};
+  hipGraphExec_t exec = nullptr;       // recorded graph for the last signature
+  std::vector<int64_t> sig_n;
+  const void* sig_ptr[5] = {};
 };
 
 namespace {
@@ -184,6 +205,25 @@ void plan_free(kpme_plan_s* pl) {
   pl->magic = 0;
 }
 
+void batch_free(kpme_batch_s* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  for (int k = 0; k < kBatchBranches; ++k) {
+    if (b->branch[k]) (void)hipStreamDestroy(b->branch[k]);
+    if (b->join[k]) (void)hipEventDestroy(b->join[k]);
+  }
+  if (b->capture) (void)hipStreamDestroy(b->capture);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  for (kpme_plan_t p : b->plans) {
+    (void)hipSetDevice(p->device);
+    (void)hipDeviceSynchronize();
+    plan_free(p);
+    delete p;
+  }
+  b->plans.clear();
+  b->magic = 0;
+  delete b;
+}
+
 kpme_status check_plan(kpme_plan_t plan) {
   if (!plan || plan->magic != kMagic) return fail(KPME_ERROR_INVALID_VALUE, "invalid plan handle");
   if (hipSetDevice(plan->device) != hipSuccess)
@@ -210,6 +250,49 @@ kpme_status validate_params(const double box[3], const int grid[3], int p, doubl
   if (precision < KPME_FP64 || precision > KPME_FP16X3)
     return fail(KPME_ERROR_INVALID_VALUE, "unknown precision");
   return KPME_SUCCESS;
+}
+
+constexpr int kMaxParts = 8;  // stage-2 partial-slab buffers per plan
+
+// ---- tuning cache: "key nparts" lines, in memory and in $KPME_TUNE_CACHE ----
+std::mutex g_tune_mu;
+std::map<std::string, int>* g_tune = nullptr;
+
+std::string tune_key(const kpme_plan_s* pl) {
+  char buf[160];
+  std::snprintf(buf, sizeof(buf), "s2parts_%dx%dx%d_p%d_R%d_r%d_prec%d", pl->K[0], pl->K[1],
+                pl->K[2], pl->p, pl->R, pl->r0, pl->prec);
+  return buf;
+}
+
+void tune_load_locked() {
+  if (g_tune) return;
+  g_tune = new std::map<std::string, int>();
+  const char* path = std::getenv("KPME_TUNE_CACHE");
+  if (!path) return;
+  std::ifstream in(path);
+  std::string k;
+  int v;
+  while (in >> k >> v) (*g_tune)[k] = v;
+}
+
+bool tune_lookup(const std::string& key, int* value) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_load_locked();
+  auto it = g_tune->find(key);
+  if (it == g_tune->end()) return false;
+  *value = it->second;
+  return true;
+}
+
+void tune_store(const std::string& key, int value) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_load_locked();
+  (*g_tune)[key] = value;
+  if (const char* path = std::getenv("KPME_TUNE_CACHE")) {
+    std::ofstream out(path, std::ios::app);
+    out << key << " " << value << "\n";
+  }
 }
 
 }  // namespace
@@ -332,13 +415,24 @@ kpme_status kpme_plan_create(kpme_plan_t* plan, const double box[3], const int g
   pl->R = R;
   pl->r0 = r0;
   const int K1 = grid[0], K2 = grid[1], K3 = grid[2];
-  pl->nparts = std::max(1, std::min(R, (512 + K3 - 1) / K3));
-  // tuning override: number of term ranges per slab in stage 2
-  if (const char* env = std::getenv("KPME_STAGE2_PARTS")) {
-    const int v = std::atoi(env);
-    if (v >= 1) pl->nparts = std::min(R, v);
+  // Stage-2 work split: K3 slabs x nparts term ranges.  Default: one wave of
+  // resident workgroups (two per CU; one per CU for K1P = 128 split paths,
+  // whose workgroups use a full register file); the autotuner or the tuning
+  // cache may override it, up to max_parts (the partial-slab buffers).
+  {
+    const bool split = (precision == KPME_BF16X3 || precision == KPME_FP16X3);
+    const int resident = (split && K1P == 128) ? 256 : 512;
+    pl->nparts = std::max(1, std::min(R, resident / K3));
+    pl->max_parts = std::max(pl->nparts, std::min(R, kMaxParts));
+    int cached = 0;
+    if (tune_lookup(tune_key(pl), &cached) && cached >= 1) pl->nparts = std::min(cached, pl->max_parts);
+    // tuning override: number of term ranges per slab in stage 2
+    if (const char* env = std::getenv("KPME_STAGE2_PARTS")) {
+      const int v = std::atoi(env);
+      if (v >= 1) pl->nparts = std::min(pl->max_parts, v);
+    }
   }
-  std::vector<int> pb(pl->nparts + 1);
+  std::vector<int> pb(pl->max_parts + 1, R);
   for (int p = 0; p <= pl->nparts; ++p) pb[p] = static_cast<int>((static_cast<long>(R) * p) / pl->nparts);
 
   // Circulant factors, zero padded: A_t (omega folded in), B_t, C_g.
@@ -537,7 +631,7 @@ kpme_status kpme_plan_create(kpme_plan_t* plan, const double box[3], const int g
     for (int k = 0; k < planes; ++k)
       if ((e = plan_alloc(pl, &pl->Y[k], nY * opsz)) != hipSuccess) break;
     if (e != hipSuccess) break;
-    if ((e = plan_alloc(pl, &pl->Phi_part, static_cast<size_t>(pl->nparts) * G * es)) != hipSuccess) break;
+    if ((e = plan_alloc(pl, &pl->Phi_part, static_cast<size_t>(pl->max_parts) * G * es)) != hipSuccess) break;
     if ((e = plan_alloc(pl, &tmp, R * sizeof(int))) != hipSuccess) break;
     pl->term_group = static_cast<int*>(tmp);
     if ((e = hipMemcpy(tmp, group_of.data(), R * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess) break;
@@ -693,6 +787,64 @@ kpme_status do_energy(kpme_plan_t plan, int64_t n, const void* q, const void* po
                   "energy");
 }
 
+hipError_t set_parts(kpme_plan_t plan, int np) {
+  np = std::max(1, std::min(np, plan->max_parts));
+  std::vector<int> pb(plan->max_parts + 1, plan->R);
+  for (int p = 0; p <= np; ++p) pb[p] = static_cast<int>((static_cast<long>(plan->R) * p) / np);
+  hipError_t e = hipMemcpy(plan->part_begin, pb.data(), pb.size() * sizeof(int),
+                           hipMemcpyHostToDevice);
+  if (e == hipSuccess) plan->nparts = np;
+  return e;
+}
+
+}  // namespace
+
+extern "C" kpme_status kpme_plan_autotune(kpme_plan_t plan, void* stream) {
+  kpme_status s = check_plan(plan);
+  if (s != KPME_SUCCESS) return s;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int cands[] = {1, 2, 3, 4, 5, 6, 8};
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return fail(KPME_ERROR_DEVICE, "hipEventCreate");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(KPME_ERROR_DEVICE, "hipEventCreate");
+  }
+  int best = plan->nparts;
+  float best_ms = 1e30f;
+  const bool was_on = plan->prof_on;
+  plan->prof_on = false;
+  for (int c : cands) {
+    if (c > plan->max_parts || c > plan->R) continue;
+    hipError_t e = set_parts(plan, c);
+    if (e != hipSuccess) { s = from_hip(e, "autotune"); break; }
+    for (int w = 0; w < 2 && s == KPME_SUCCESS; ++w) s = do_skp(plan, plan->Qg, plan->Phig, st);
+    (void)hipEventRecord(e0, st);
+    for (int r = 0; r < 5 && s == KPME_SUCCESS; ++r) s = do_skp(plan, plan->Qg, plan->Phig, st);
+    (void)hipEventRecord(e1, st);
+    float ms = 0.f;
+    if (s == KPME_SUCCESS && hipEventSynchronize(e1) == hipSuccess &&
+        hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms < best_ms) {
+      best_ms = ms;
+      best = c;
+    }
+    if (s != KPME_SUCCESS) break;
+  }
+  plan->prof_on = was_on;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (s != KPME_SUCCESS) return s;
+  hipError_t e = set_parts(plan, best);
+  if (e != hipSuccess) return from_hip(e, "autotune");
+  tune_store(tune_key(plan), best);
+  return KPME_SUCCESS;
+}
+
+extern "C" int kpme_plan_stage2_parts(kpme_plan_t plan) {
+  return (plan && plan->magic == kMagic) ? plan->nparts : -1;
+}
+
+namespace {
 }  // namespace
 
 kpme_status kpme_spread(kpme_plan_t plan, int64_t n, const void* pos, const void* q, void* grid,
@@ -849,22 +1001,149 @@ kpme_status kpme_batch_create(kpme_batch_t* batch, int count, const double* box3
                               const int* grid3, const int* spline_order, const double* beta,
                               const int* skp_rank, int precision,
                               const int64_t* max_particles, int device) {
-  (void)count; (void)box3; (void)grid3; (void)spline_order; (void)beta; (void)skp_rank;
-  (void)precision; (void)max_particles; (void)device;
-  if (batch) *batch = nullptr;
-  return fail(KPME_ERROR_NOT_SUPPORTED, "batched evaluation is not available in this build");
+  if (!batch) return fail(KPME_ERROR_INVALID_VALUE, "batch must not be NULL");
+  *batch = nullptr;
+  if (count < 1 || !box3 || !grid3 || !spline_order || !beta || !skp_rank || !max_particles)
+    return fail(KPME_ERROR_INVALID_VALUE, "count >= 1 and all arrays are required");
+  kpme_batch_s* b = new kpme_batch_s();
+  b->device = device;
+  for (int sidx = 0; sidx < count; ++sidx) {
+    kpme_plan_t pl = nullptr;
+    kpme_status s = kpme_plan_create(&pl, box3 + 3 * sidx, grid3 + 3 * sidx, spline_order[sidx],
+                                     beta[sidx], skp_rank[sidx], 1e-6, precision,
+                                     max_particles[sidx], device);
+    if (s != KPME_SUCCESS) {
+      const std::string msg = "system " + std::to_string(sidx) + ": " + g_last_error;
+      batch_free(b);
+      return fail(s, msg);
+    }
+    b->plans.push_back(pl);
+  }
+  // autotune each distinct class once (cached in memory and on disk)
+  std::map<std::string, int> done;
+  for (kpme_plan_t pl : b->plans) {
+    const std::string key = tune_key(pl);
+    auto it = done.find(key);
+    if (it != done.end()) {
+      if (set_parts(pl, it->second) != hipSuccess) break;
+      continue;
+    }
+    int cached = 0;
+    if (tune_lookup(key, &cached)) {
+      done[key] = pl->nparts;
+      continue;
+    }
+    kpme_status s = kpme_plan_autotune(pl, nullptr);
+    if (s != KPME_SUCCESS) {
+      batch_free(b);
+      return s;
+    }
+    done[key] = pl->nparts;
+  }
+  for (int k = 0; k < kBatchBranches; ++k) {
+    if (hipStreamCreateWithFlags(&b->branch[k], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming) != hipSuccess) {
+      batch_free(b);
+      return fail(KPME_ERROR_DEVICE, "stream/event creation failed");
+    }
+  }
+  if (hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess) {
+    batch_free(b);
+    return fail(KPME_ERROR_DEVICE, "stream/event creation failed");
+  }
+  // longest-processing-time assignment of systems to graph branches
+  std::vector<int> idx(count);
+  for (int k = 0; k < count; ++k) idx[k] = k;
+  auto cost = [&](int k) {
+    const kpme_plan_s* pl = b->plans[k];
+    const double G = static_cast<double>(pl->K[0]) * pl->K[1] * pl->K[2];
+    return G * pl->R * (pl->K[0] + pl->K[1]) * (pl->prec == KPME_FP64 ? 16.0 : 1.0) +
+           static_cast<double>(pl->max_n) * pl->p * pl->p * pl->p * 200.0;
+  };
+  std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return cost(x) > cost(y); });
+  double load[kBatchBranches] = {0};
+  b->branch_of.assign(count, 0);
+  for (int k : idx) {
+    int best = 0;
+    for (int j = 1; j < kBatchBranches; ++j)
+      if (load[j] < load[best]) best = j;
+    b->branch_of[k] = best;
+    load[best] += cost(k);
+  }
+  *batch = b;
+  return KPME_SUCCESS;
 }
 
 kpme_status kpme_batch_destroy(kpme_batch_t batch) {
-  (void)batch;
-  return fail(KPME_ERROR_INVALID_VALUE, "invalid batch handle");
+  if (!batch || batch->magic != kBatchMagic) return fail(KPME_ERROR_INVALID_VALUE, "invalid batch handle");
+  batch_free(batch);
+  return KPME_SUCCESS;
 }
 
 kpme_status kpme_batch_evaluate(kpme_batch_t batch, const int64_t* n, const void* pos,
                                 const void* q, void* pot, void* force, double* energy4,
                                 void* stream) {
-  (void)batch; (void)n; (void)pos; (void)q; (void)pot; (void)force; (void)energy4; (void)stream;
-  return fail(KPME_ERROR_INVALID_VALUE, "invalid batch handle");
+  if (!batch || batch->magic != kBatchMagic) return fail(KPME_ERROR_INVALID_VALUE, "invalid batch handle");
+  if (!n) return fail(KPME_ERROR_INVALID_VALUE, "n must not be NULL");
+  const int count = static_cast<int>(batch->plans.size());
+  int64_t total = 0;
+  for (int k = 0; k < count; ++k) {
+    if (n[k] < 0 || n[k] > batch->plans[k]->max_n)
+      return fail(KPME_ERROR_INVALID_VALUE, "n[s] must be in [0, max_particles[s]]");
+    total += n[k];
+  }
+  if (total > 0 && (!pos || !q)) return fail(KPME_ERROR_INVALID_VALUE, "pos and q must not be NULL");
+  if (hipSetDevice(batch->device) != hipSuccess) return fail(KPME_ERROR_DEVICE, "hipSetDevice failed");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  // the graph is recorded once per argument signature and replayed afterwards
+  std::vector<int64_t> sig(n, n + count);
+  const void* ptrs[5] = {pos, q, pot, force, energy4};
+  const bool same = batch->exec && sig == batch->sig_n &&
+                    std::equal(ptrs, ptrs + 5, batch->sig_ptr);
+  if (!same) {
+    if (batch->exec) {
+      (void)hipGraphExecDestroy(batch->exec);
+      batch->exec = nullptr;
+    }
+    const size_t es = batch->plans[0]->esize();
+    hipError_t e = hipStreamBeginCapture(batch->capture, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return from_hip(e, "batch capture");
+    kpme_status s = KPME_SUCCESS;
+    (void)hipEventRecord(batch->fork, batch->capture);
+    for (int k = 0; k < kBatchBranches; ++k) (void)hipStreamWaitEvent(batch->branch[k], batch->fork, 0);
+    int64_t off = 0;
+    for (int k = 0; k < count && s == KPME_SUCCESS; ++k) {
+      const char* P = static_cast<const char*>(pos);
+      const char* Q = static_cast<const char*>(q);
+      s = kpme_evaluate(batch->plans[k], n[k], P ? P + 3 * off * es : nullptr,
+                        Q ? Q + off * es : nullptr,
+                        pot ? static_cast<char*>(pot) + off * es : nullptr,
+                        force ? static_cast<char*>(force) + 3 * off * es : nullptr,
+                        energy4 ? energy4 + 4 * k : nullptr, batch->branch[batch->branch_of[k]]);
+      off += n[k];
+    }
+    for (int k = 0; k < kBatchBranches; ++k) {
+      (void)hipEventRecord(batch->join[k], batch->branch[k]);
+      (void)hipStreamWaitEvent(batch->capture, batch->join[k], 0);
+    }
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(batch->capture, &graph);
+    if (s != KPME_SUCCESS) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return s;
+    }
+    if (e != hipSuccess) return from_hip(e, "batch capture");
+    e = hipGraphInstantiate(&batch->exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      batch->exec = nullptr;
+      return from_hip(e, "graph instantiate");
+    }
+    batch->sig_n = sig;
+    std::copy(ptrs, ptrs + 5, batch->sig_ptr);
+  }
+  return from_hip(hipGraphLaunch(batch->exec, st), "graph launch");
 }
 
 }  // extern "C"

@@ -59,6 +59,7 @@ _SIGNATURES = {
                           ctypes.POINTER(_I64), _INT],
     "kpme_batch_destroy": [_P],
     "kpme_plan_profile": [_P, _INT],
+    "kpme_plan_autotune": [_P, _P],
     "kpme_plan_profile_read": [_P, _DP, ctypes.POINTER(_I64)],
     "kpme_batch_evaluate": [_P, ctypes.POINTER(_I64), _P, _P, _P, _P, _P, _P],
 }
@@ -81,6 +82,8 @@ def lib():
         L.kpme_last_error.restype = ctypes.c_char_p
         L.kpme_device_count.argtypes = []
         L.kpme_device_count.restype = ctypes.c_int
+        L.kpme_plan_stage2_parts.argtypes = [_P]
+        L.kpme_plan_stage2_parts.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -226,6 +229,14 @@ class Plan:
                                    self._p(frc), self._p(e4), _stream()))
         return e4, pot, frc
 
+    def autotune(self):
+        """Run the library's stage-2 autotuner on the current stream; returns the split."""
+        _check(lib().kpme_plan_autotune(self._h, _stream()))
+        return self.stage2_parts()
+
+    def stage2_parts(self):
+        return lib().kpme_plan_stage2_parts(self._h)
+
     def profile(self, enable=True):
         """Switch the library's per-stage hipEvent timers on or off."""
         _check(lib().kpme_plan_profile(self._h, 1 if enable else 0))
@@ -256,6 +267,58 @@ class Plan:
                                             self._p(g_energy), self._p(g_pot), self._p(gp),
                                             self._p(gq), _stream()))
         return gp, gq
+
+
+class BatchPlan:
+    """Independent systems evaluated by one replayed HIP graph (kpme_batch_*)."""
+
+    def __init__(self, boxes, grids, orders, betas, ranks, precision="fp16x3",
+                 max_particles=None, device=0):
+        import torch
+        count = len(grids)
+        self.count = count
+        self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        self.dtype = torch.float64 if self.precision == FP64 else torch.float32
+        self.device = torch.device("cuda", device)
+        box = (ctypes.c_double * (3 * count))(*[float(x) for b in boxes for x in b])
+        grd = (ctypes.c_int * (3 * count))(*[int(x) for g in grids for x in g])
+        order = (ctypes.c_int * count)(*[int(x) for x in orders])
+        beta = (ctypes.c_double * count)(*[float(x) for x in betas])
+        rank = (ctypes.c_int * count)(*[int(x) for x in ranks])
+        nmax = (ctypes.c_int64 * count)(*[int(x) for x in max_particles])
+        self._h = _P()
+        _check(lib().kpme_batch_create(ctypes.byref(self._h), count, box, grd, order, beta,
+                                       rank, self.precision, nmax, int(device)))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                lib().kpme_batch_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    def evaluate(self, n, pos, q, pot=None, force=None, energy=None):
+        """n: per-system counts; pos (sum n, 3) and q (sum n) concatenated in order.
+        Returns (energy4 [count, 4], pot, force); pass output tensors to reuse them."""
+        import torch
+        total = int(sum(n))
+        for t, shape in ((pos, (total, 3)), (q, (total,))):
+            if not (isinstance(t, torch.Tensor) and t.device == self.device
+                    and t.dtype == self.dtype and t.is_contiguous() and tuple(t.shape) == shape):
+                raise TypeError(f"expected a contiguous {self.dtype} tensor of shape {shape}")
+        if energy is None:
+            energy = torch.empty((self.count, 4), dtype=torch.float64, device=self.device)
+        if pot is None:
+            pot = torch.empty(total, dtype=self.dtype, device=self.device)
+        if force is None:
+            force = torch.empty((total, 3), dtype=self.dtype, device=self.device)
+        nn = (ctypes.c_int64 * self.count)(*[int(x) for x in n])
+        p = lambda t: ctypes.c_void_p(t.data_ptr())
+        _check(lib().kpme_batch_evaluate(self._h, nn, p(pos), p(q), p(pot), p(force),
+                                         p(energy), _stream()))
+        return energy, pot, force
 
 
 def _autograd_function():

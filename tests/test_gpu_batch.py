@@ -1,0 +1,88 @@
+"""GPU checks of the batched evaluation (one replayed HIP graph for many
+independent systems): every system against its own single-plan evaluation,
+every graph replay against the eager result (with eager work and
+synchronisation between replays), and a small FP64 batch against the oracle.
+
+Tolerances: batch vs single plan relE <= 1e-6 and relative RMS <= 1e-5 (the
+same kernels; only the order of floating-point atomics in the spread and the
+autotuned stage-2 split differ); FP64 batch vs oracle 1e-10.
+"""
+import numpy as np
+import pytest
+
+from oracle import skp
+from paper_2601_18838_amd import systems
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def relrms(a, b):
+    return np.sqrt(((a - b) ** 2).sum() / (b ** 2).sum())
+
+
+def build(batch, prec):
+    from paper_2601_18838_amd import kpme
+    wls = [b[0] for b in batch]
+    bp = kpme.BatchPlan([w.box for w in wls], [w.grid for w in wls], [w.order for w in wls],
+                        [w.beta for w in wls], [w.rank for w in wls], precision=prec,
+                        max_particles=[w.n for w in wls])
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    pos = torch.tensor(np.concatenate([b[1] for b in batch]), dtype=dt, device="cuda")
+    q = torch.tensor(np.concatenate([b[2] for b in batch]), dtype=dt, device="cuda")
+    return bp, pos, q, [w.n for w in wls]
+
+
+def test_batch_matches_single_plans_and_graph_replays():
+    from paper_2601_18838_amd import kpme
+    batch = systems.batch_systems(count=10)
+    print("[batch] 10 systems fp16x3", flush=True)
+    bp, pos, q, n = build(batch, "fp16x3")
+    e0, pot0, f0 = [x.clone() for x in bp.evaluate(n, pos, q)]
+    torch.cuda.synchronize()
+    # replays, with unrelated eager work in between
+    for rep in range(3):
+        junk = torch.randn(1 << 20, device="cuda")
+        junk.mul_(2.0).sum().item()
+        e, pot, f = bp.evaluate(n, pos, q)
+        torch.cuda.synchronize()
+        np.testing.assert_allclose(e.cpu().numpy(), e0.cpu().numpy(), rtol=1e-6, atol=1e-9)
+        assert relrms(pot.double().cpu().numpy(), pot0.double().cpu().numpy()) < 1e-6
+        assert relrms(f.double().cpu().numpy(), f0.double().cpu().numpy()) < 1e-6
+    # every system against its own single-plan evaluation
+    off = 0
+    for k, (wl, p_np, q_np) in enumerate(batch):
+        pl = kpme.Plan(wl.box, wl.grid, wl.order, wl.beta, rank=wl.rank, precision="fp16x3",
+                       max_particles=wl.n)
+        es, ps, fs = pl.evaluate(pos[off:off + wl.n].contiguous(), q[off:off + wl.n].contiguous())
+        es = es.cpu().numpy()
+        assert abs(e0[k, 0].item() - es[0]) <= 1e-6 * abs(es[0]), k
+        assert relrms(pot0[off:off + wl.n].double().cpu().numpy(), ps.double().cpu().numpy()) < 1e-5
+        assert relrms(f0[off:off + wl.n].double().cpu().numpy(), fs.double().cpu().numpy()) < 1e-5
+        off += wl.n
+
+
+def test_small_fp64_batch_against_oracle():
+    print("[batch] fp64 vs oracle", flush=True)
+    cases = []
+    for seed, (box, grid, p, rank) in enumerate([((20.0,) * 3, (16, 16, 16), 4, 8),
+                                                 ((21.0, 26.0, 31.0), (20, 25, 30), 6, 12),
+                                                 ((12.0, 12.0, 24.0), (12, 12, 24), 4, 5)]):
+        pos, q = systems.uniform_pm1(400 + 100 * seed, box, 100 + seed)
+        wl = systems.Workload(f"t{seed}", box, grid, p, 0.5, rank=rank, kind="given", n=len(q))
+        cases.append((wl, pos, q))
+    bp, pos, q, n = build(cases, "fp64")
+    e4, pot, f = bp.evaluate(n, pos, q)
+    off = 0
+    for k, (wl, p_np, q_np) in enumerate(cases):
+        ref = skp.Plan(wl.box, wl.grid, wl.order, wl.beta, rank=wl.rank).evaluate(p_np, q_np)
+        assert abs(e4[k, 0].item() - ref["E_rec"]) < 1e-10 * abs(ref["E_rec"])
+        assert relrms(pot[off:off + wl.n].cpu().numpy(), ref["phi"]) < 1e-10
+        assert relrms(f[off:off + wl.n].cpu().numpy(), ref["F"]) < 1e-10
+        off += wl.n
