@@ -57,18 +57,23 @@ def copy_calibration(mib):
 
 
 def time_steps(plan, P, Q, out, steps, warmup):
+    """Wall time per evaluation over `steps` back-to-back evaluations (no
+    per-stage events in this region), then the per-stage breakdown from a
+    second, event-instrumented pass of the same length."""
     import torch
     for _ in range(warmup):
         plan.evaluate(P, Q, out=out)
-    torch.cuda.synchronize()
-    plan.profile(True)
-    plan.profile_read()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         plan.evaluate(P, Q, out=out)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    plan.profile(True)
+    plan.profile_read()
+    for _ in range(steps):
+        plan.evaluate(P, Q, out=out)
+    torch.cuda.synchronize()
     stages = plan.profile_read()
     plan.profile(False)
     return dt / steps, stages
@@ -172,6 +177,7 @@ def main():
         dt = torch.float64 if prec == "fp64" else torch.float32
         plans[prec] = kpme.Plan(wl.box, wl.grid, wl.order, wl.beta, rank=wl.rank, tol=wl.tol,
                                 precision=prec, max_particles=n)
+        plans[prec].autotune()          # the library's stage-2 work-split tuner
         tensors[prec] = (torch.tensor(pos, dtype=dt, device="cuda"),
                          torch.tensor(q, dtype=dt, device="cuda"))
         outs[prec] = (torch.empty(4, dtype=torch.float64, device="cuda"),
@@ -226,7 +232,8 @@ def main():
         "config": {"workload": wl.name, "N": n, "grid": list(wl.grid), "order": wl.order,
                    "beta": wl.beta, "box": list(wl.box), "rank": R, "r0": info["r0"],
                    "rank_rule": f"relative Frobenius tail <= {wl.tol:g}",
-                   "precision": mixed, "reference": "fp64 GPU path at equal R"},
+                   "precision": mixed, "reference": "fp64 GPU path at equal R",
+                   "stage2_parts": plans[mixed].stage2_parts()},
         "ns_per_particle": t_mixed * 1e9 / n,
         "fp64_evals_per_s": 1.0 / t_ref,
         "fp64_ns_per_particle": t_ref * 1e9 / n,

@@ -295,6 +295,13 @@ void tune_store(const std::string& key, int value) {
   }
 }
 
+// n items in np contiguous, near-equal ranges; entries past np repeat n.
+std::vector<int> split_range(int n, int np, int max_parts) {
+  std::vector<int> pb(max_parts + 1, n);
+  for (int p = 0; p <= np; ++p) pb[p] = static_cast<int>((static_cast<long>(n) * p) / np);
+  return pb;
+}
+
 }  // namespace
 
 extern "C" {
@@ -432,8 +439,7 @@ kpme_status kpme_plan_create(kpme_plan_t* plan, const double box[3], const int g
       if (v >= 1) pl->nparts = std::min(pl->max_parts, v);
     }
   }
-  std::vector<int> pb(pl->max_parts + 1, R);
-  for (int p = 0; p <= pl->nparts; ++p) pb[p] = static_cast<int>((static_cast<long>(R) * p) / pl->nparts);
+  const std::vector<int> pb = split_range(R, pl->nparts, pl->max_parts);
 
   // Circulant factors, zero padded: A_t (omega folded in), B_t, C_g.
   const size_t nA = static_cast<size_t>(R) * K1P * K1P, nB = static_cast<size_t>(R) * K2P * K2P;
@@ -496,13 +502,15 @@ kpme_status kpme_plan_create(kpme_plan_t* plan, const double box[3], const int g
 
   // Split paths: per term, [hi plane | lo plane], each plane holding 8 shifted
   // copies of the reversed axis-1 generating vector (length blen) and 4 of the
-  // reversed, omega-weighted axis-0 vector (length alen); see stage 2.
+  // reversed, omega-weighted axis-0 vector (length alen), unwrapped:
+  // copy s at x holds entry (K_P - x - s) mod K; copies s >= 1 are shifted by
+  // kX3ShiftB / kX3ShiftA halves (LDS banks); see stage 2.
   const bool split = (precision == KPME_BF16X3 || precision == KPME_FP16X3);
   std::vector<uint16_t> hvec;
   if (split) {
     pl->blen = x3_blen(K2P);
     pl->alen = x3_alen(K1P);
-    const size_t plane = 8 * static_cast<size_t>(pl->blen) + 4 * pl->alen;
+    const size_t plane = static_cast<size_t>(x3_plane(K1P, K2P));
     hvec.assign(2 * plane * R, 0);
     auto put = [&](size_t idx, double x) {
       uint16_t h, l;
@@ -524,20 +532,16 @@ kpme_status kpme_plan_create(kpme_plan_t* plan, const double box[3], const int g
       const size_t base = 2 * plane * r;
       for (int sh = 0; sh < 8; ++sh)
         for (int x = 0; x < pl->blen; ++x) {
-          const int idx = ((-(x + sh)) % K2 + K2) % K2;
-          put(base + static_cast<size_t>(sh) * pl->blen + x, sB * cb[idx]);
+          const int idx = ((K2P - x - sh) % K2 + K2) % K2;
+          put(base + static_cast<size_t>(sh) * pl->blen + (sh ? kX3ShiftB : 0) + x, sB * cb[idx]);
         }
+      const size_t abase = base + 8 * static_cast<size_t>(pl->blen) + 8;
       for (int sh = 0; sh < 4; ++sh)
         for (int x = 0; x < pl->alen; ++x) {
-          const int idx = ((-(x + sh)) % K1 + K1) % K1;
-          put(base + 8 * static_cast<size_t>(pl->blen) + static_cast<size_t>(sh) * pl->alen + x,
+          const int idx = ((K1P - x - sh) % K1 + K1) % K1;
+          put(abase + static_cast<size_t>(sh) * pl->alen + (sh ? kX3ShiftA : 0) + x,
               sA * t.omega * ca[idx]);
         }
-    }
-    if ((2 * plane) / 8 > static_cast<size_t>(4 * 2 * K2P)) {
-      plan_free(pl);
-      delete pl;
-      return fail(KPME_ERROR_NOT_SUPPORTED, "term vectors exceed the stage-2 prefetch buffer");
     }
   }
 
@@ -789,8 +793,7 @@ kpme_status do_energy(kpme_plan_t plan, int64_t n, const void* q, const void* po
 
 hipError_t set_parts(kpme_plan_t plan, int np) {
   np = std::max(1, std::min(np, plan->max_parts));
-  std::vector<int> pb(plan->max_parts + 1, plan->R);
-  for (int p = 0; p <= np; ++p) pb[p] = static_cast<int>((static_cast<long>(plan->R) * p) / np);
+  const std::vector<int> pb = split_range(plan->R, np, plan->max_parts);
   hipError_t e = hipMemcpy(plan->part_begin, pb.data(), pb.size() * sizeof(int),
                            hipMemcpyHostToDevice);
   if (e == hipSuccess) plan->nparts = np;

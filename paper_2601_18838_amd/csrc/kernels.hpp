@@ -38,10 +38,20 @@ struct SkpArgs {
 };
 
 // Lengths of one shifted copy of the reversed circulant vectors (split
-// precisions), rounded to 8 halves so that every copy starts 16-byte aligned;
-// bounds use the padded extents, which are >= K.
-inline int x3_blen(int K2P) { return (K2P + 8 + 7) / 8 * 8; }
-inline int x3_alen(int K1P) { return (K1P + 4 + 7) / 8 * 8; }
+// precisions).  The copies are unwrapped over twice the padded extent, so a
+// fragment's start needs no reduction modulo K and every fragment offset is
+// a per-lane base plus a compile-time constant.  Lengths are multiples of 8
+// halves (every copy starts 16-byte aligned) and copy s starts at bank
+// offset 4 s (B) or 8 s (A) dwords, so the lanes of one fragment read, which
+// fetch from consecutive copies, do not collide in LDS banks.
+inline int x3_blen(int K2P) { return 2 * K2P + 8; }
+inline int x3_alen(int K1P) { return 2 * K1P + 16; }
+// Copy s >= 1 of the B (A) vector starts kX3ShiftB (kX3ShiftA) halves past
+// s * blen (s * alen): with the lengths above this puts the 8 (4) copies that
+// the lanes of one fragment read on disjoint LDS bank groups.  One plane of a
+// term: [B copies | A copies], 8 * blen + 8 + 4 * alen + 8 halves.
+constexpr int kX3ShiftB = 8, kX3ShiftA = 4;
+inline int x3_plane(int K1P, int K2P) { return 8 * x3_blen(K2P) + 8 + 4 * x3_alen(K1P) + 8; }
 
 hipError_t launch_skp_sum(const SkpArgs& a, hipStream_t st);
 hipError_t launch_skp_stage1(const SkpArgs& a, hipStream_t st);

@@ -30,78 +30,132 @@ namespace {
 constexpr int S1 = 64;  // stage-1 output tile (rows and columns)
 
 // ----------------------------------------------------------------------------
-// Stage 1, split precision (BF16X3 / FP16X3).  C hi/lo: [nrows][K3P]
-// (pre-scaled); Q: fp32 [K1][K2][K3], multiplied by *qscale (a power of two,
-// FP16X3 only) before the split; the FP32 accumulator is multiplied by sy
-// (a power of two) before Y is split and stored.  Y hi/lo: [nrows][K1P*K2P].
+// Stage 1, split precision (BF16X3 / FP16X3), one wave per block: a tile of
+// 64 slab positions p = g1 K2P + g2 (rows of Q, the MFMA A operand) against
+// kS1Tiles 16-row tiles of C (rows n = (i, k3), the B operand), looping over
+// the K3P / 32 chunks of g3 with the next chunk's Q values in flight.
+// The 64 positions are dealt to the four 16-row MFMA tiles so that tile u,
+// accumulator row 4a + r, holds position 16a + 4u + r: a lane then owns 16
+// consecutive positions of one output row and stores them as 32 bytes per
+// plane.  Q is multiplied by *qscale (a power of two, FP16X3) before its
+// split, the FP32 result by sy (a power of two) before Y's split.
+// C hi/lo: [nrows][K3P] (pre-scaled, zero-padded); Y hi/lo: [nrows][slab].
+constexpr int kS1Tiles = 4;
+
 template <typename H>
-__global__ __launch_bounds__(256) void stage1_x3(
+__global__ __launch_bounds__(64) void stage1_x3(
     const float* __restrict__ Q, const H* __restrict__ Chi, const H* __restrict__ Clo,
     H* __restrict__ Yhi, H* __restrict__ Ylo, int K1, int K2, int K3, int K3P, int K2P,
     long slab, int nrows, const double* __restrict__ qscale, float sy) {
   typedef typename HVec<H>::v8 v8;
-  constexpr int KC = 32, STR = KC + 8;
-  __shared__ __attribute__((aligned(16))) H Ah[S1 * STR], Al[S1 * STR], Bh[S1 * STR], Bl[S1 * STR];
-  const long m0 = static_cast<long>(blockIdx.x) * S1;
-  const int n0 = blockIdx.y * S1;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wr = wave >> 1, wc = wave & 1, q = lane >> 4, m = lane & 15;
+  const int lane = threadIdx.x, q = lane >> 4, m = lane & 15;
+  const long p0 = static_cast<long>(blockIdx.y) * 64;
+  const int nt0 = blockIdx.x * kS1Tiles;
   const float sq = qscale ? static_cast<float>(*qscale) : 1.0f;
-  floatx4 acc[2][2];
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K3P; k0 += KC) {
-    __syncthreads();
-    for (int e = tid; e < S1 * (KC / 8); e += 256) {
-      const int r = e / (KC / 8), c8 = e % (KC / 8);
-      const int n = n0 + r;
-      v8 vh = {}, vl = {};
-      if (n < nrows) {
-        vh = *reinterpret_cast<const v8*>(&Chi[static_cast<long>(n) * K3P + k0 + 8 * c8]);
-        vl = *reinterpret_cast<const v8*>(&Clo[static_cast<long>(n) * K3P + k0 + 8 * c8]);
-      }
-      *reinterpret_cast<v8*>(&Ah[r * STR + 8 * c8]) = vh;
-      *reinterpret_cast<v8*>(&Al[r * STR + 8 * c8]) = vl;
-    }
-    for (int e = tid; e < S1 * KC; e += 256) {
-      const int r = e / KC, c = e % KC;
-      const long mp = m0 + r;
-      const int g1 = static_cast<int>(mp / K2P), g2 = static_cast<int>(mp % K2P);
-      const int k = k0 + c;
-      float x = 0.f;
-      if (g1 < K1 && g2 < K2 && k < K3) x = sq * Q[(static_cast<long>(g1) * K2 + g2) * K3 + k];
-      H h, l;
-      split_h<H>(x, h, l);
-      Bh[r * STR + c] = h;
-      Bl[r * STR + c] = l;
-    }
-    __syncthreads();
-    v8 ah[2], al[2], bh[2], bl[2];
-    for (int i = 0; i < 2; ++i) {
-      ah[i] = *reinterpret_cast<const v8*>(&Ah[(wr * 32 + 16 * i + m) * STR + 8 * q]);
-      al[i] = *reinterpret_cast<const v8*>(&Al[(wr * 32 + 16 * i + m) * STR + 8 * q]);
-      bh[i] = *reinterpret_cast<const v8*>(&Bh[(wc * 32 + 16 * i + m) * STR + 8 * q]);
-      bl[i] = *reinterpret_cast<const v8*>(&Bl[(wc * 32 + 16 * i + m) * STR + 8 * q]);
-    }
-    for (int i = 0; i < 2; ++i)
-      for (int j = 0; j < 2; ++j) {
-        acc[i][j] = mfma_h(ah[i], bh[j], acc[i][j]);
-        acc[i][j] = mfma_h(ah[i], bl[j], acc[i][j]);
-        acc[i][j] = mfma_h(al[i], bh[j], acc[i][j]);
-      }
+  const bool vec4 = (K3 & 3) == 0;  // rows 16-byte aligned, 4-float groups all in or out
+  // Q rows of this lane's A-operand rows: tile u holds p = p0 + 16 (m / 4) + 4 u + m % 4
+  const float* row[4];
+  bool valid[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const long p = p0 + 16 * (m >> 2) + 4 * u + (m & 3);
+    const int g1 = static_cast<int>(p / K2P), g2 = static_cast<int>(p % K2P);
+    valid[u] = g1 < K1 && g2 < K2;
+    row[u] = Q + (static_cast<long>(valid[u] ? g1 : 0) * K2 + (valid[u] ? g2 : 0)) * K3;
   }
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j)
-      for (int r = 0; r < 4; ++r) {
-        const int row = n0 + wr * 32 + 16 * i + 4 * q + r;
-        const long col = m0 + wc * 32 + 16 * j + m;
-        if (row < nrows && col < slab) {
-          H h, l;
-          split_h<H>(sy * acc[i][j][r], h, l);
-          Yhi[row * slab + col] = h;
-          Ylo[row * slab + col] = l;
+  auto load = [&](int kc, float (&x)[4][8]) {
+    const int k0 = 32 * kc + 8 * q;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (vec4) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int k = k0 + 4 * h;
+          float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+          if (valid[u] && k < K3) v = *reinterpret_cast<const float4*>(&row[u][k]);
+          x[u][4 * h] = v.x; x[u][4 * h + 1] = v.y; x[u][4 * h + 2] = v.z; x[u][4 * h + 3] = v.w;
         }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) x[u][e] = (valid[u] && k0 + e < K3) ? row[u][k0 + e] : 0.f;
       }
+    }
+  };
+  // C fragments (B operand) of the wave's n tiles for one K chunk
+  auto loadc = [&](int kc, v8 (&bh)[kS1Tiles], v8 (&bl)[kS1Tiles]) {
+#pragma unroll
+    for (int t = 0; t < kS1Tiles; ++t) {
+      const int n = (nt0 + t) * 16 + m;
+      bh[t] = v8{};
+      bl[t] = v8{};
+      if (n < nrows) {
+        bh[t] = *reinterpret_cast<const v8*>(&Chi[static_cast<long>(n) * K3P + 32 * kc + 8 * q]);
+        bl[t] = *reinterpret_cast<const v8*>(&Clo[static_cast<long>(n) * K3P + 32 * kc + 8 * q]);
+      }
+    }
+  };
+  floatx4 acc[kS1Tiles][4];
+#pragma unroll
+  for (int t = 0; t < kS1Tiles; ++t)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[t][u] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const int nkc = K3P / 32;
+  float x[4][8];
+  v8 bh[kS1Tiles], bl[kS1Tiles];
+  load(0, x);
+  loadc(0, bh, bl);
+  for (int kc = 0; kc < nkc; ++kc) {
+    v8 ah[4], al[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        H h, l;
+        split_h<H>(sq * x[u][e], h, l);
+        ah[u][e] = h;
+        al[u][e] = l;
+      }
+    v8 ch[kS1Tiles], cl[kS1Tiles];
+#pragma unroll
+    for (int t = 0; t < kS1Tiles; ++t) {
+      ch[t] = bh[t];
+      cl[t] = bl[t];
+    }
+    // the next chunk's operands load while this chunk's MFMAs run
+    if (kc + 1 < nkc) {
+      load(kc + 1, x);
+      loadc(kc + 1, bh, bl);
+    }
+#pragma unroll
+    for (int t = 0; t < kS1Tiles; ++t) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[t][u] = mfma_h(ah[u], ch[t], acc[t][u]);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[t][u] = mfma_h(ah[u], cl[t], acc[t][u]);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[t][u] = mfma_h(al[u], ch[t], acc[t][u]);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < kS1Tiles; ++t) {
+    const int n = (nt0 + t) * 16 + m;
+    if (n >= nrows) continue;
+    v8 yh[2], yl[2];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        H h, l;
+        split_h<H>(sy * acc[t][u][r], h, l);
+        yh[u >> 1][4 * (u & 1) + r] = h;
+        yl[u >> 1][4 * (u & 1) + r] = l;
+      }
+    const long o = static_cast<long>(n) * slab + p0 + 16 * q;
+    *reinterpret_cast<v8*>(&Yhi[o]) = yh[0];
+    *reinterpret_cast<v8*>(&Yhi[o + 8]) = yh[1];
+    *reinterpret_cast<v8*>(&Ylo[o]) = yl[0];
+    *reinterpret_cast<v8*>(&Ylo[o + 8]) = yl[1];
+  }
 }
 
 // Stage 1, FP32 / FP64 (16x16x4 MFMA).  C: [nrows][K3P]; Y: [nrows][slab].
@@ -166,19 +220,23 @@ __global__ __launch_bounds__(256) void stage1_k4(const T* __restrict__ Q,
 // slab of the current outer-SVD group stays in LDS.  T is multiplied by st
 // (a power of two, FP16X3) before its split.
 // K1P = 128 runs with at most 256 threads (K2P <= 128) so that one wave per
-// SIMD may use the full register file without spilling.
-template <typename H, int RT>
+// SIMD may use the full register file without spilling.  K1P = 16 RT and
+// K2P = 32 NKC are compile-time, so every circulant fragment offset is a
+// term-independent value computed once per thread, and the fragments of the
+// next step are loaded while the current step's MFMAs run.
+template <typename H, int RT, int NKC>
 __global__ __launch_bounds__(RT >= 8 ? 256 : 512) void stage2_x3(
     const H* __restrict__ Yhi, const H* __restrict__ Ylo, const H* __restrict__ vec,
     const int* __restrict__ term_group, const int* __restrict__ part_begin,
-    float* __restrict__ Phi_part, int K1, int K2, int K3, int K2P, int blen, int alen,
-    float st) {
+    float* __restrict__ Phi_part, int K1, int K2, int K3, float st) {
   typedef typename HVec<H>::v8 v8;
   typedef typename HVec<H>::v4 v4;
-  constexpr int K1P = RT * 16, CT = 2, PF = 4;  // PF: 16-byte prefetch chunks per thread
-  const int YSTR = K2P + 8;
-  const int plane = 8 * blen + 4 * alen;        // halves per plane of one term
-  const int tsz = 2 * plane;                    // halves per term (hi plane, lo plane)
+  constexpr int K1P = RT * 16, K2P = NKC * 32, CT = 2;
+  constexpr int blen = 2 * K2P + 8, alen = 2 * K1P + 16;  // x3_blen, x3_alen
+  constexpr int plane = 8 * blen + 8 + 4 * alen + 8;  // x3_plane: halves per plane
+  constexpr int tsz = 2 * plane;                // halves per term (hi plane, lo plane)
+  constexpr int PF = (tsz / 8 + 64 * NKC - 1) / (64 * NKC);  // 16-byte chunks per thread
+  constexpr int YSTR = K2P + 8;
   extern __shared__ __attribute__((aligned(16))) char smem[];
   H* Ysh = reinterpret_cast<H*>(smem);
   H* Ysl = Ysh + K1P * YSTR;
@@ -187,17 +245,24 @@ __global__ __launch_bounds__(RT >= 8 ? 256 : 512) void stage2_x3(
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int lane = tid & 63, wave = tid >> 6, q = lane >> 4, m = lane & 15;
   const int col0 = wave * 16 * CT;
-  const long slab = static_cast<long>(K1P) * K2P;
-  const int nchunk = tsz / 8;
+  constexpr long slab = static_cast<long>(K1P) * K2P;
+  constexpr int nchunk = tsz / 8;
   floatx4 acc2[RT][CT];
+#pragma unroll
   for (int i = 0; i < RT; ++i)
+#pragma unroll
     for (int j = 0; j < CT; ++j) acc2[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
   const int t0 = part_begin[part], t1 = part_begin[part + 1];
-  // fragment start offsets that do not depend on the term
-  //   B: y = (32 kc + 8 q - col0 - 16 j - m) mod K2;  A: y = (32 c + 4 q - 16 i - m) mod K1
-  auto md = [](int x, int k) { x %= k; return x < 0 ? x + k : x; };
-  const int yb0 = md(8 * q - col0 - m, K2);
-  const int ya0 = md(4 * q - m, K1);
+  // Fragment offsets (halves) into one plane of a term's vectors:
+  //   B fragment (kc, j): entries b((k2 - g2) mod K2) for g2 = 32 kc + 8 q + e,
+  //     k2 = col0 + 16 j + m, read from copy (y & 7) at (y & ~7) with
+  //     y = (32 kc + 8 q - col0 - 16 j - m) mod K2;
+  //   A fragment halves for a K offset 16 d: y = (4 q - m + 16 d) mod K1,
+  //     copy (y & 3) at (y & ~3); d = 2 c - i (first half), 2 c - i + 1 (second).
+  const int uB = 8 * q - col0 - m + K2P, uA = 4 * q - m + K1P;
+  const int sB = uB & 7, sA = uA & 3;
+  const int offB = sB * blen + (sB ? kX3ShiftB : 0) + (uB & ~7) - 16;
+  const int offA = 8 * blen + 8 + sA * alen + (sA ? kX3ShiftA : 0) + (uA & ~3) - 16 * (RT - 1);
   // prologue: term t0's vectors into buffer 0
   for (int c = tid; c < nchunk; c += nthr)
     if (t0 < t1)
@@ -211,7 +276,7 @@ __global__ __launch_bounds__(RT >= 8 ? 256 : 512) void stage2_x3(
     if (g != cur) {
       const H* yh = Yhi + (static_cast<long>(g) * K3 + s) * slab;
       const H* yl = Ylo + (static_cast<long>(g) * K3 + s) * slab;
-      const int cpr = K2P / 8;
+      constexpr int cpr = K2P / 8;
       for (int e = tid; e < K1P * cpr; e += nthr) {
         const int r = e / cpr, c8 = e % cpr;
         *reinterpret_cast<v8*>(&Ysh[r * YSTR + 8 * c8]) =
@@ -232,65 +297,99 @@ __global__ __launch_bounds__(RT >= 8 ? 256 : 512) void stage2_x3(
         if (c < nchunk) pre[k] = *reinterpret_cast<const v8*>(&src[8 * c]);
       }
     }
-    const H* Bvh = vbuf + buf * tsz;
-    const H* Avh = Bvh + 8 * blen;
+    const H* Bvh = vbuf + buf * tsz + offB;
     const H* Bvl = Bvh + plane;
-    const H* Avl = Bvl + 8 * blen;
+    const H* Avh = vbuf + buf * tsz + offA;
+    const H* Avl = Avh + plane;
     // GEMM1: T[g1][k2] = sum_g2 Y[g1][g2] B_t[k2][g2]
     floatx4 acc1[RT][CT];
+#pragma unroll
     for (int i = 0; i < RT; ++i)
+#pragma unroll
       for (int j = 0; j < CT; ++j) acc1[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    for (int kc = 0; kc < K2P / 32; ++kc) {
+#pragma unroll
+    for (int kc = 0; kc < NKC; ++kc) {
       v8 bh[CT], bl[CT];
+#pragma unroll
       for (int j = 0; j < CT; ++j) {
-        const int y = md(yb0 + 32 * kc - 16 * j, K2);
-        const int off = (y & 7) * blen + (y & ~7);
-        bh[j] = *reinterpret_cast<const v8*>(&Bvh[off]);
-        bl[j] = *reinterpret_cast<const v8*>(&Bvl[off]);
+        bh[j] = *reinterpret_cast<const v8*>(&Bvh[32 * kc + 16 * (1 - j)]);
+        bl[j] = *reinterpret_cast<const v8*>(&Bvl[32 * kc + 16 * (1 - j)]);
       }
+      const int yo = m * YSTR + 32 * kc + 8 * q;
+      v8 ah = *reinterpret_cast<const v8*>(&Ysh[yo]);
+      v8 al = *reinterpret_cast<const v8*>(&Ysl[yo]);
+#pragma unroll
       for (int i = 0; i < RT; ++i) {
-        const int off = (16 * i + m) * YSTR + 32 * kc + 8 * q;
-        const v8 ah = *reinterpret_cast<const v8*>(&Ysh[off]);
-        const v8 al = *reinterpret_cast<const v8*>(&Ysl[off]);
-        for (int j = 0; j < CT; ++j) {
-          acc1[i][j] = mfma_h(ah, bh[j], acc1[i][j]);
-          acc1[i][j] = mfma_h(ah, bl[j], acc1[i][j]);
-          acc1[i][j] = mfma_h(al, bh[j], acc1[i][j]);
+        v8 nh = ah, nl = al;
+        if (i + 1 < RT) {
+          nh = *reinterpret_cast<const v8*>(&Ysh[yo + 16 * (i + 1) * YSTR]);
+          nl = *reinterpret_cast<const v8*>(&Ysl[yo + 16 * (i + 1) * YSTR]);
         }
+#pragma unroll
+        for (int j = 0; j < CT; ++j) acc1[i][j] = mfma_h(ah, bh[j], acc1[i][j]);
+#pragma unroll
+        for (int j = 0; j < CT; ++j) acc1[i][j] = mfma_h(ah, bl[j], acc1[i][j]);
+#pragma unroll
+        for (int j = 0; j < CT; ++j) acc1[i][j] = mfma_h(al, bh[j], acc1[i][j]);
+        ah = nh;
+        al = nl;
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
-    // split T into 16-bit hi/lo, in the accumulator layout
-    typename HVec<H>::v4 th[RT][CT], tl[RT][CT];
-    for (int i = 0; i < RT; ++i)
-      for (int j = 0; j < CT; ++j)
+    // GEMM2: Phi[k1][k2] += sum_g1 A_t[k1][g1] T[g1][k2], K chunks of 32 rows
+    // of T taken as {32c + 4q + r} u {32c + 16 + 4q + r}, so that the chunk's
+    // two accumulator tiles are the B operand; T is multiplied by st and split
+    // into 16-bit hi/lo in place.  Because A_t is circulant, the A fragment of
+    // output row tile i and chunk c depends on d = 2c - i only: the d loop
+    // reads each distinct fragment once and applies it to every (c, i) pair.
+    v8 tbh[RT / 2][CT], tbl[RT / 2][CT];
+#pragma unroll
+    for (int c = 0; c < RT / 2; ++c)
+#pragma unroll
+      for (int j = 0; j < CT; ++j) {
+        v4 h0, l0, h1, l1;
+#pragma unroll
         for (int r = 0; r < 4; ++r) {
           H h, l;
-          split_h<H>(st * acc1[i][j][r], h, l);
-          th[i][j][r] = h;
-          tl[i][j][r] = l;
+          split_h<H>(st * acc1[2 * c][j][r], h, l);
+          h0[r] = h;
+          l0[r] = l;
+          split_h<H>(st * acc1[2 * c + 1][j][r], h, l);
+          h1[r] = h;
+          l1[r] = l;
         }
-    // GEMM2: Phi[k1][k2] += sum_g1 A_t[k1][g1] T[g1][k2], K chunks of 32 rows
-    // of T taken as {32c + 4q + r} u {32c + 16 + 4q + r}.
-    for (int c = 0; c < RT / 2; ++c) {
-      v8 tbh[CT], tbl[CT];
-      for (int j = 0; j < CT; ++j) {
-        tbh[j] = cat44<v4, v8>(th[2 * c][j], th[2 * c + 1][j]);
-        tbl[j] = cat44<v4, v8>(tl[2 * c][j], tl[2 * c + 1][j]);
+        tbh[c][j] = cat44<v4, v8>(h0, h1);
+        tbl[c][j] = cat44<v4, v8>(l0, l1);
       }
-      for (int i = 0; i < RT; ++i) {
-        const int y0 = md(ya0 + 32 * c - 16 * i, K1);
-        const int y1 = md(y0 + 16, K1);
-        const int o0 = (y0 & 3) * alen + (y0 & ~3), o1 = (y1 & 3) * alen + (y1 & ~3);
-        const v8 ah = cat44<v4, v8>(*reinterpret_cast<const v4*>(&Avh[o0]),
-                                    *reinterpret_cast<const v4*>(&Avh[o1]));
-        const v8 al = cat44<v4, v8>(*reinterpret_cast<const v4*>(&Avl[o0]),
-                                    *reinterpret_cast<const v4*>(&Avl[o1]));
-        for (int j = 0; j < CT; ++j) {
-          acc2[i][j] = mfma_h(ah, tbh[j], acc2[i][j]);
-          acc2[i][j] = mfma_h(ah, tbl[j], acc2[i][j]);
-          acc2[i][j] = mfma_h(al, tbh[j], acc2[i][j]);
+    auto afrag = [&](const H* base, int dd) {  // dd = d + RT - 1
+      return cat44<v4, v8>(*reinterpret_cast<const v4*>(&base[16 * dd]),
+                           *reinterpret_cast<const v4*>(&base[16 * dd + 16]));
+    };
+    v8 ah = afrag(Avh, 0), al = afrag(Avl, 0);
+#pragma unroll
+    for (int dd = 0; dd < 2 * RT - 2; ++dd) {
+      v8 nh = ah, nl = al;
+      if (dd + 1 < 2 * RT - 2) {
+        nh = afrag(Avh, dd + 1);
+        nl = afrag(Avl, dd + 1);
+      }
+      const int d = dd - (RT - 1);
+#pragma unroll
+      for (int pass = 0; pass < 3; ++pass)
+#pragma unroll
+        for (int c = 0; c < RT / 2; ++c) {
+          const int i = 2 * c - d;
+          if (i < 0 || i >= RT) continue;
+#pragma unroll
+          for (int j = 0; j < CT; ++j) {
+            if (pass == 0) acc2[i][j] = mfma_h(ah, tbh[c][j], acc2[i][j]);
+            if (pass == 1) acc2[i][j] = mfma_h(ah, tbl[c][j], acc2[i][j]);
+            if (pass == 2) acc2[i][j] = mfma_h(al, tbh[c][j], acc2[i][j]);
+          }
         }
-      }
+      ah = nh;
+      al = nl;
+      __builtin_amdgcn_sched_barrier(0);
     }
     // publish the prefetched vectors into the other buffer (read after the
     // barrier at the top of the next iteration)
@@ -304,9 +403,12 @@ __global__ __launch_bounds__(RT >= 8 ? 256 : 512) void stage2_x3(
     }
   }
   float* out = Phi_part + (static_cast<long>(part) * K3 + s) * K1 * K2;
+#pragma unroll
   for (int i = 0; i < RT; ++i)
+#pragma unroll
     for (int j = 0; j < CT; ++j) {
       const int k2 = col0 + 16 * j + m;
+#pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int k1 = 16 * i + 4 * q + r;
         if (k1 < K1 && k2 < K2) out[static_cast<long>(k1) * K2 + k2] = acc2[i][j][r];
@@ -491,21 +593,33 @@ hipError_t set_lds(K kernel, size_t bytes) {
                              static_cast<int>(bytes));
 }
 
-template <typename H, int RT>
+template <typename H, int RT, int NKC>
 hipError_t launch_s2_x3(const SkpArgs& a, hipStream_t st) {
   const int K1P = RT * 16;
-  const size_t tsz = 2 * (8 * static_cast<size_t>(a.blen) + 4 * a.alen);
-  const size_t lds = sizeof(H) * (2 * static_cast<size_t>(K1P) * (a.K2P + 8) + 2 * tsz);
-  hipError_t e = set_lds(stage2_x3<H, RT>, lds);
+  const size_t tsz = 2 * static_cast<size_t>(x3_plane(K1P, a.K2P));
+  const size_t lds = sizeof(H) * (2 * static_cast<size_t>(K1P) * (32 * NKC + 8) + 2 * tsz);
+  hipError_t e = set_lds(stage2_x3<H, RT, NKC>, lds);
   if (e != hipSuccess) return e;
-  const int threads = 64 * (a.K2P / 32);
-  if (threads > (RT >= 8 ? 256 : 512)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((stage2_x3<H, RT>), dim3(a.K[2], a.nparts), dim3(threads), lds, st,
+  const int threads = 64 * NKC;
+  if (threads > (RT >= 8 ? 256 : 512) || a.K2P != 32 * NKC || a.blen != x3_blen(a.K2P) ||
+      a.alen != x3_alen(K1P))
+    return hipErrorInvalidValue;
+  hipLaunchKernelGGL((stage2_x3<H, RT, NKC>), dim3(a.K[2], a.nparts), dim3(threads), lds, st,
                      static_cast<const H*>(a.Y[0]), static_cast<const H*>(a.Y[1]),
                      static_cast<const H*>(a.vec), a.term_group, a.part_begin,
-                     static_cast<float*>(a.Phi_part), a.K[0], a.K[1], a.K[2], a.K2P, a.blen,
-                     a.alen, a.st);
+                     static_cast<float*>(a.Phi_part), a.K[0], a.K[1], a.K[2], a.st);
   return hipGetLastError();
+}
+
+template <typename H, int RT>
+hipError_t launch_s2_x3(const SkpArgs& a, hipStream_t st) {
+  switch (a.K2P) {
+    case 32: return launch_s2_x3<H, RT, 1>(a, st);
+    case 64: return launch_s2_x3<H, RT, 2>(a, st);
+    case 96: return launch_s2_x3<H, RT, 3>(a, st);
+    case 128: return launch_s2_x3<H, RT, 4>(a, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <typename T, int RT, int CT, bool AL>
@@ -543,7 +657,7 @@ hipError_t dispatch_s2(const SkpArgs& a, hipStream_t st) {
 size_t stage2_lds_bytes(int prec, int K1P, int K2P) {
   if (prec == PREC_BF16X3 || prec == PREC_FP16X3) {
     // Y slab (two planes) + two buffers of circulant vectors
-    const size_t tsz = 2 * (8 * static_cast<size_t>(x3_blen(K2P)) + 4 * x3_alen(K1P));
+    const size_t tsz = 2 * static_cast<size_t>(x3_plane(K1P, K2P));
     return 2 * (2 * static_cast<size_t>(K1P) * (K2P + 8) + 2 * tsz);
   }
   if (prec == PREC_FP32) return sizeof(float) * static_cast<size_t>(K1P) * (K2P + 1);
@@ -568,21 +682,26 @@ hipError_t launch_sum_final(const double* part2, int np, double* out, hipStream_
   return hipGetLastError();
 }
 
+template <typename H>
+hipError_t launch_s1_x3(const SkpArgs& a, const double* qscale, float sy, hipStream_t st) {
+  const long slab = static_cast<long>(a.K1P) * a.K2P;
+  const int nrows = a.r0 * a.K[2];
+  const int ntiles = (nrows + 15) / 16;
+  dim3 grid((ntiles + kS1Tiles - 1) / kS1Tiles, static_cast<unsigned>(slab / 64));
+  hipLaunchKernelGGL((stage1_x3<H>), grid, dim3(64), 0, st, static_cast<const float*>(a.Q),
+                     static_cast<const H*>(a.C[0]), static_cast<const H*>(a.C[1]),
+                     static_cast<H*>(a.Y[0]), static_cast<H*>(a.Y[1]), a.K[0], a.K[1], a.K[2],
+                     a.K3P, a.K2P, slab, nrows, qscale, sy);
+  return hipGetLastError();
+}
+
 hipError_t launch_skp_stage1(const SkpArgs& a, hipStream_t st) {
   const long slab = static_cast<long>(a.K1P) * a.K2P;
   const int nrows = a.r0 * a.K[2];
   dim3 g1(static_cast<unsigned>(slab / S1), (nrows + S1 - 1) / S1);
-  if (a.prec == PREC_BF16X3)
-    hipLaunchKernelGGL((stage1_x3<bf16>), g1, dim3(256), 0, st, static_cast<const float*>(a.Q),
-                       static_cast<const bf16*>(a.C[0]), static_cast<const bf16*>(a.C[1]),
-                       static_cast<bf16*>(a.Y[0]), static_cast<bf16*>(a.Y[1]), a.K[0], a.K[1],
-                       a.K[2], a.K3P, a.K2P, slab, nrows, nullptr, 1.0f);
-  else if (a.prec == PREC_FP16X3)
-    hipLaunchKernelGGL((stage1_x3<f16>), g1, dim3(256), 0, st, static_cast<const float*>(a.Q),
-                       static_cast<const f16*>(a.C[0]), static_cast<const f16*>(a.C[1]),
-                       static_cast<f16*>(a.Y[0]), static_cast<f16*>(a.Y[1]), a.K[0], a.K[1],
-                       a.K[2], a.K3P, a.K2P, slab, nrows, a.sumQ + 1, a.sy);
-  else if (a.prec == PREC_FP32)
+  if (a.prec == PREC_BF16X3) return launch_s1_x3<bf16>(a, nullptr, 1.0f, st);
+  if (a.prec == PREC_FP16X3) return launch_s1_x3<f16>(a, a.sumQ + 1, a.sy, st);
+  if (a.prec == PREC_FP32)
     hipLaunchKernelGGL((stage1_k4<float>), g1, dim3(256), 0, st, static_cast<const float*>(a.Q),
                        static_cast<const float*>(a.C[0]), static_cast<float*>(a.Y[0]), a.K[0],
                        a.K[1], a.K[2], a.K3P, a.K2P, slab, nrows);
