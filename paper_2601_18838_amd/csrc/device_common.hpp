@@ -64,3 +64,22 @@ template <> struct Vec4<float> { typedef floatx4 type; };
 template <> struct Vec4<double> { typedef doublex4 type; };
 
 }  // namespace kpme
+
+namespace kpme {
+
+// Workgroups are handed to the 8 XCDs (each with its own L2) in turn: linear
+// workgroup b runs on XCD b % 8.  xcd_order(b, n) renumbers them so that
+// every XCD gets one contiguous range of the logical order; kernels whose
+// neighbouring logical workgroups share inputs then reuse them in one L2.
+constexpr int kNumXcd = 8;
+__device__ __forceinline__ int xcd_order(int b, int n) {
+  const int x = b % kNumXcd, i = b / kNumXcd;
+  const int per = n / kNumXcd, rem = n % kNumXcd;
+  return x * per + min(x, rem) + i;
+}
+__device__ __forceinline__ int linear_block() {
+  return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+}
+__device__ __forceinline__ int num_blocks() { return gridDim.x * gridDim.y * gridDim.z; }
+
+}  // namespace kpme

@@ -290,7 +290,9 @@ __global__ __launch_bounds__(256) void spread_brick(const T* __restrict__ sorted
   __shared__ int hstart[64], hpre[65];
   __shared__ double red[256], mx[256];
   const int E0 = bg.edge[0], E1 = bg.edge[1], E2 = bg.edge[2];
-  int own[3], rest = blockIdx.x;
+  // neighbouring bricks (which read overlapping particle lists) share an XCD
+  const int brick = xcd_order(blockIdx.x, gridDim.x);
+  int own[3], rest = brick;
   own[2] = rest % bg.nb[2]; rest /= bg.nb[2];
   own[1] = rest % bg.nb[1];
   own[0] = rest / bg.nb[1];
@@ -374,8 +376,8 @@ __global__ __launch_bounds__(256) void spread_brick(const T* __restrict__ sorted
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    part2[2 * blockIdx.x] = red[0];
-    part2[2 * blockIdx.x + 1] = mx[0];
+    part2[2 * brick] = red[0];
+    part2[2 * brick + 1] = mx[0];
   }
 }
 
@@ -391,7 +393,9 @@ __global__ __launch_bounds__(256) void gather_sorted(long n, const T* __restrict
                                                      T* __restrict__ force,
                                                      double* __restrict__ part3, GridGeom g) {
   __shared__ double red[3][256];
-  const long s = blockIdx.x * static_cast<long>(blockDim.x) + threadIdx.x;
+  // neighbouring particle blocks (neighbouring bricks) share an XCD's L2
+  const int blk = xcd_order(blockIdx.x, gridDim.x);
+  const long s = blk * static_cast<long>(blockDim.x) + threadIdx.x;
   double e0 = 0, e1 = 0, e2 = 0;
   if (s < n) {
     T w[3][P], dw[3][P];
@@ -457,7 +461,7 @@ __global__ __launch_bounds__(256) void gather_sorted(long n, const T* __restrict
       __syncthreads();
     }
     if (threadIdx.x == 0)
-      for (int k = 0; k < 3; ++k) part3[3 * blockIdx.x + k] = red[k][0];
+      for (int k = 0; k < 3; ++k) part3[3 * blk + k] = red[k][0];
   }
 }
 
@@ -486,7 +490,7 @@ __global__ __launch_bounds__(256) void gather_backward(
     const T* __restrict__ Phi, const T* __restrict__ Psi, const double* __restrict__ g_energy,
     const T* __restrict__ g_pot, const double* __restrict__ sumq, double beta, double volume,
     T* __restrict__ grad_pos, T* __restrict__ grad_q, GridGeom g) {
-  const long s = blockIdx.x * static_cast<long>(blockDim.x) + threadIdx.x;
+  const long s = xcd_order(blockIdx.x, gridDim.x) * static_cast<long>(blockDim.x) + threadIdx.x;
   if (s >= n) return;
   T w[3][P], dw[3][P];
   int base[3];

@@ -49,8 +49,11 @@ __global__ __launch_bounds__(64) void stage1_x3(
     long slab, int nrows, const double* __restrict__ qscale, float sy) {
   typedef typename HVec<H>::v8 v8;
   const int lane = threadIdx.x, q = lane >> 4, m = lane & 15;
-  const long p0 = static_cast<long>(blockIdx.y) * 64;
-  const int nt0 = blockIdx.x * kS1Tiles;
+  // logical order: the n splits of one position tile are consecutive (and so
+  // share an XCD and its L2 copy of the Q tile)
+  const int L = xcd_order(linear_block(), num_blocks());
+  const long p0 = static_cast<long>(L / gridDim.x) * 64;
+  const int nt0 = (L % gridDim.x) * kS1Tiles;
   const float sq = qscale ? static_cast<float>(*qscale) : 1.0f;
   const bool vec4 = (K3 & 3) == 0;  // rows 16-byte aligned, 4-float groups all in or out
   // Q rows of this lane's A-operand rows: tile u holds p = p0 + 16 (m / 4) + 4 u + m % 4
@@ -158,6 +161,127 @@ __global__ __launch_bounds__(64) void stage1_x3(
   }
 }
 
+// Stage 1, split precision, K3P <= 128 (NK = K3P / 32 chunks): a workgroup
+// of four waves takes one tile of 64 positions; its Q rows are split into
+// hi/lo once, into LDS, and every wave keeps the A fragments of the whole K
+// range in registers while it streams its share of the 16-row C tiles
+// (kS1Split workgroups per position tile), the next tile's C fragments in
+// flight.  Position dealing and output layout as in stage1_x3.
+constexpr int kS1Split = 2;
+
+template <typename H, int NK>
+__global__ __launch_bounds__(256) void stage1_x3_lds(
+    const float* __restrict__ Q, const H* __restrict__ Chi, const H* __restrict__ Clo,
+    H* __restrict__ Yhi, H* __restrict__ Ylo, int K1, int K2, int K3, int K2P, long slab,
+    int nrows, const double* __restrict__ qscale, float sy) {
+  typedef typename HVec<H>::v8 v8;
+  constexpr int K3P = 32 * NK, QSTR = K3P + 8;
+  __shared__ __attribute__((aligned(16))) H Qh[64 * QSTR], Ql[64 * QSTR];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, q = lane >> 4, m = lane & 15;
+  // logical order: the splits of one position tile are consecutive (one XCD)
+  const int L = xcd_order(linear_block(), num_blocks());
+  const long p0 = static_cast<long>(L / kS1Split) * 64;
+  const int split = L % kS1Split;
+  const float sq = qscale ? static_cast<float>(*qscale) : 1.0f;
+  // Q tile -> LDS hi/lo (row r = p - p0, zero outside the grid and for k >= K3)
+  {
+    constexpr int c4n = K3P / 4;
+    for (int e = tid; e < 64 * c4n; e += 256) {
+      const int r = e / c4n, k = 4 * (e % c4n);
+      const long p = p0 + r;
+      const int g1 = static_cast<int>(p / K2P), g2 = static_cast<int>(p % K2P);
+      const bool valid = g1 < K1 && g2 < K2;
+      const float* row = Q + (static_cast<long>(valid ? g1 : 0) * K2 + (valid ? g2 : 0)) * K3;
+      float x[4] = {0.f, 0.f, 0.f, 0.f};
+      if ((K3 & 3) == 0) {
+        if (valid && k < K3) {
+          const float4 v = *reinterpret_cast<const float4*>(&row[k]);
+          x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
+        }
+      } else {
+#pragma unroll
+        for (int h = 0; h < 4; ++h) x[h] = (valid && k + h < K3) ? row[k + h] : 0.f;
+      }
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        H hi, lo;
+        split_h<H>(sq * x[h], hi, lo);
+        Qh[r * QSTR + k + h] = hi;
+        Ql[r * QSTR + k + h] = lo;
+      }
+    }
+  }
+  __syncthreads();
+  // A fragments of the whole K range: tile u, lane (q, m) holds row
+  // 16 (m / 4) + 4 u + m % 4, columns 32 kc + 8 q .. + 7
+  v8 ah[NK][4], al[NK][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int r = 16 * (m >> 2) + 4 * u + (m & 3);
+#pragma unroll
+    for (int kc = 0; kc < NK; ++kc) {
+      ah[kc][u] = *reinterpret_cast<const v8*>(&Qh[r * QSTR + 32 * kc + 8 * q]);
+      al[kc][u] = *reinterpret_cast<const v8*>(&Ql[r * QSTR + 32 * kc + 8 * q]);
+    }
+  }
+  const int ntiles = (nrows + 15) / 16;
+  const int per = (ntiles + kS1Split - 1) / kS1Split;
+  const int t0 = split * per, t1 = min(ntiles, t0 + per);
+  auto loadc = [&](int t, v8 (&bh)[NK], v8 (&bl)[NK]) {
+    const int n = 16 * t + m;
+#pragma unroll
+    for (int kc = 0; kc < NK; ++kc) {
+      bh[kc] = v8{};
+      bl[kc] = v8{};
+      if (t < t1 && n < nrows) {
+        bh[kc] = *reinterpret_cast<const v8*>(&Chi[static_cast<long>(n) * K3P + 32 * kc + 8 * q]);
+        bl[kc] = *reinterpret_cast<const v8*>(&Clo[static_cast<long>(n) * K3P + 32 * kc + 8 * q]);
+      }
+    }
+  };
+  v8 bh[NK], bl[NK];
+  loadc(t0 + wave, bh, bl);
+  for (int t = t0 + wave; t < t1; t += 4) {
+    v8 ch[NK], cl[NK];
+#pragma unroll
+    for (int kc = 0; kc < NK; ++kc) {
+      ch[kc] = bh[kc];
+      cl[kc] = bl[kc];
+    }
+    loadc(t + 4, bh, bl);  // the wave's next tile
+    floatx4 acc[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[u] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kc = 0; kc < NK; ++kc) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] = mfma_h(ah[kc][u], ch[kc], acc[u]);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] = mfma_h(ah[kc][u], cl[kc], acc[u]);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] = mfma_h(al[kc][u], ch[kc], acc[u]);
+    }
+    const int n = 16 * t + m;
+    if (n < nrows) {
+      v8 yh[2], yl[2];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          H h, l;
+          split_h<H>(sy * acc[u][r], h, l);
+          yh[u >> 1][4 * (u & 1) + r] = h;
+          yl[u >> 1][4 * (u & 1) + r] = l;
+        }
+      const long o = static_cast<long>(n) * slab + p0 + 16 * q;
+      *reinterpret_cast<v8*>(&Yhi[o]) = yh[0];
+      *reinterpret_cast<v8*>(&Yhi[o + 8]) = yh[1];
+      *reinterpret_cast<v8*>(&Ylo[o]) = yl[0];
+      *reinterpret_cast<v8*>(&Ylo[o + 8]) = yl[1];
+    }
+  }
+}
+
 // Stage 1, FP32 / FP64 (16x16x4 MFMA).  C: [nrows][K3P]; Y: [nrows][slab].
 template <typename T>
 __global__ __launch_bounds__(256) void stage1_k4(const T* __restrict__ Q,
@@ -241,7 +365,10 @@ __global__ __launch_bounds__(RT >= 8 ? 256 : 512) void stage2_x3(
   H* Ysh = reinterpret_cast<H*>(smem);
   H* Ysl = Ysh + K1P * YSTR;
   H* vbuf = Ysl + K1P * YSTR;                   // [2][tsz]
-  const int s = blockIdx.x, part = blockIdx.y;
+  // logical order: the term ranges of one slab are consecutive (one XCD and
+  // L2 for the slab's Y planes)
+  const int L = xcd_order(linear_block(), num_blocks());
+  const int s = L / gridDim.y, part = L % gridDim.y;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int lane = tid & 63, wave = tid >> 6, q = lane >> 4, m = lane & 15;
   const int col0 = wave * 16 * CT;
@@ -497,7 +624,8 @@ __global__ __launch_bounds__(512) void stage2_k4(
 }
 
 // Sum the partial slabs [part][k3][k1][k2] in order, transpose to
-// [k1][k2][k3] and subtract c * sum(Q).
+// [k1][k2][k3] and subtract c * sum(Q).  One workgroup per (k1, 32 x 32 tile
+// of k2 x k3); interior tiles of 4-aligned extents move float4 vectors.
 template <typename A, typename O>
 __global__ __launch_bounds__(256) void finalize(const A* __restrict__ part, int nparts,
                                                 O* __restrict__ Phi, int K1, int K2,
@@ -506,25 +634,52 @@ __global__ __launch_bounds__(256) void finalize(const A* __restrict__ part, int 
                                                 double const_scale) {
   __shared__ A tile[32][33];
   const int k1 = blockIdx.z, k2b = blockIdx.x * 32, k3b = blockIdx.y * 32;
+  const int t = threadIdx.x;
+  const long pstride = static_cast<long>(K3) * K1 * K2;
+  const bool vec = sizeof(A) == 4 && (K2 & 3) == 0 && (K3 & 3) == 0 && k2b + 32 <= K2 &&
+                   k3b + 32 <= K3;
+  if (vec) {
+    const int r = t >> 3, c4 = (t & 7) * 4;  // k3 row, k2 column group
+    const long base = (static_cast<long>(k3b + r) * K1 + k1) * K2 + k2b + c4;
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int p = 0; p < nparts; ++p) {
+      const float4 w = *reinterpret_cast<const float4*>(&part[p * pstride + base]);
+      v.x += w.x; v.y += w.y; v.z += w.z; v.w += w.w;
+    }
+    tile[r][c4] = v.x;
+    tile[r][c4 + 1] = v.y;
+    tile[r][c4 + 2] = v.z;
+    tile[r][c4 + 3] = v.w;
+  } else {
+    for (int j = t >> 5; j < 32; j += 8) {
+      const int k3 = k3b + j, k2 = k2b + (t & 31);
+      A v = 0;
+      if (k3 < K3 && k2 < K2) {
+        const long base = (static_cast<long>(k3) * K1 + k1) * K2 + k2;
+        for (int p = 0; p < nparts; ++p) v += part[p * pstride + base];
+      }
+      tile[j][t & 31] = v;
+    }
+  }
   const A corr = static_cast<A>(c0 * sumQ[0]);
   // the partial slabs carry the product of the split-precision scales
   const A unscale = qscale ? static_cast<A>(1.0 / (qscale[0] * const_scale)) : A(1);
-  const long pstride = static_cast<long>(K3) * K1 * K2;
-  for (int j = threadIdx.y; j < 32; j += 8) {
-    const int k3 = k3b + j, k2 = k2b + threadIdx.x;
-    A v = 0;
-    if (k3 < K3 && k2 < K2) {
-      const long base = (static_cast<long>(k3) * K1 + k1) * K2 + k2;
-      for (int p = 0; p < nparts; ++p) v += part[p * pstride + base];
-    }
-    tile[j][threadIdx.x] = v;
-  }
   __syncthreads();
-  for (int j = threadIdx.y; j < 32; j += 8) {
-    const int k2 = k2b + j, k3 = k3b + threadIdx.x;
-    if (k2 < K2 && k3 < K3)
-      Phi[(static_cast<long>(k1) * K2 + k2) * K3 + k3] =
-          static_cast<O>(unscale * tile[threadIdx.x][j] - corr);
+  if (vec) {
+    const int r = t >> 3, c4 = (t & 7) * 4;  // k2 row, k3 column group
+    float4 o;
+    o.x = unscale * tile[c4][r] - corr;
+    o.y = unscale * tile[c4 + 1][r] - corr;
+    o.z = unscale * tile[c4 + 2][r] - corr;
+    o.w = unscale * tile[c4 + 3][r] - corr;
+    *reinterpret_cast<float4*>(&Phi[(static_cast<long>(k1) * K2 + k2b + r) * K3 + k3b + c4]) = o;
+  } else {
+    for (int j = t >> 5; j < 32; j += 8) {
+      const int k2 = k2b + j, k3 = k3b + (t & 31);
+      if (k2 < K2 && k3 < K3)
+        Phi[(static_cast<long>(k1) * K2 + k2) * K3 + k3] =
+            static_cast<O>(unscale * tile[t & 31][j] - corr);
+    }
   }
 }
 
@@ -687,7 +842,22 @@ hipError_t launch_s1_x3(const SkpArgs& a, const double* qscale, float sy, hipStr
   const long slab = static_cast<long>(a.K1P) * a.K2P;
   const int nrows = a.r0 * a.K[2];
   const int ntiles = (nrows + 15) / 16;
-  dim3 grid((ntiles + kS1Tiles - 1) / kS1Tiles, static_cast<unsigned>(slab / 64));
+  const unsigned ptiles = static_cast<unsigned>(slab / 64);
+#define KPME_S1(NK)                                                                        \
+  hipLaunchKernelGGL((stage1_x3_lds<H, NK>), dim3(kS1Split, ptiles), dim3(256), 0, st,    \
+                     static_cast<const float*>(a.Q), static_cast<const H*>(a.C[0]),        \
+                     static_cast<const H*>(a.C[1]), static_cast<H*>(a.Y[0]),               \
+                     static_cast<H*>(a.Y[1]), a.K[0], a.K[1], a.K[2], a.K2P, slab, nrows,  \
+                     qscale, sy)
+  switch (a.K3P) {
+    case 32: KPME_S1(1); return hipGetLastError();
+    case 64: KPME_S1(2); return hipGetLastError();
+    case 96: KPME_S1(3); return hipGetLastError();
+    case 128: KPME_S1(4); return hipGetLastError();
+    default: break;
+  }
+#undef KPME_S1
+  dim3 grid((ntiles + kS1Tiles - 1) / kS1Tiles, ptiles);
   hipLaunchKernelGGL((stage1_x3<H>), grid, dim3(64), 0, st, static_cast<const float*>(a.Q),
                      static_cast<const H*>(a.C[0]), static_cast<const H*>(a.C[1]),
                      static_cast<H*>(a.Y[0]), static_cast<H*>(a.Y[1]), a.K[0], a.K[1], a.K[2],
@@ -726,12 +896,12 @@ hipError_t launch_skp_stage2(const SkpArgs& a, hipStream_t st) {
 hipError_t launch_skp_finalize(const SkpArgs& a, hipStream_t st) {
   dim3 gf((a.K[1] + 31) / 32, (a.K[2] + 31) / 32, a.K[0]);
   if (a.prec == PREC_FP64)
-    hipLaunchKernelGGL((finalize<double, double>), gf, dim3(32, 8), 0, st,
+    hipLaunchKernelGGL((finalize<double, double>), gf, dim3(256), 0, st,
                        static_cast<const double*>(a.Phi_part), a.nparts,
                        static_cast<double*>(a.Phi), a.K[0], a.K[1], a.K[2], a.sumQ, a.c0,
                        nullptr, 1.0);
   else
-    hipLaunchKernelGGL((finalize<float, float>), gf, dim3(32, 8), 0, st,
+    hipLaunchKernelGGL((finalize<float, float>), gf, dim3(256), 0, st,
                        static_cast<const float*>(a.Phi_part), a.nparts,
                        static_cast<float*>(a.Phi), a.K[0], a.K[1], a.K[2], a.sumQ, a.c0,
                        a.prec == PREC_FP16X3 ? a.sumQ + 1 : nullptr, a.const_scale);
