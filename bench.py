@@ -43,6 +43,31 @@ def parse():
     return ap.parse_args()
 
 
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "stage2_x3_water_n99999_g96_p4_traffic.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2601_18838_amd", "csrc", "skp_kernels.hip")
+
+
+def committed_traffic(workload, precision, parts):
+    """HBM bytes per stage-2 launch from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE, scaled by the copy-kernel calibration), or None
+    when that summary is for another configuration or the kernel source has
+    changed since the counters were taken."""
+    import hashlib
+    try:
+        fields = {}
+        for line in open(TRAFFIC_SUMMARY):
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].strip().split(": ", 1)
+                fields[k] = v.strip("` ")
+        sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+        if (fields.get("source_sha256") != sha or fields.get("workload") != workload
+                or fields.get("precision") != precision or int(fields.get("stage2_parts", -1)) != parts):
+            return None
+        return float(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def copy_calibration(mib):
     """Five plain device-to-device copies of a known size, for scaling HBM byte counters."""
     import torch
@@ -247,7 +272,7 @@ def main():
         "stage_us_fp64": stage_us_fp64,
         "roofline": {"bound": "mfma", "kernel": "skp_stage2", "achieved": achieved,
                      "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": None,
+                     "traffic": committed_traffic(wl.name, mixed, plans[mixed].stage2_parts()),
                      "flops_per_launch": issued,
                      "effective_single_product_tflops": flops_s2 / avg_s2 / 1e12},
     }

@@ -813,8 +813,10 @@ extern "C" kpme_status kpme_plan_autotune(kpme_plan_t plan, void* stream) {
     (void)hipEventDestroy(e0);
     return fail(KPME_ERROR_DEVICE, "hipEventCreate");
   }
-  int best = plan->nparts;
-  float best_ms = 1e30f;
+  // time every candidate; keep the smallest split within 3% of the fastest
+  // (fewer partial slabs to write and sum, and a choice that is stable
+  // against timing noise)
+  std::vector<std::pair<int, float>> timed;
   const bool was_on = plan->prof_on;
   plan->prof_on = false;
   for (int c : cands) {
@@ -827,11 +829,16 @@ extern "C" kpme_status kpme_plan_autotune(kpme_plan_t plan, void* stream) {
     (void)hipEventRecord(e1, st);
     float ms = 0.f;
     if (s == KPME_SUCCESS && hipEventSynchronize(e1) == hipSuccess &&
-        hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms < best_ms) {
-      best_ms = ms;
-      best = c;
-    }
+        hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
+      timed.emplace_back(c, ms);
     if (s != KPME_SUCCESS) break;
+  }
+  int best = plan->nparts;
+  if (!timed.empty()) {
+    float fastest = 1e30f;
+    for (const auto& t : timed) fastest = std::min(fastest, t.second);
+    for (const auto& t : timed)
+      if (t.second <= 1.03f * fastest) { best = t.first; break; }  // cands ascend
   }
   plan->prof_on = was_on;
   (void)hipEventDestroy(e0);
