@@ -150,6 +150,7 @@ struct kpme_batch_s {
   hipEvent_t fork = nullptr;
   hipEvent_t join[kBatchBranches] = {};
   hipGraphExec_t exec = nullptr;       // recorded graph for the last signature
+  hipEvent_t launched = nullptr;       // recorded after each launch of exec
   std::vector<int64_t> sig_n;
   const void* sig_ptr[5] = {};
 };
@@ -206,7 +207,11 @@ void plan_free(kpme_plan_s* pl) {
 }
 
 void batch_free(kpme_batch_s* b) {
+  // nothing of the batch may still be executing when it is released
+  (void)hipSetDevice(b->device);
+  (void)hipDeviceSynchronize();
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->launched) (void)hipEventDestroy(b->launched);
   for (int k = 0; k < kBatchBranches; ++k) {
     if (b->branch[k]) (void)hipStreamDestroy(b->branch[k]);
     if (b->join[k]) (void)hipEventDestroy(b->join[k]);
@@ -1058,7 +1063,8 @@ kpme_status kpme_batch_create(kpme_batch_t* batch, int count, const double* box3
     }
   }
   if (hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->launched, hipEventDisableTiming) != hipSuccess) {
     batch_free(b);
     return fail(KPME_ERROR_DEVICE, "stream/event creation failed");
   }
@@ -1113,6 +1119,9 @@ kpme_status kpme_batch_evaluate(kpme_batch_t batch, const int64_t* n, const void
                     std::equal(ptrs, ptrs + 5, batch->sig_ptr);
   if (!same) {
     if (batch->exec) {
+      // the previous recording may still be executing: wait for its last
+      // launch before releasing it
+      (void)hipEventSynchronize(batch->launched);
       (void)hipGraphExecDestroy(batch->exec);
       batch->exec = nullptr;
     }
@@ -1153,7 +1162,9 @@ kpme_status kpme_batch_evaluate(kpme_batch_t batch, const int64_t* n, const void
     batch->sig_n = sig;
     std::copy(ptrs, ptrs + 5, batch->sig_ptr);
   }
-  return from_hip(hipGraphLaunch(batch->exec, st), "graph launch");
+  hipError_t e = hipGraphLaunch(batch->exec, st);
+  if (e == hipSuccess) e = hipEventRecord(batch->launched, st);
+  return from_hip(e, "graph launch");
 }
 
 }  // extern "C"

@@ -86,3 +86,19 @@ def test_small_fp64_batch_against_oracle():
         assert relrms(pot[off:off + wl.n].cpu().numpy(), ref["phi"]) < 1e-10
         assert relrms(f[off:off + wl.n].cpu().numpy(), ref["F"]) < 1e-10
         off += wl.n
+
+
+def test_rerecording_while_previous_replay_runs():
+    """Back-to-back evaluations with fresh output buffers re-record the graph
+    each time while the previous replay may still be executing; the library
+    waits for that replay before releasing it."""
+    batch = systems.batch_systems(count=6, base_seed=7000)
+    print("[batch] re-recording, 6 systems fp16x3", flush=True)
+    bp, pos, q, n = build(batch, "fp16x3")
+    ref = [x.clone() for x in bp.evaluate(n, pos, q)]
+    torch.cuda.synchronize()
+    outs = [bp.evaluate(n, pos, q) for _ in range(4)]   # no synchronisation in between
+    torch.cuda.synchronize()
+    for e, pot, f in outs:
+        np.testing.assert_allclose(e.cpu().numpy(), ref[0].cpu().numpy(), rtol=1e-6, atol=1e-9)
+        assert relrms(pot.double().cpu().numpy(), ref[1].double().cpu().numpy()) < 1e-6
