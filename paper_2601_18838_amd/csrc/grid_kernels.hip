@@ -413,10 +413,15 @@ __global__ __launch_bounds__(256) void gather_sorted(long n, const T* __restrict
       if (kc[c] < 0) kc[c] += K3;
     }
     T phi = 0, g0 = 0, g1 = 0, g2 = 0;
+    // unrolled so that a whole plane (small P: the whole stencil) of loads is
+    // in flight at once
+    constexpr int UA = P <= 4 ? P : 1, UB = P <= 8 ? P : 1;
+#pragma unroll UA
     for (int a = 0; a < P; ++a) {
       int ka = base[0] - a;
       if (ka < 0) ka += K1;
       T sa = 0, sa1 = 0, sa2 = 0;
+#pragma unroll UB
       for (int b = 0; b < P; ++b) {
         int kb = base[1] - b;
         if (kb < 0) kb += K2;
