@@ -20,8 +20,9 @@ definitions it follows:
   estimate_svd), real circulant per-axis factors (Sec. 2.3-2.4, Eq. VtV,
   Eq. formfinale), the three mode products per term (Sec. 3.2-3.3, Alg. 1 and
   Alg. 2) and the constant correction (Sec. 4.1 Eq. termbonsum, Alg. 4).
-* ``quadrature`` -- the sinc-quadrature SKP of the kernel (Sec. 2.1.2,
-  Eqs. one_over_r_int, quaddecompalpham, estimatequad).
+
+The sinc-quadrature SKP of the kernel (Sec. 2.1.2) is not part of the hot
+path built here and has no oracle module.
 
 Parity status of each function is stated in its module header; every function
 here is pinned by a test in ``tests/test_oracle_*.py`` against values the

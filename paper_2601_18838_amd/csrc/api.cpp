@@ -670,6 +670,12 @@ kpme_status kpme_plan_create(kpme_plan_t* plan, const double box[3], const int g
     bn.nbr = static_cast<int*>(tmp);
     if ((e = hipMemcpy(tmp, hnbr.data(), hnbr.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess) break;
     if ((e = plan_alloc(pl, &bn.sorted, nmax * 4 * es)) != hipSuccess) break;
+    if (spline_order > 4) {  // per-brick tiles of the two-pass spread
+      size_t ntile = 1;
+      for (int j = 0; j < 3; ++j) ntile *= static_cast<size_t>(bg.edge[j] + spline_order - 1);
+      if ((e = plan_alloc(pl, &bn.tiles, static_cast<size_t>(bg.nbricks) * ntile * es)) != hipSuccess)
+        break;
+    }
     if ((e = hipMemset(bn.count, 0, nb1 * sizeof(int))) != hipSuccess) break;
     if ((e = plan_alloc(pl, &tmp, 4 * static_cast<size_t>(bg.nbricks) * sizeof(double))) != hipSuccess) break;
     pl->part2 = static_cast<double*>(tmp);  // two (sum, max) sets: forward, adjoint

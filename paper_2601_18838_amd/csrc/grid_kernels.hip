@@ -381,6 +381,143 @@ __global__ __launch_bounds__(256) void spread_brick(const T* __restrict__ sorted
   }
 }
 
+// Home-computes spread, pass 1: one wave per grid brick adds the stencils of
+// the particles binned in that brick into an LDS tile covering the brick and
+// the P - 1 planes below it on each axis, H_j = edge_j + P - 1 points, where
+// every stencil point of those particles falls (no masking, each particle
+// visited once), then stores the tile, rounded from the FP64 LDS sums to T,
+// to tiles[brick].  Local tile coordinate of grid point k_j:
+// k_j - lo_j + P - 1 (unwrapped).
+template <typename T, int P>
+__global__ __launch_bounds__(64) void spread_home(const T* __restrict__ sorted,
+                                                  const int* __restrict__ offset,
+                                                  T* __restrict__ tiles, GridGeom g, BinGeom bg) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  double* tile = reinterpret_cast<double*>(smem);
+  const int brick = xcd_order(blockIdx.x, gridDim.x);
+  int own[3], rest = brick;
+  own[2] = rest % bg.nb[2]; rest /= bg.nb[2];
+  own[1] = rest % bg.nb[1];
+  own[0] = rest / bg.nb[1];
+  int lo[3], H[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    lo[j] = own[j] * bg.edge[j];
+    H[j] = bg.edge[j] + P - 1;
+  }
+  const int ntile = H[0] * H[1] * H[2];
+  for (int e = threadIdx.x; e < ntile; e += blockDim.x) tile[e] = 0.0;
+  __syncthreads();
+  const int i0 = offset[brick], i1 = offset[brick + 1];
+  for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    T w[3][P], dw[P];
+    int l[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      int base;
+      const T f = scaled(sorted[4L * i + j], g.L[j], g.K[j], base);
+      bspline<T, P>(f, w[j], dw);
+      // the particle was binned by the same floor, so base lies in this
+      // brick; the clamp only keeps a corrupted input inside the tile
+      l[j] = min(max(base - lo[j] + P - 1, P - 1), H[j] - 1);
+    }
+    const T qi = sorted[4L * i + 3];
+#pragma unroll
+    for (int a = 0; a < P; ++a) {
+      const T wa = qi * w[0][a];
+#pragma unroll
+      for (int b = 0; b < P; ++b) {
+        const T wab = wa * w[1][b];
+        double* row = tile + ((l[0] - a) * H[1] + l[1] - b) * H[2] + l[2];
+#pragma unroll
+        for (int c = 0; c < P; ++c) atomicAdd(row - c, static_cast<double>(wab * w[2][c]));
+      }
+    }
+  }
+  __syncthreads();
+  T* out = tiles + static_cast<long>(brick) * ntile;
+  for (int e = threadIdx.x; e < ntile; e += blockDim.x) out[e] = static_cast<T>(tile[e]);
+}
+
+// Pass 2: one workgroup per grid brick sums, for each of its points and in a
+// fixed order, the tiles of the home bricks whose stencils reach it (the
+// per-axis lists nbr[axis][brick] = {count, b0, b1, ...}; a point is covered
+// by tile h at local coordinates (k_j - lo_h + P - 1) mod K_j + m K_j < H_j,
+// more than one image only when a stencil is wider than the grid).  Writes
+// every grid value once and the brick's FP64 (sum, max) to part2[brick].
+template <typename T, int P>
+__global__ __launch_bounds__(256) void spread_combine(const T* __restrict__ tiles,
+                                                      const int* __restrict__ nbr,
+                                                      T* __restrict__ grid,
+                                                      double* __restrict__ part2, GridGeom g,
+                                                      BinGeom bg) {
+  __shared__ double red[256], mx[256];
+  const int brick = xcd_order(blockIdx.x, gridDim.x);
+  int own[3], rest = brick;
+  own[2] = rest % bg.nb[2]; rest /= bg.nb[2];
+  own[1] = rest % bg.nb[1];
+  own[0] = rest / bg.nb[1];
+  int lo[3], ext[3], H[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    lo[j] = own[j] * bg.edge[j];
+    ext[j] = min(bg.edge[j], g.K[j] - lo[j]);
+    H[j] = bg.edge[j] + P - 1;
+  }
+  const int ntile = H[0] * H[1] * H[2];
+  const int* n0 = nbr + kNbrRec * (0 * bg.nbmax + own[0]);
+  const int* n1 = nbr + kNbrRec * (1 * bg.nbmax + own[1]);
+  const int* n2 = nbr + kNbrRec * (2 * bg.nbmax + own[2]);
+  double s = 0.0, m = 0.0;
+  const int npts = ext[0] * ext[1] * ext[2];
+  for (int e = threadIdx.x; e < npts; e += blockDim.x) {
+    const int k2 = lo[2] + e % ext[2], k1 = lo[1] + (e / ext[2]) % ext[1],
+              k0 = lo[0] + e / (ext[1] * ext[2]);
+    double acc = 0.0;
+    for (int x = 0; x < n0[0]; ++x) {
+      const int h0 = n0[1 + x];
+      int r0 = k0 - h0 * bg.edge[0] + P - 1;
+      while (r0 < 0) r0 += g.K[0];
+      while (r0 >= g.K[0]) r0 -= g.K[0];
+      for (int l0 = r0; l0 < H[0]; l0 += g.K[0])
+        for (int y = 0; y < n1[0]; ++y) {
+          const int h1 = n1[1 + y];
+          int r1 = k1 - h1 * bg.edge[1] + P - 1;
+          while (r1 < 0) r1 += g.K[1];
+          while (r1 >= g.K[1]) r1 -= g.K[1];
+          for (int l1 = r1; l1 < H[1]; l1 += g.K[1])
+            for (int z = 0; z < n2[0]; ++z) {
+              const int h2 = n2[1 + z];
+              int r2 = k2 - h2 * bg.edge[2] + P - 1;
+              while (r2 < 0) r2 += g.K[2];
+              while (r2 >= g.K[2]) r2 -= g.K[2];
+              const T* t = tiles + static_cast<long>((h0 * bg.nb[1] + h1) * bg.nb[2] + h2) * ntile +
+                           (l0 * H[1] + l1) * H[2];
+              for (int l2 = r2; l2 < H[2]; l2 += g.K[2]) acc += static_cast<double>(t[l2]);
+            }
+        }
+    }
+    const T v = static_cast<T>(acc);
+    grid[(static_cast<long>(k0) * g.K[1] + k1) * g.K[2] + k2] = v;
+    s += static_cast<double>(v);
+    m = fmax(m, fabs(static_cast<double>(v)));
+  }
+  red[threadIdx.x] = s;
+  mx[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      red[threadIdx.x] += red[threadIdx.x + w];
+      mx[threadIdx.x] = fmax(mx[threadIdx.x], mx[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part2[2 * brick] = red[0];
+    part2[2 * brick + 1] = mx[0];
+  }
+}
+
 // Gather in binned order (neighbouring threads read neighbouring grid
 // values); results are written back to the caller's order through perm.
 // Each workgroup also writes its FP64 partial sums (q pot, q, q^2) to
@@ -513,9 +650,12 @@ __global__ __launch_bounds__(256) void gather_backward(
   }
   // v[0]: W.grid, v[1..3]: derivatives along the three axes (in u units)
   T vf[4] = {0, 0, 0, 0}, vs[4] = {0, 0, 0, 0};
+  constexpr int UA = P <= 4 ? P : 1, UB = P <= 8 ? P : 1;  // loads in flight
+#pragma unroll UA
   for (int a = 0; a < P; ++a) {
     int ka = base[0] - a;
     if (ka < 0) ka += K1;
+#pragma unroll UB
     for (int b = 0; b < P; ++b) {
       int kb = base[1] - b;
       if (kb < 0) kb += K2;
@@ -716,13 +856,26 @@ hipError_t scatter_t(const Bins& b, int64_t n, const void* pos, const void* q, h
   return hipGetLastError();
 }
 
+// Spread dispatch by spline order: for P <= 4 the owner-computes kernel (one
+// pass, each particle seen by ~(1 + (P-1)/8)^3 owner bricks); for larger P
+// the two-pass home-computes scheme, which sees each particle once.
 template <typename T, int P>
 hipError_t spread_brick_p(const GridGeom& g, const Bins& b, const void* src, void* grid,
                           double* part2, hipStream_t st) {
-  const size_t lds = sizeof(double) * b.geom.edge[0] * b.geom.edge[1] * b.geom.edge[2];
-  hipLaunchKernelGGL((spread_brick<T, P>), dim3(b.geom.nbricks), dim3(256), lds, st,
-                     static_cast<const T*>(src ? src : b.sorted), b.offset, b.nbr,
-                     static_cast<T*>(grid), part2, g, b.geom);
+  const T* srt = static_cast<const T*>(src ? src : b.sorted);
+  if (P <= 4) {
+    const size_t lds = sizeof(double) * b.geom.edge[0] * b.geom.edge[1] * b.geom.edge[2];
+    hipLaunchKernelGGL((spread_brick<T, P>), dim3(b.geom.nbricks), dim3(256), lds, st, srt,
+                       b.offset, b.nbr, static_cast<T*>(grid), part2, g, b.geom);
+    return hipGetLastError();
+  }
+  const int ntile = (b.geom.edge[0] + P - 1) * (b.geom.edge[1] + P - 1) * (b.geom.edge[2] + P - 1);
+  hipLaunchKernelGGL((spread_home<T, P>), dim3(b.geom.nbricks), dim3(64),
+                     sizeof(double) * ntile, st, srt, b.offset, static_cast<T*>(b.tiles), g,
+                     b.geom);
+  hipLaunchKernelGGL((spread_combine<T, P>), dim3(b.geom.nbricks), dim3(256), 0, st,
+                     static_cast<const T*>(b.tiles), b.nbr, static_cast<T*>(grid), part2, g,
+                     b.geom);
   return hipGetLastError();
 }
 

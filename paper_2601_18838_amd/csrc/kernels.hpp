@@ -85,6 +85,7 @@ struct Bins {
   int* slot;      // [max_n] rank inside the brick
   int* perm;      // [max_n] sorted position -> caller index
   int* nbr;       // [3][nbmax][kNbrRec] home bricks reaching each owner brick
+  void* tiles;    // [nbricks][(edge + p - 1)^3] per-brick spread tiles (plan precision)
   void* sorted;   // [max_n][4] x, y, z, q in binned order (plan precision)
 };
 
