@@ -441,64 +441,72 @@ __global__ __launch_bounds__(64) void spread_home(const T* __restrict__ sorted,
 
 // Pass 2: one workgroup per grid brick sums, for each of its points and in a
 // fixed order, the tiles of the home bricks whose stencils reach it (the
-// per-axis lists nbr[axis][brick] = {count, b0, b1, ...}; a point is covered
-// by tile h at local coordinates (k_j - lo_h + P - 1) mod K_j + m K_j < H_j,
-// more than one image only when a stencil is wider than the grid).  Writes
-// every grid value once and the brick's FP64 (sum, max) to part2[brick].
+// per-axis lists nbr[axis][brick] = {count, b0, b1, ...}).  Point x_j of the
+// owner brick sits in tile h at local coordinate x_j + d_j(h) with
+// d_j(h) = (lo_owner - lo_h + P - 1) reduced so that the image lies in the
+// tile (when a stencil is wider than the grid, further images at + m K_j are
+// summed too).  Writes every grid value once and the brick's FP64 (sum, max)
+// to part2[brick].
 template <typename T, int P>
-__global__ __launch_bounds__(256) void spread_combine(const T* __restrict__ tiles,
+__global__ __launch_bounds__(512) void spread_combine(const T* __restrict__ tiles,
                                                       const int* __restrict__ nbr,
                                                       T* __restrict__ grid,
                                                       double* __restrict__ part2, GridGeom g,
                                                       BinGeom bg) {
-  __shared__ double red[256], mx[256];
+  __shared__ double red[512], mx[512];
+  __shared__ int dlt[3][kNbrRec], hid[3][kNbrRec];
   const int brick = xcd_order(blockIdx.x, gridDim.x);
   int own[3], rest = brick;
   own[2] = rest % bg.nb[2]; rest /= bg.nb[2];
   own[1] = rest % bg.nb[1];
   own[0] = rest / bg.nb[1];
-  int lo[3], ext[3], H[3];
+  int lo[3], ext[3], H[3], cnt[3];
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
     lo[j] = own[j] * bg.edge[j];
     ext[j] = min(bg.edge[j], g.K[j] - lo[j]);
     H[j] = bg.edge[j] + P - 1;
+    cnt[j] = nbr[kNbrRec * (j * bg.nbmax + own[j])];
   }
+  if (threadIdx.x < 3 * (kNbrRec - 1)) {
+    const int j = threadIdx.x / (kNbrRec - 1), x = threadIdx.x % (kNbrRec - 1);
+    const int* list = nbr + kNbrRec * (j * bg.nbmax + own[j]);
+    if (x < list[0]) {
+      // smallest non-negative image of lo_owner - lo_h + P - 1 modulo K_j
+      int d = lo[j] - list[1 + x] * bg.edge[j] + P - 1;
+      while (d < 0) d += g.K[j];
+      while (d >= g.K[j]) d -= g.K[j];
+      dlt[j][x] = d;
+      hid[j][x] = list[1 + x];
+    }
+  }
+  __syncthreads();
   const int ntile = H[0] * H[1] * H[2];
-  const int* n0 = nbr + kNbrRec * (0 * bg.nbmax + own[0]);
-  const int* n1 = nbr + kNbrRec * (1 * bg.nbmax + own[1]);
-  const int* n2 = nbr + kNbrRec * (2 * bg.nbmax + own[2]);
   double s = 0.0, m = 0.0;
   const int npts = ext[0] * ext[1] * ext[2];
   for (int e = threadIdx.x; e < npts; e += blockDim.x) {
-    const int k2 = lo[2] + e % ext[2], k1 = lo[1] + (e / ext[2]) % ext[1],
-              k0 = lo[0] + e / (ext[1] * ext[2]);
+    const int x2 = e % ext[2], x1 = (e / ext[2]) % ext[1], x0 = e / (ext[1] * ext[2]);
     double acc = 0.0;
-    for (int x = 0; x < n0[0]; ++x) {
-      const int h0 = n0[1 + x];
-      int r0 = k0 - h0 * bg.edge[0] + P - 1;
-      while (r0 < 0) r0 += g.K[0];
-      while (r0 >= g.K[0]) r0 -= g.K[0];
-      for (int l0 = r0; l0 < H[0]; l0 += g.K[0])
-        for (int y = 0; y < n1[0]; ++y) {
-          const int h1 = n1[1 + y];
-          int r1 = k1 - h1 * bg.edge[1] + P - 1;
-          while (r1 < 0) r1 += g.K[1];
-          while (r1 >= g.K[1]) r1 -= g.K[1];
-          for (int l1 = r1; l1 < H[1]; l1 += g.K[1])
-            for (int z = 0; z < n2[0]; ++z) {
-              const int h2 = n2[1 + z];
-              int r2 = k2 - h2 * bg.edge[2] + P - 1;
-              while (r2 < 0) r2 += g.K[2];
-              while (r2 >= g.K[2]) r2 -= g.K[2];
-              const T* t = tiles + static_cast<long>((h0 * bg.nb[1] + h1) * bg.nb[2] + h2) * ntile +
+    for (int a = 0; a < cnt[0]; ++a) {
+      int l0 = x0 + dlt[0][a];
+      if (l0 >= g.K[0]) l0 -= g.K[0];
+      for (; l0 < H[0]; l0 += g.K[0])
+        for (int b = 0; b < cnt[1]; ++b) {
+          int l1 = x1 + dlt[1][b];
+          if (l1 >= g.K[1]) l1 -= g.K[1];
+          for (; l1 < H[1]; l1 += g.K[1])
+            for (int c = 0; c < cnt[2]; ++c) {
+              int l2 = x2 + dlt[2][c];
+              if (l2 >= g.K[2]) l2 -= g.K[2];
+              const T* t = tiles + static_cast<long>((hid[0][a] * bg.nb[1] + hid[1][b]) * bg.nb[2] +
+                                                     hid[2][c]) * ntile +
                            (l0 * H[1] + l1) * H[2];
-              for (int l2 = r2; l2 < H[2]; l2 += g.K[2]) acc += static_cast<double>(t[l2]);
+              for (; l2 < H[2]; l2 += g.K[2]) acc += static_cast<double>(t[l2]);
             }
         }
     }
     const T v = static_cast<T>(acc);
-    grid[(static_cast<long>(k0) * g.K[1] + k1) * g.K[2] + k2] = v;
+    grid[(static_cast<long>(lo[0] + x0) * g.K[1] + lo[1] + x1) * g.K[2] + lo[2] + x2] = v;
     s += static_cast<double>(v);
     m = fmax(m, fabs(static_cast<double>(v)));
   }
@@ -873,7 +881,7 @@ hipError_t spread_brick_p(const GridGeom& g, const Bins& b, const void* src, voi
   hipLaunchKernelGGL((spread_home<T, P>), dim3(b.geom.nbricks), dim3(64),
                      sizeof(double) * ntile, st, srt, b.offset, static_cast<T*>(b.tiles), g,
                      b.geom);
-  hipLaunchKernelGGL((spread_combine<T, P>), dim3(b.geom.nbricks), dim3(256), 0, st,
+  hipLaunchKernelGGL((spread_combine<T, P>), dim3(b.geom.nbricks), dim3(512), 0, st,
                      static_cast<const T*>(b.tiles), b.nbr, static_cast<T*>(grid), part2, g,
                      b.geom);
   return hipGetLastError();
