@@ -120,7 +120,7 @@ struct kpme_plan_s {
   void* Q2g = nullptr;        // adjoint: spread of the upstream potential gradient
   void* Psig = nullptr;       // adjoint: Theta applied to it
   void* sorted2 = nullptr;    // adjoint: binned (x, y, z, g_pot)
-  double* part3 = nullptr;    // per-256-particle energy partial sums
+  double* part3 = nullptr;    // energy partial sums of the binned gather (per brick)
   int gather_blocks = 0;
   // per-stage hipEvent pairs recorded on the calling stream while profiling
   bool prof_on = false;
@@ -679,7 +679,9 @@ kpme_status kpme_plan_create(kpme_plan_t* plan, const double box[3], const int g
     if ((e = hipMemset(bn.count, 0, nb1 * sizeof(int))) != hipSuccess) break;
     if ((e = plan_alloc(pl, &tmp, 4 * static_cast<size_t>(bg.nbricks) * sizeof(double))) != hipSuccess) break;
     pl->part2 = static_cast<double*>(tmp);  // two (sum, max) sets: forward, adjoint
-    pl->gather_blocks = static_cast<int>((max_particles + 255) / 256);
+    // energy partials of the binned gather: one triple per brick or per 256
+    // particles (gather_partials)
+    pl->gather_blocks = std::max(static_cast<int>((max_particles + 255) / 256), bg.nbricks);
     if ((e = plan_alloc(pl, &tmp, 3 * static_cast<size_t>(pl->gather_blocks) * sizeof(double))) != hipSuccess) break;
     pl->part3 = static_cast<double*>(tmp);
     if ((e = plan_alloc(pl, &pl->Q2g, G * es)) != hipSuccess) break;
@@ -918,7 +920,7 @@ kpme_status kpme_evaluate(kpme_plan_t plan, int64_t n, const void* pos, const vo
   hipStream_t st = static_cast<hipStream_t>(stream);
   if ((s = do_spread(plan, n, pos, q, plan->Qg, st)) != KPME_SUCCESS) return s;
   if ((s = do_skp(plan, plan->Qg, plan->Phig, st, true)) != KPME_SUCCESS) return s;
-  const int nblk = static_cast<int>((n + 255) / 256);
+  const int nblk = n > 0 ? gather_partials(plan->prec, plan->p, plan->bins, n) : 0;
   if (pot || force || energy4) {
     // the particles are still binned from the spread: gather in binned order,
     // with the energy partial sums of each workgroup

@@ -615,6 +615,114 @@ __global__ __launch_bounds__(256) void gather_sorted(long n, const T* __restrict
   }
 }
 
+// Gather by brick: one workgroup per grid brick stages in LDS the potential
+// values that the stencils of the particles binned in it read -- the brick
+// and the P - 1 planes below it on each axis, H_j = edge_j + P - 1 points,
+// wrapped periodically -- then interpolates those particles from LDS (every
+// stencil point is inside the tile: no masking).  Results go back to the
+// caller's order through perm; each workgroup writes its FP64 partial sums
+// (q pot, q, q^2) to part3[brick] for the energy reduction.
+template <typename T, int P>
+__global__ __launch_bounds__(256) void gather_brick(const T* __restrict__ sorted,
+                                                    const int* __restrict__ offset,
+                                                    const int* __restrict__ perm,
+                                                    const T* __restrict__ grid,
+                                                    T* __restrict__ pot, T* __restrict__ force,
+                                                    double* __restrict__ part3, GridGeom g,
+                                                    BinGeom bg) {
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  T* tile = reinterpret_cast<T*>(smem);
+  __shared__ double red[3][256];
+  const int brick = xcd_order(blockIdx.x, gridDim.x);
+  int own[3], rest = brick;
+  own[2] = rest % bg.nb[2]; rest /= bg.nb[2];
+  own[1] = rest % bg.nb[1];
+  own[0] = rest / bg.nb[1];
+  int lo[3], H[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    lo[j] = own[j] * bg.edge[j];
+    H[j] = bg.edge[j] + P - 1;
+  }
+  const int K1 = g.K[0], K2 = g.K[1], K3 = g.K[2];
+  const int ntile = H[0] * H[1] * H[2];
+  for (int e = threadIdx.x; e < ntile; e += blockDim.x) {
+    int k2 = lo[2] - (P - 1) + e % H[2], k1 = lo[1] - (P - 1) + (e / H[2]) % H[1],
+        k0 = lo[0] - (P - 1) + e / (H[1] * H[2]);
+    while (k0 < 0) k0 += K1;
+    while (k0 >= K1) k0 -= K1;
+    while (k1 < 0) k1 += K2;
+    while (k1 >= K2) k1 -= K2;
+    while (k2 < 0) k2 += K3;
+    while (k2 >= K3) k2 -= K3;
+    tile[e] = grid[(static_cast<long>(k0) * K2 + k1) * K3 + k2];
+  }
+  __syncthreads();
+  double e0 = 0, e1 = 0, e2 = 0;
+  const int i0 = offset[brick], i1 = offset[brick + 1];
+  for (int s = i0 + threadIdx.x; s < i1; s += blockDim.x) {
+    T w[3][P], dw[3][P];
+    int l[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      int base;
+      const T f = scaled(sorted[4L * s + j], g.L[j], g.K[j], base);
+      bspline<T, P>(f, w[j], dw[j]);
+      // binned by the same floor: base lies in this brick (the clamp only
+      // keeps a corrupted input inside the tile)
+      l[j] = min(max(base - lo[j] + P - 1, P - 1), H[j] - 1);
+    }
+    T phi = 0, g0 = 0, g1 = 0, g2 = 0;
+    constexpr int UB = P <= 8 ? P : 1;
+    for (int a = 0; a < P; ++a) {
+      T sa = 0, sa1 = 0, sa2 = 0;
+#pragma unroll UB
+      for (int b = 0; b < P; ++b) {
+        const T* row = tile + ((l[0] - a) * H[1] + l[1] - b) * H[2] + l[2];
+        T sv = 0, s2 = 0;
+#pragma unroll
+        for (int c = 0; c < P; ++c) {
+          const T v = row[-c];
+          sv += w[2][c] * v;
+          s2 += dw[2][c] * v;
+        }
+        sa += w[1][b] * sv;
+        sa1 += dw[1][b] * sv;
+        sa2 += w[1][b] * s2;
+      }
+      phi += w[0][a] * sa;
+      g0 += dw[0][a] * sa;
+      g1 += w[0][a] * sa1;
+      g2 += w[0][a] * sa2;
+    }
+    const long i = perm[s];
+    const T qi = sorted[4L * s + 3];
+    if (pot) pot[i] = phi;
+    if (force) {
+      force[3 * i + 0] = -qi * g0 * static_cast<T>(K1 / g.L[0]);
+      force[3 * i + 1] = -qi * g1 * static_cast<T>(K2 / g.L[1]);
+      force[3 * i + 2] = -qi * g2 * static_cast<T>(K3 / g.L[2]);
+    }
+    const double qd = static_cast<double>(qi);
+    e0 += qd * static_cast<double>(phi);
+    e1 += qd;
+    e2 += qd * qd;
+  }
+  if (part3) {
+    red[0][threadIdx.x] = e0;
+    red[1][threadIdx.x] = e1;
+    red[2][threadIdx.x] = e2;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+      if (threadIdx.x < w)
+        for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0)
+      for (int k = 0; k < 3; ++k) part3[3 * brick + k] = red[k][0];
+  }
+}
+
 // sorted2[d] = (x, y, z, g[perm[d]]): the binned positions with a second
 // per-particle value (the adjoint's upstream potential gradient) as charge.
 template <typename T>
@@ -887,18 +995,36 @@ hipError_t spread_brick_p(const GridGeom& g, const Bins& b, const void* src, voi
   return hipGetLastError();
 }
 
+// Gather dispatch: for FP32 and spline orders above 4 the brick-tiled kernel
+// (each potential value staged once in LDS and read by every stencil that
+// needs it); otherwise particles read the grid directly (fewer particles per
+// brick and smaller stencils do not amortise the staging).
 template <typename T, int P>
-hipError_t gather_sorted_p(const GridGeom& g, const Bins& b, int64_t n, const void* grid,
-                           void* pot, void* force, double* part3, hipStream_t st) {
-  const unsigned blocks = static_cast<unsigned>((n + 255) / 256);
-  hipLaunchKernelGGL((gather_sorted<T, P>), dim3(blocks), dim3(256), 0, st,
-                     static_cast<long>(n), static_cast<const T*>(b.sorted), b.perm,
-                     static_cast<const T*>(grid), static_cast<T*>(pot), static_cast<T*>(force),
-                     part3, g);
+hipError_t gather_brick_p(const GridGeom& g, const Bins& b, int64_t n, const void* grid,
+                          void* pot, void* force, double* part3, hipStream_t st) {
+  if (sizeof(T) == 4 && P > 4) {
+    const int ntile = (b.geom.edge[0] + P - 1) * (b.geom.edge[1] + P - 1) * (b.geom.edge[2] + P - 1);
+    hipLaunchKernelGGL((gather_brick<T, P>), dim3(b.geom.nbricks), dim3(128), sizeof(T) * ntile,
+                       st, static_cast<const T*>(b.sorted), b.offset, b.perm,
+                       static_cast<const T*>(grid), static_cast<T*>(pot), static_cast<T*>(force),
+                       part3, g, b.geom);
+  } else {
+    const unsigned blocks = static_cast<unsigned>((n + 255) / 256);
+    hipLaunchKernelGGL((gather_sorted<T, P>), dim3(blocks), dim3(256), 0, st,
+                       static_cast<long>(n), static_cast<const T*>(b.sorted), b.perm,
+                       static_cast<const T*>(grid), static_cast<T*>(pot), static_cast<T*>(force),
+                       part3, g);
+  }
   return hipGetLastError();
 }
 
+
 }  // namespace
+
+// Number of energy partial-sum triples the binned gather writes.
+int gather_partials(int prec, int p, const Bins& b, int64_t n) {
+  return (prec != PREC_FP64 && p > 4) ? b.geom.nbricks : static_cast<int>((n + 255) / 256);
+}
 
 hipError_t launch_bin(int prec, const GridGeom& g, const Bins& b, int64_t n, const void* pos,
                       const void* q, hipStream_t st) {
@@ -924,11 +1050,11 @@ hipError_t launch_gather_binned(int prec, const GridGeom& g, const Bins& b, int6
                                 hipStream_t st) {
   if (n == 0) return hipSuccess;
   if (prec == PREC_FP64) {
-#define CALL(P) gather_sorted_p<double, P>(g, b, n, grid, pot, force, part3, st)
+#define CALL(P) gather_brick_p<double, P>(g, b, n, grid, pot, force, part3, st)
     KPME_ORDER_SWITCH(g.p, CALL)
 #undef CALL
   }
-#define CALL(P) gather_sorted_p<float, P>(g, b, n, grid, pot, force, part3, st)
+#define CALL(P) gather_brick_p<float, P>(g, b, n, grid, pot, force, part3, st)
   KPME_ORDER_SWITCH(g.p, CALL)
 #undef CALL
 }

@@ -102,10 +102,11 @@ hipError_t launch_bin(int prec, const GridGeom& g, const Bins& b, int64_t n, con
 // binned (x, y, z, charge) records to spread (NULL: the plan's own bins).
 hipError_t launch_spread_binned(int prec, const GridGeom& g, const Bins& b, void* grid,
                                 double* part2, hipStream_t st, const void* src = nullptr);
-// part3 (3 doubles per 256 particles, may be NULL): energy partial sums.
+// part3 (may be NULL): energy partial sums, gather_partials() triples.
 hipError_t launch_gather_binned(int prec, const GridGeom& g, const Bins& b, int64_t n,
                                 const void* grid, void* pot, void* force, double* part3,
                                 hipStream_t st);
+int gather_partials(int prec, int p, const Bins& b, int64_t n);
 hipError_t launch_resort_charges(int prec, const Bins& b, int64_t n, const void* gval,
                                  void* sorted2, hipStream_t st);
 hipError_t launch_gather_backward(int prec, const GridGeom& g, const Bins& b, int64_t n,
