@@ -169,7 +169,7 @@ __device__ __forceinline__ int brick_of_particle(const T* __restrict__ pos, long
 // Histogram with a per-workgroup LDS copy (up to kLdsHist bricks): each
 // workgroup ranks its particles inside the bricks in LDS, then reserves one
 // range per brick with a single global atomic.  count[] must be zero on entry.
-constexpr int kBinPer = 8;        // particles per thread
+constexpr int kBinPer = 4;        // particles per thread
 constexpr int kLdsHist = 8192;    // bricks handled with an LDS histogram
 
 template <typename T>
