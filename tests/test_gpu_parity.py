@@ -74,6 +74,9 @@ CASES = {
     "small_pm1": ((20.0, 20.0, 20.0), (16, 16, 16), 4, 0.35, 8, 1000, "pm1", 1),
     "ragged_noncubic": ((21.0, 26.0, 31.0), (20, 25, 30), 6, 0.6, 24, 1500, "water", 12),
     "tall_k1": ((40.0, 15.0, 22.0), (100, 36, 44), 4, 0.5, 30, 3000, "pm1", 13),
+    # order-6 stencils on 6- to 9-point axes: a brick tile (brick + 5 planes)
+    # is longer than the axis, so one grid point has several tile images
+    "wide_stencil": ((6.0, 7.0, 9.0), (6, 7, 9), 6, 0.9, 40, 300, "pm1", 14),
 }
 
 
