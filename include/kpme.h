@@ -206,7 +206,10 @@ kpme_status kpme_factors_compute(const double box[3], const int grid[3],
  * cost.  kpme_batch_evaluate records, for a new argument signature (n[] and
  * the five pointers), every system's kpme_evaluate launch sequence into one
  * HIP graph with parallel branches, and replays it as a single launch on
- * `stream`; an unchanged signature only replays.  pos/q/pot/force are device
+ * `stream`; an unchanged signature only replays.  A recording replaced by a
+ * new signature is kept (it may still be executing) and released after a
+ * device-wide synchronisation, every 8 replacements and at destroy, so a
+ * signature change never waits for the previous replay.  pos/q/pot/force are device
  * arrays concatenated in system order (offsets = prefix sums of n[s]);
  * energy4 (device) receives 4 doubles per system; pot/force/energy4 may be
  * NULL.  n[s] <= max_particles[s] (host array).  Errors as for the single

@@ -110,6 +110,10 @@ struct kpme_plan_s {
   void* Phi_part = nullptr;
   int* term_group = nullptr;
   int* part_begin = nullptr;
+  int* step_term = nullptr;   // split paths: stage-2 steps (see build_steps)
+  int* step_group = nullptr;
+  int* step_begin = nullptr;
+  int nsteps = 0, streams = 1;
   double* scratch = nullptr;  // 3 * kSumBlocks doubles
   double* scalars = nullptr;  // [0] sum(Q), [1..4] energy
   void* Qg = nullptr;         // internal grids
@@ -138,6 +142,7 @@ struct kpme_plan_s {
 };
 
 constexpr int kBatchBranches = 4;  // parallel branches of the batch graph
+constexpr size_t kRetiredCap = 8;  // replaced graph recordings kept before a release
 constexpr uint32_t kBatchMagic = 0x4b42544eu;
 
 struct kpme_batch_s {
@@ -150,7 +155,9 @@ struct kpme_batch_s {
   hipEvent_t fork = nullptr;
   hipEvent_t join[kBatchBranches] = {};
   hipGraphExec_t exec = nullptr;       // recorded graph for the last signature
-  hipEvent_t launched = nullptr;       // recorded after each launch of exec
+  // recordings replaced by a newer one; released only after a device-wide
+  // synchronisation (every kRetiredCap replacements, and at destroy)
+  std::vector<hipGraphExec_t> retired;
   std::vector<int64_t> sig_n;
   const void* sig_ptr[5] = {};
 };
@@ -211,7 +218,8 @@ void batch_free(kpme_batch_s* b) {
   (void)hipSetDevice(b->device);
   (void)hipDeviceSynchronize();
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
-  if (b->launched) (void)hipEventDestroy(b->launched);
+  for (hipGraphExec_t x : b->retired) (void)hipGraphExecDestroy(x);
+  b->retired.clear();
   for (int k = 0; k < kBatchBranches; ++k) {
     if (b->branch[k]) (void)hipStreamDestroy(b->branch[k]);
     if (b->join[k]) (void)hipEventDestroy(b->join[k]);
@@ -297,6 +305,26 @@ void tune_store(const std::string& key, int value) {
   if (const char* path = std::getenv("KPME_TUNE_CACHE")) {
     std::ofstream out(path, std::ios::app);
     out << key << " " << value << "\n";
+  }
+}
+
+// Stage-2 steps of the split paths: the terms of each outer-SVD group (in
+// device order) taken `streams` at a time; a group's last step may leave
+// streams idle (-1).  Steps never mix groups, so all streams of a workgroup
+// multiply the same Y slab.
+void build_steps(const std::vector<int>& group_of, int streams, std::vector<int>& term,
+                 std::vector<int>& group) {
+  term.clear();
+  group.clear();
+  const int R = static_cast<int>(group_of.size());
+  for (int a = 0; a < R;) {
+    int b = a;
+    while (b < R && group_of[b] == group_of[a]) ++b;
+    for (int t = a; t < b; t += streams) {
+      for (int k = 0; k < streams; ++k) term.push_back(t + k < b ? t + k : -1);
+      group.push_back(group_of[a]);
+    }
+    a = b;
   }
 }
 
@@ -445,6 +473,13 @@ kpme_status kpme_plan_create(kpme_plan_t* plan, const double box[3], const int g
     }
   }
   const std::vector<int> pb = split_range(R, pl->nparts, pl->max_parts);
+  std::vector<int> step_term, step_group;
+  if (precision == KPME_BF16X3 || precision == KPME_FP16X3) {
+    pl->streams = x3_streams(K1P, K2P);
+    build_steps(group_of, pl->streams, step_term, step_group);
+  }
+  pl->nsteps = static_cast<int>(step_group.size());
+  const std::vector<int> sb = split_range(pl->nsteps, pl->nparts, pl->max_parts);
 
   // Circulant factors, zero padded: A_t (omega folded in), B_t, C_g.
   const size_t nA = static_cast<size_t>(R) * K1P * K1P, nB = static_cast<size_t>(R) * K2P * K2P;
@@ -647,6 +682,19 @@ kpme_status kpme_plan_create(kpme_plan_t* plan, const double box[3], const int g
     if ((e = plan_alloc(pl, &tmp, pb.size() * sizeof(int))) != hipSuccess) break;
     pl->part_begin = static_cast<int*>(tmp);
     if ((e = hipMemcpy(tmp, pb.data(), pb.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess) break;
+    if (pl->nsteps > 0) {
+      if ((e = plan_alloc(pl, &tmp, step_term.size() * sizeof(int))) != hipSuccess) break;
+      pl->step_term = static_cast<int*>(tmp);
+      if ((e = hipMemcpy(tmp, step_term.data(), step_term.size() * sizeof(int),
+                         hipMemcpyHostToDevice)) != hipSuccess) break;
+      if ((e = plan_alloc(pl, &tmp, step_group.size() * sizeof(int))) != hipSuccess) break;
+      pl->step_group = static_cast<int*>(tmp);
+      if ((e = hipMemcpy(tmp, step_group.data(), step_group.size() * sizeof(int),
+                         hipMemcpyHostToDevice)) != hipSuccess) break;
+      if ((e = plan_alloc(pl, &tmp, sb.size() * sizeof(int))) != hipSuccess) break;
+      pl->step_begin = static_cast<int*>(tmp);
+      if ((e = hipMemcpy(tmp, sb.data(), sb.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess) break;
+    }
     if ((e = plan_alloc(pl, &tmp, 3 * kSumBlocks * sizeof(double))) != hipSuccess) break;
     pl->scratch = static_cast<double*>(tmp);
     if ((e = plan_alloc(pl, &tmp, 8 * sizeof(double))) != hipSuccess) break;
@@ -762,6 +810,10 @@ kpme_status do_skp(kpme_plan_t plan, const void* in, void* out, hipStream_t st,
   a.alen = plan->alen;
   a.term_group = plan->term_group;
   a.part_begin = plan->part_begin;
+  a.x3_streams = plan->streams;
+  a.step_term = plan->step_term;
+  a.step_group = plan->step_group;
+  a.step_begin = plan->step_begin;
   a.scratch = plan->scratch;
   a.sumQ = scalars;
   a.c0 = plan->zero_mode;
@@ -809,6 +861,10 @@ hipError_t set_parts(kpme_plan_t plan, int np) {
   const std::vector<int> pb = split_range(plan->R, np, plan->max_parts);
   hipError_t e = hipMemcpy(plan->part_begin, pb.data(), pb.size() * sizeof(int),
                            hipMemcpyHostToDevice);
+  if (e == hipSuccess && plan->nsteps > 0) {
+    const std::vector<int> sb = split_range(plan->nsteps, np, plan->max_parts);
+    e = hipMemcpy(plan->step_begin, sb.data(), sb.size() * sizeof(int), hipMemcpyHostToDevice);
+  }
   if (e == hipSuccess) plan->nparts = np;
   return e;
 }
@@ -1071,8 +1127,7 @@ kpme_status kpme_batch_create(kpme_batch_t* batch, int count, const double* box3
     }
   }
   if (hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&b->launched, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess) {
     batch_free(b);
     return fail(KPME_ERROR_DEVICE, "stream/event creation failed");
   }
@@ -1127,10 +1182,14 @@ kpme_status kpme_batch_evaluate(kpme_batch_t batch, const int64_t* n, const void
                     std::equal(ptrs, ptrs + 5, batch->sig_ptr);
   if (!same) {
     if (batch->exec) {
-      // the previous recording may still be executing: wait for its last
-      // launch before releasing it
-      (void)hipEventSynchronize(batch->launched);
-      (void)hipGraphExecDestroy(batch->exec);
+      // the previous recording may still be executing: keep it, and release
+      // the kept ones only after the device has drained
+      if (batch->retired.size() >= kRetiredCap) {
+        if (hipDeviceSynchronize() != hipSuccess) return fail(KPME_ERROR_DEVICE, "hipDeviceSynchronize");
+        for (hipGraphExec_t x : batch->retired) (void)hipGraphExecDestroy(x);
+        batch->retired.clear();
+      }
+      batch->retired.push_back(batch->exec);
       batch->exec = nullptr;
     }
     const size_t es = batch->plans[0]->esize();
@@ -1170,9 +1229,7 @@ kpme_status kpme_batch_evaluate(kpme_batch_t batch, const int64_t* n, const void
     batch->sig_n = sig;
     std::copy(ptrs, ptrs + 5, batch->sig_ptr);
   }
-  hipError_t e = hipGraphLaunch(batch->exec, st);
-  if (e == hipSuccess) e = hipEventRecord(batch->launched, st);
-  return from_hip(e, "graph launch");
+  return from_hip(hipGraphLaunch(batch->exec, st), "graph launch");
 }
 
 }  // extern "C"

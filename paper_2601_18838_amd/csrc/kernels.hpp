@@ -30,6 +30,11 @@ struct SkpArgs {
   void* Phi_part;        // [nparts][K3][K1][K2]
   const int* term_group; // [R] group of each term (terms sorted by group)
   const int* part_begin; // [nparts + 1]
+  // split-precision stage 2: steps of x3_streams terms of one group
+  int x3_streams;
+  const int* step_term;  // [nsteps * x3_streams], -1 = idle stream
+  const int* step_group; // [nsteps]
+  const int* step_begin; // [nparts + 1]
   double* scratch;       // >= kSumBlocks doubles
   double* sumQ;          // 2 doubles: sum(Q), then the FP16X3 grid scale
   double c0;             // theta_hat_R(0)
@@ -52,6 +57,11 @@ inline int x3_alen(int K1P) { return 2 * K1P + 16; }
 // term: [B copies | A copies], 8 * blen + 8 + 4 * alen + 8 halves.
 constexpr int kX3ShiftB = 8, kX3ShiftA = 4;
 inline int x3_plane(int K1P, int K2P) { return 8 * x3_blen(K2P) + 8 + 4 * x3_alen(K1P) + 8; }
+// Split-precision stage 2 shape: column tiles of 16 per wave (CT) and term
+// streams per workgroup (NS).  96 x 96 slabs: two streams of two 48-column
+// waves (four-wave workgroups, two per CU: two waves on every SIMD).
+constexpr int x3_ct(int K1P, int K2P) { return (K1P == 96 && K2P == 96) ? 3 : 2; }
+constexpr int x3_streams(int K1P, int K2P) { return (K1P == 96 && K2P == 96) ? 2 : 1; }
 
 hipError_t launch_skp_sum(const SkpArgs& a, hipStream_t st);
 hipError_t launch_skp_stage1(const SkpArgs& a, hipStream_t st);

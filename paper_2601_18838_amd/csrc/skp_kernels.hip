@@ -331,8 +331,9 @@ __global__ __launch_bounds__(256) void stage1_k4(const T* __restrict__ Q,
 }
 
 // ----------------------------------------------------------------------------
-// Stage 2, split precision.  One workgroup = (slab s, term part); wave w owns
-// output columns [32 w, 32 w + 32).
+// Stage 2, split precision.  One workgroup = (slab s, range of steps); it has
+// NS streams of WPS = K2P / (16 CT) waves, and wave w of a stream owns output
+// columns [16 CT w, 16 CT (w + 1)).
 //
 // A_t and B_t are circulant: A_t[k1][g1] = a_t((k1 - g1) mod K1).  Each term
 // is stored as shifted copies of its reversed generating vectors,
@@ -343,35 +344,46 @@ __global__ __launch_bounds__(256) void stage1_k4(const T* __restrict__ Q,
 // registers while the current term computes (double-buffered LDS).  The Y
 // slab of the current outer-SVD group stays in LDS.  T is multiplied by st
 // (a power of two, FP16X3) before its split.
-// K1P = 128 runs with at most 256 threads (K2P <= 128) so that one wave per
-// SIMD may use the full register file without spilling.  K1P = 16 RT and
-// K2P = 32 NKC are compile-time, so every circulant fragment offset is a
-// term-independent value computed once per thread, and the fragments of the
-// next step are loaded while the current step's MFMAs run.
-template <typename H, int RT, int NKC>
-__global__ __launch_bounds__(RT >= 8 ? 256 : 512) void stage2_x3(
+//
+// A step holds NS terms of one outer-SVD group (-1: the stream idles for that
+// step); stream k computes the k-th term of every step on the shared Y slab
+// with its own vector buffers, and the streams' sums are added through LDS
+// at the end, in stream order.  Every wave reads the whole Y slab and its
+// columns' B fragments, and the A fragments of all rows, per term: wider
+// column tiles (CT) cut that LDS traffic per term, at the cost of
+// accumulator registers.  K1P = 128 runs with one wave per SIMD, which may
+// then use the full register file.
+template <typename H, int RT, int NKC, int CT, int NS>
+__global__ __launch_bounds__(64 * (2 * NKC / CT) * NS)
+__attribute__((amdgpu_waves_per_eu(RT >= 8 ? 1 : 2))) void stage2_x3(
     const H* __restrict__ Yhi, const H* __restrict__ Ylo, const H* __restrict__ vec,
-    const int* __restrict__ term_group, const int* __restrict__ part_begin,
-    float* __restrict__ Phi_part, int K1, int K2, int K3, float st) {
+    const int* __restrict__ step_term, const int* __restrict__ step_group,
+    const int* __restrict__ step_begin, float* __restrict__ Phi_part, int K1, int K2, int K3,
+    float st) {
   typedef typename HVec<H>::v8 v8;
   typedef typename HVec<H>::v4 v4;
-  constexpr int K1P = RT * 16, K2P = NKC * 32, CT = 2;
+  static_assert((2 * NKC) % CT == 0, "column tiles must divide K2P / 16");
+  constexpr int K1P = RT * 16, K2P = NKC * 32;
+  constexpr int WPS = 2 * NKC / CT;             // waves per stream
   constexpr int blen = 2 * K2P + 8, alen = 2 * K1P + 16;  // x3_blen, x3_alen
   constexpr int plane = 8 * blen + 8 + 4 * alen + 8;  // x3_plane: halves per plane
   constexpr int tsz = 2 * plane;                // halves per term (hi plane, lo plane)
-  constexpr int PF = (tsz / 8 + 64 * NKC - 1) / (64 * NKC);  // 16-byte chunks per thread
+  constexpr int STHR = 64 * WPS;                // threads per stream
+  constexpr int PF = (tsz / 8 + STHR - 1) / STHR;  // 16-byte chunks per stream thread
   constexpr int YSTR = K2P + 8;
   extern __shared__ __attribute__((aligned(16))) char smem[];
   H* Ysh = reinterpret_cast<H*>(smem);
   H* Ysl = Ysh + K1P * YSTR;
-  H* vbuf = Ysl + K1P * YSTR;                   // [2][tsz]
+  H* vbase = Ysl + K1P * YSTR;                  // [NS][2][tsz]
   // logical order: the term ranges of one slab are consecutive (one XCD and
   // L2 for the slab's Y planes)
   const int L = xcd_order(linear_block(), num_blocks());
   const int s = L / gridDim.y, part = L % gridDim.y;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int lane = tid & 63, wave = tid >> 6, q = lane >> 4, m = lane & 15;
-  const int col0 = wave * 16 * CT;
+  const int strm = wave / WPS, cw = wave - strm * WPS, stid = tid - strm * STHR;
+  const int col0 = cw * 16 * CT;
+  H* vbuf = vbase + strm * 2 * tsz;
   constexpr long slab = static_cast<long>(K1P) * K2P;
   constexpr int nchunk = tsz / 8;
   floatx4 acc2[RT][CT];
@@ -379,26 +391,33 @@ __global__ __launch_bounds__(RT >= 8 ? 256 : 512) void stage2_x3(
   for (int i = 0; i < RT; ++i)
 #pragma unroll
     for (int j = 0; j < CT; ++j) acc2[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-  const int t0 = part_begin[part], t1 = part_begin[part + 1];
-  // Fragment offsets (halves) into one plane of a term's vectors:
-  //   B fragment (kc, j): entries b((k2 - g2) mod K2) for g2 = 32 kc + 8 q + e,
-  //     k2 = col0 + 16 j + m, read from copy (y & 7) at (y & ~7) with
-  //     y = (32 kc + 8 q - col0 - 16 j - m) mod K2;
-  //   A fragment halves for a K offset 16 d: y = (4 q - m + 16 d) mod K1,
-  //     copy (y & 3) at (y & ~3); d = 2 c - i (first half), 2 c - i + 1 (second).
+  const int s0 = step_begin[part], s1 = step_begin[part + 1];
+  // Fragment bases (halves) into one plane of a term's vectors.  Copy s of
+  // the B vector holds at x the entry for (k2 - g2) = x + s - K2P, so the B
+  // fragment (kc, j) -- g2 = 32 kc + 8 q + e, k2 = col0 + 16 j + m -- starts
+  // at u = uB + 32 kc - 16 j in copy (u & 7) at (u & ~7) with
+  // uB = 8 q - col0 - m + K2P; the kc, j part is a multiple of 8, hence a
+  // constant offset from offB.  Likewise the A half-fragment at K offset 16 d
+  // (d = 2 c - i, then 2 c - i + 1) starts at uA + 16 d, uA = 4 q - m + K1P,
+  // in copy (uA & 3).  Copies s >= 1 start kX3ShiftB / kX3ShiftA halves late.
   const int uB = 8 * q - col0 - m + K2P, uA = 4 * q - m + K1P;
   const int sB = uB & 7, sA = uA & 3;
   const int offB = sB * blen + (sB ? kX3ShiftB : 0) + (uB & ~7) - 16;
   const int offA = 8 * blen + 8 + sA * alen + (sA ? kX3ShiftA : 0) + (uA & ~3) - 16 * (RT - 1);
-  // prologue: term t0's vectors into buffer 0
-  for (int c = tid; c < nchunk; c += nthr)
-    if (t0 < t1)
-      *reinterpret_cast<v8*>(&vbuf[8 * c]) =
-          *reinterpret_cast<const v8*>(&vec[static_cast<long>(t0) * tsz + 8 * c]);
+  // prologue: this stream's first term's vectors into its buffer 0
+  if (s0 < s1) {
+    const int tf = step_term[s0 * NS + strm];
+    if (tf >= 0)
+      for (int c = stid; c < nchunk; c += STHR)
+        *reinterpret_cast<v8*>(&vbuf[8 * c]) =
+            *reinterpret_cast<const v8*>(&vec[static_cast<long>(tf) * tsz + 8 * c]);
+  }
   int cur = -1;
-  for (int t = t0; t < t1; ++t) {
-    const int g = term_group[t];
-    const int buf = (t - t0) & 1;
+  for (int sp = s0; sp < s1; ++sp) {
+    const int g = step_group[sp];
+    const int t = step_term[sp * NS + strm];
+    const int tn = (sp + 1 < s1) ? step_term[(sp + 1) * NS + strm] : -1;
+    const int buf = (sp - s0) & 1;
     __syncthreads();
     if (g != cur) {
       const H* yh = Yhi + (static_cast<long>(g) * K3 + s) * slab;
@@ -414,16 +433,17 @@ __global__ __launch_bounds__(RT >= 8 ? 256 : 512) void stage2_x3(
       cur = g;
       __syncthreads();
     }
-    // prefetch the next term's vectors into registers
+    // prefetch this stream's next term's vectors into registers
     v8 pre[PF];
-    if (t + 1 < t1) {
-      const H* src = vec + static_cast<long>(t + 1) * tsz;
+    if (tn >= 0) {
+      const H* src = vec + static_cast<long>(tn) * tsz;
 #pragma unroll
       for (int k = 0; k < PF; ++k) {
-        const int c = tid + k * nthr;
+        const int c = stid + k * STHR;
         if (c < nchunk) pre[k] = *reinterpret_cast<const v8*>(&src[8 * c]);
       }
     }
+    if (t >= 0) {
     const H* Bvh = vbuf + buf * tsz + offB;
     const H* Bvl = Bvh + plane;
     const H* Avh = vbuf + buf * tsz + offA;
@@ -518,16 +538,45 @@ __global__ __launch_bounds__(RT >= 8 ? 256 : 512) void stage2_x3(
       al = nl;
       __builtin_amdgcn_sched_barrier(0);
     }
+    }  // t >= 0
     // publish the prefetched vectors into the other buffer (read after the
-    // barrier at the top of the next iteration)
-    if (t + 1 < t1) {
+    // barrier at the top of the next step)
+    if (tn >= 0) {
       H* dst = vbuf + (buf ^ 1) * tsz;
 #pragma unroll
       for (int k = 0; k < PF; ++k) {
-        const int c = tid + k * nthr;
+        const int c = stid + k * STHR;
         if (c < nchunk) *reinterpret_cast<v8*>(&dst[8 * c]) = pre[k];
       }
     }
+  }
+  if (NS > 1) {
+    // streams 1.. hand their sums to stream 0 through the (now free) Y area in
+    // a lane-private layout; stream 0 adds them in stream order
+    float* red = reinterpret_cast<float*>(smem);
+    for (int k = 1; k < NS; ++k) {
+      __syncthreads();
+      if (strm == k) {
+#pragma unroll
+        for (int i = 0; i < RT; ++i)
+#pragma unroll
+          for (int j = 0; j < CT; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              red[(((cw * RT + i) * CT + j) * 4 + r) * 64 + lane] = acc2[i][j][r];
+      }
+      __syncthreads();
+      if (strm == 0) {
+#pragma unroll
+        for (int i = 0; i < RT; ++i)
+#pragma unroll
+          for (int j = 0; j < CT; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              acc2[i][j][r] += red[(((cw * RT + i) * CT + j) * 4 + r) * 64 + lane];
+      }
+    }
+    if (strm != 0) return;
   }
   float* out = Phi_part + (static_cast<long>(part) * K3 + s) * K1 * K2;
 #pragma unroll
@@ -542,6 +591,8 @@ __global__ __launch_bounds__(RT >= 8 ? 256 : 512) void stage2_x3(
       }
     }
 }
+
+// Stage 2, FP32 / FP64 with the 16x16x4 MFMAs.  The factors are symmetric,
 
 // Stage 2, FP32 / FP64 with the 16x16x4 MFMAs.  The factors are symmetric,
 // which lets the global-memory operand reads run along rows (coalesced).
@@ -750,18 +801,18 @@ hipError_t set_lds(K kernel, size_t bytes) {
 
 template <typename H, int RT, int NKC>
 hipError_t launch_s2_x3(const SkpArgs& a, hipStream_t st) {
-  const int K1P = RT * 16;
-  const size_t tsz = 2 * static_cast<size_t>(x3_plane(K1P, a.K2P));
-  const size_t lds = sizeof(H) * (2 * static_cast<size_t>(K1P) * (32 * NKC + 8) + 2 * tsz);
-  hipError_t e = set_lds(stage2_x3<H, RT, NKC>, lds);
+  constexpr int K1P = RT * 16, K2P = NKC * 32;
+  constexpr int CT = x3_ct(K1P, K2P), NS = x3_streams(K1P, K2P);
+  const size_t tsz = 2 * static_cast<size_t>(x3_plane(K1P, K2P));
+  const size_t lds = sizeof(H) * (2 * static_cast<size_t>(K1P) * (K2P + 8) + 2 * NS * tsz);
+  hipError_t e = set_lds(stage2_x3<H, RT, NKC, CT, NS>, lds);
   if (e != hipSuccess) return e;
-  const int threads = 64 * NKC;
-  if (threads > (RT >= 8 ? 256 : 512) || a.K2P != 32 * NKC || a.blen != x3_blen(a.K2P) ||
-      a.alen != x3_alen(K1P))
+  const int threads = 64 * (K2P / (16 * CT)) * NS;
+  if (a.K2P != K2P || a.x3_streams != NS || a.blen != x3_blen(K2P) || a.alen != x3_alen(K1P))
     return hipErrorInvalidValue;
-  hipLaunchKernelGGL((stage2_x3<H, RT, NKC>), dim3(a.K[2], a.nparts), dim3(threads), lds, st,
-                     static_cast<const H*>(a.Y[0]), static_cast<const H*>(a.Y[1]),
-                     static_cast<const H*>(a.vec), a.term_group, a.part_begin,
+  hipLaunchKernelGGL((stage2_x3<H, RT, NKC, CT, NS>), dim3(a.K[2], a.nparts), dim3(threads),
+                     lds, st, static_cast<const H*>(a.Y[0]), static_cast<const H*>(a.Y[1]),
+                     static_cast<const H*>(a.vec), a.step_term, a.step_group, a.step_begin,
                      static_cast<float*>(a.Phi_part), a.K[0], a.K[1], a.K[2], a.st);
   return hipGetLastError();
 }
@@ -811,9 +862,9 @@ hipError_t dispatch_s2(const SkpArgs& a, hipStream_t st) {
 
 size_t stage2_lds_bytes(int prec, int K1P, int K2P) {
   if (prec == PREC_BF16X3 || prec == PREC_FP16X3) {
-    // Y slab (two planes) + two buffers of circulant vectors
+    // Y slab (two planes) + two buffers of circulant vectors per stream
     const size_t tsz = 2 * static_cast<size_t>(x3_plane(K1P, K2P));
-    return 2 * (2 * static_cast<size_t>(K1P) * (K2P + 8) + 2 * tsz);
+    return 2 * (2 * static_cast<size_t>(K1P) * (K2P + 8) + 2 * x3_streams(K1P, K2P) * tsz);
   }
   if (prec == PREC_FP32) return sizeof(float) * static_cast<size_t>(K1P) * (K2P + 1);
   return sizeof(double) * static_cast<size_t>(K1P) * (K2P + 1);
