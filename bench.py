@@ -263,7 +263,8 @@ def main():
                    "beta": wl.beta, "box": list(wl.box), "rank": R, "r0": info["r0"],
                    "rank_rule": f"relative Frobenius tail <= {wl.tol:g}",
                    "precision": mixed, "reference": "fp64 GPU path at equal R",
-                   "stage2_parts": plans[mixed].stage2_parts()},
+                   "stage2_parts": plans[mixed].stage2_parts(),
+                   "stage1_split": plans[mixed].stage1_split()},
         "ns_per_particle": t_mixed * 1e9 / n,
         "fp64_evals_per_s": 1.0 / t_ref,
         "fp64_ns_per_particle": t_ref * 1e9 / n,

@@ -94,6 +94,7 @@ struct kpme_plan_s {
   double box[3] = {0, 0, 0};
   double beta = 0;
   int R = 0, r0 = 0, total_terms = 0, nparts = 1, max_parts = 1;
+  int s1_split = 2;  // split stage 1: workgroups per position tile
   int64_t max_n = 0;
   double theta_norm = 0, trunc_err = 0, zero_mode = 0;
   float sy = 1.f, st = 1.f;   // FP16X3 powers of two for Y and T
@@ -271,11 +272,28 @@ constexpr int kMaxParts = 8;  // stage-2 partial-slab buffers per plan
 std::mutex g_tune_mu;
 std::map<std::string, int>* g_tune = nullptr;
 
-std::string tune_key(const kpme_plan_s* pl) {
+// what: "s2parts" (stage-2 term ranges) or "s1split" (stage-1 split)
+std::string tune_key(const kpme_plan_s* pl, const char* what = "s2parts") {
   char buf[160];
-  std::snprintf(buf, sizeof(buf), "s2parts_%dx%dx%d_p%d_R%d_r%d_prec%d", pl->K[0], pl->K[1],
+  std::snprintf(buf, sizeof(buf), "%s_%dx%dx%d_p%d_R%d_r%d_prec%d", what, pl->K[0], pl->K[1],
                 pl->K[2], pl->p, pl->R, pl->r0, pl->prec);
   return buf;
+}
+
+// Default stage-1 split (split precisions): the candidate with the least
+// modelled time, (largest C-tile count of a wave + 1 for the Q tile) x
+// (workgroups per CU, rounded up), over 256 CUs.
+int default_s1_split(int r0, int K3, int K1P, int K2P) {
+  const int ntiles = (r0 * K3 + 15) / 16;
+  const long ptiles = static_cast<long>(K1P) * K2P / 64;
+  int best = 2;
+  long best_cost = -1;
+  for (int s : {2, 3, 4, 6}) {
+    const long per_wave = ((ntiles + s - 1) / s + 3) / 4;
+    const long cost = (per_wave + 1) * ((s * ptiles + 255) / 256);
+    if (best_cost < 0 || cost < best_cost) { best = s; best_cost = cost; }
+  }
+  return best;
 }
 
 void tune_load_locked() {
@@ -466,6 +484,13 @@ kpme_status kpme_plan_create(kpme_plan_t* plan, const double box[3], const int g
     pl->max_parts = std::max(pl->nparts, std::min(R, kMaxParts));
     int cached = 0;
     if (tune_lookup(tune_key(pl), &cached) && cached >= 1) pl->nparts = std::min(cached, pl->max_parts);
+    pl->s1_split = default_s1_split(r0, K3, K1P, K2P);
+    if (tune_lookup(tune_key(pl, "s1split"), &cached) && cached >= 1) pl->s1_split = cached;
+    // tuning override: workgroups per position tile in split stage 1
+    if (const char* env = std::getenv("KPME_STAGE1_SPLIT")) {
+      const int v = std::atoi(env);
+      if (v >= 1) pl->s1_split = v;
+    }
     // tuning override: number of term ranges per slab in stage 2
     if (const char* env = std::getenv("KPME_STAGE2_PARTS")) {
       const int v = std::atoi(env);
@@ -802,6 +827,7 @@ kpme_status do_skp(kpme_plan_t plan, const void* in, void* out, hipStream_t st,
   for (int j = 0; j < 3; ++j) a.K[j] = plan->K[j];
   a.K1P = plan->K1P; a.K2P = plan->K2P; a.K3P = plan->K3P;
   a.r0 = plan->r0; a.R = plan->R; a.nparts = plan->nparts;
+  a.s1_split = plan->s1_split;
   a.Q = in; a.Phi = out;
   for (int k = 0; k < 2; ++k) { a.A[k] = plan->A[k]; a.B[k] = plan->B[k]; a.C[k] = plan->C[k]; a.Y[k] = plan->Y[k]; }
   a.Phi_part = plan->Phi_part;
@@ -882,16 +908,10 @@ extern "C" kpme_status kpme_plan_autotune(kpme_plan_t plan, void* stream) {
     (void)hipEventDestroy(e0);
     return fail(KPME_ERROR_DEVICE, "hipEventCreate");
   }
-  // time every candidate; keep the smallest split within 3% of the fastest
-  // (fewer partial slabs to write and sum, and a choice that is stable
-  // against timing noise)
-  std::vector<std::pair<int, float>> timed;
   const bool was_on = plan->prof_on;
   plan->prof_on = false;
-  for (int c : cands) {
-    if (c > plan->max_parts || c > plan->R) continue;
-    hipError_t e = set_parts(plan, c);
-    if (e != hipSuccess) { s = from_hip(e, "autotune"); break; }
+  // milliseconds of 5 SKP applications after 2 untimed ones; < 0 on failure
+  auto time_skp = [&]() -> float {
     for (int w = 0; w < 2 && s == KPME_SUCCESS; ++w) s = do_skp(plan, plan->Qg, plan->Phig, st);
     (void)hipEventRecord(e0, st);
     for (int r = 0; r < 5 && s == KPME_SUCCESS; ++r) s = do_skp(plan, plan->Qg, plan->Phig, st);
@@ -899,8 +919,20 @@ extern "C" kpme_status kpme_plan_autotune(kpme_plan_t plan, void* stream) {
     float ms = 0.f;
     if (s == KPME_SUCCESS && hipEventSynchronize(e1) == hipSuccess &&
         hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
-      timed.emplace_back(c, ms);
+      return ms;
+    return -1.f;
+  };
+  // stage-2 term ranges: time every candidate; keep the smallest split within
+  // 3% of the fastest (fewer partial slabs to write and sum, and a choice
+  // that is stable against timing noise)
+  std::vector<std::pair<int, float>> timed;
+  for (int c : cands) {
+    if (c > plan->max_parts || c > plan->R) continue;
+    hipError_t e = set_parts(plan, c);
+    if (e != hipSuccess) { s = from_hip(e, "autotune"); break; }
+    const float ms = time_skp();
     if (s != KPME_SUCCESS) break;
+    if (ms >= 0.f) timed.emplace_back(c, ms);
   }
   int best = plan->nparts;
   if (!timed.empty()) {
@@ -909,12 +941,28 @@ extern "C" kpme_status kpme_plan_autotune(kpme_plan_t plan, void* stream) {
     for (const auto& t : timed)
       if (t.second <= 1.03f * fastest) { best = t.first; break; }  // cands ascend
   }
+  if (s == KPME_SUCCESS) {
+    hipError_t e = set_parts(plan, best);
+    if (e != hipSuccess) s = from_hip(e, "autotune");
+  }
+  // stage-1 split (split precisions with the LDS-tiled stage 1): the fastest
+  const bool s1_tiled = (plan->prec == PREC_BF16X3 || plan->prec == PREC_FP16X3) && plan->K3P <= 128;
+  if (s == KPME_SUCCESS && s1_tiled) {
+    int best1 = plan->s1_split;
+    float fastest = -1.f;
+    for (int c : {1, 2, 3, 4, 6}) {
+      plan->s1_split = c;
+      const float ms = time_skp();
+      if (s != KPME_SUCCESS) break;
+      if (ms >= 0.f && (fastest < 0.f || ms < fastest)) { fastest = ms; best1 = c; }
+    }
+    plan->s1_split = best1;
+  }
   plan->prof_on = was_on;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (s != KPME_SUCCESS) return s;
-  hipError_t e = set_parts(plan, best);
-  if (e != hipSuccess) return from_hip(e, "autotune");
+  if (s1_tiled) tune_store(tune_key(plan, "s1split"), plan->s1_split);
   tune_store(tune_key(plan), best);
   return KPME_SUCCESS;
 }
@@ -923,8 +971,9 @@ extern "C" int kpme_plan_stage2_parts(kpme_plan_t plan) {
   return (plan && plan->magic == kMagic) ? plan->nparts : -1;
 }
 
-namespace {
-}  // namespace
+extern "C" int kpme_plan_stage1_split(kpme_plan_t plan) {
+  return (plan && plan->magic == kMagic) ? plan->s1_split : -1;
+}
 
 kpme_status kpme_spread(kpme_plan_t plan, int64_t n, const void* pos, const void* q, void* grid,
                         void* stream) {
@@ -1099,17 +1148,18 @@ kpme_status kpme_batch_create(kpme_batch_t* batch, int count, const double* box3
     b->plans.push_back(pl);
   }
   // autotune each distinct class once (cached in memory and on disk)
-  std::map<std::string, int> done;
+  std::map<std::string, std::pair<int, int>> done;  // class -> (parts, stage-1 split)
   for (kpme_plan_t pl : b->plans) {
     const std::string key = tune_key(pl);
     auto it = done.find(key);
     if (it != done.end()) {
-      if (set_parts(pl, it->second) != hipSuccess) break;
+      if (set_parts(pl, it->second.first) != hipSuccess) break;
+      pl->s1_split = it->second.second;
       continue;
     }
     int cached = 0;
     if (tune_lookup(key, &cached)) {
-      done[key] = pl->nparts;
+      done[key] = {pl->nparts, pl->s1_split};
       continue;
     }
     kpme_status s = kpme_plan_autotune(pl, nullptr);
@@ -1117,7 +1167,7 @@ kpme_status kpme_batch_create(kpme_batch_t* batch, int count, const double* box3
       batch_free(b);
       return s;
     }
-    done[key] = pl->nparts;
+    done[key] = {pl->nparts, pl->s1_split};
   }
   for (int k = 0; k < kBatchBranches; ++k) {
     if (hipStreamCreateWithFlags(&b->branch[k], hipStreamNonBlocking) != hipSuccess ||

@@ -194,9 +194,24 @@ __global__ __launch_bounds__(256) void bin_count_lds(long n, const T* __restrict
     }
   }
   __syncthreads();
-  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-    const int c = hist[b];
-    hist[b] = c ? atomicAdd(&count[b], c) : 0;  // hist now holds this block's base
+  // one global atomic per non-empty brick (hist then holds this block's
+  // base), issued kFlush at a time so that their round trips overlap
+  constexpr int kFlush = 8;
+  for (int b0 = threadIdx.x; b0 < nb; b0 += kFlush * blockDim.x) {
+    int c[kFlush];
+#pragma unroll
+    for (int k = 0; k < kFlush; ++k) {
+      const int b = b0 + k * static_cast<int>(blockDim.x);
+      c[k] = b < nb ? hist[b] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < kFlush; ++k)
+      if (c[k]) c[k] = atomicAdd(&count[b0 + k * static_cast<int>(blockDim.x)], c[k]);
+#pragma unroll
+    for (int k = 0; k < kFlush; ++k) {
+      const int b = b0 + k * static_cast<int>(blockDim.x);
+      if (b < nb) hist[b] = c[k];
+    }
   }
   __syncthreads();
 #pragma unroll
@@ -227,27 +242,38 @@ __global__ __launch_bounds__(256) void bin_count(long n, const T* __restrict__ p
 // zero for the next binning.
 __global__ __launch_bounds__(1024) void bin_scan(int* __restrict__ count, int nbricks,
                                                  int* __restrict__ offset) {
-  __shared__ int part[1024];
-  const int t = threadIdx.x;
+  __shared__ int wsum[16];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int per = (nbricks + 1023) / 1024;
   const int b0 = t * per, b1 = min(b0 + per, nbricks);
   int s = 0;
   for (int b = b0; b < b1; ++b) s += count[b];
-  part[t] = s;
-  __syncthreads();
-  for (int w = 1; w < 1024; w <<= 1) {  // Hillis-Steele inclusive scan
-    const int v = (t >= w) ? part[t - w] : 0;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
+  // inclusive scan: within each wave by shuffles, then over the 16 wave totals
+  int inc = s;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int v = __shfl_up(inc, d, 64);
+    if (lane >= d) inc += v;
   }
-  int run = part[t] - s;
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  if (w == 0) {
+    int x = lane < 16 ? wsum[lane] : 0;
+#pragma unroll
+    for (int d = 1; d < 16; d <<= 1) {
+      const int v = __shfl_up(x, d, 64);
+      if (lane >= d) x += v;
+    }
+    if (lane < 16) wsum[lane] = x;
+  }
+  __syncthreads();
+  int run = inc - s + (w > 0 ? wsum[w - 1] : 0);
   for (int b = b0; b < b1; ++b) {
     offset[b] = run;
     run += count[b];
     count[b] = 0;
   }
-  if (t == 1023) offset[nbricks] = part[1023];
+  if (t == 1023) offset[nbricks] = wsum[15];
 }
 
 template <typename T>

@@ -19,6 +19,7 @@ struct SkpArgs {
   int K[3];
   int K1P, K2P, K3P;     // padded extents (multiples of 32)
   int r0, R, nparts;
+  int s1_split;          // split stage 1: workgroups per 64-position tile
   const void* Q;         // grid_in  [K1][K2][K3]
   void* Phi;             // grid_out [K1][K2][K3]
   const void* vec;       // split paths: per-term circulant vector copies (see stage 2)

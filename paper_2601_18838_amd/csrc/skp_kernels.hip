@@ -165,9 +165,10 @@ __global__ __launch_bounds__(64) void stage1_x3(
 // of four waves takes one tile of 64 positions; its Q rows are split into
 // hi/lo once, into LDS, and every wave keeps the A fragments of the whole K
 // range in registers while it streams its share of the 16-row C tiles
-// (kS1Split workgroups per position tile), the next tile's C fragments in
-// flight.  Position dealing and output layout as in stage1_x3.
-constexpr int kS1Split = 2;
+// (gridDim.x workgroups per position tile; the plan picks that split, since
+// the C tiles of one workgroup should spread evenly over its four waves),
+// the next tile's C fragments in flight.  Position dealing and output layout
+// as in stage1_x3.
 
 template <typename H, int NK>
 __global__ __launch_bounds__(256) void stage1_x3_lds(
@@ -180,8 +181,9 @@ __global__ __launch_bounds__(256) void stage1_x3_lds(
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, q = lane >> 4, m = lane & 15;
   // logical order: the splits of one position tile are consecutive (one XCD)
   const int L = xcd_order(linear_block(), num_blocks());
-  const long p0 = static_cast<long>(L / kS1Split) * 64;
-  const int split = L % kS1Split;
+  const int nsplit = gridDim.x;
+  const long p0 = static_cast<long>(L / nsplit) * 64;
+  const int split = L % nsplit;
   const float sq = qscale ? static_cast<float>(*qscale) : 1.0f;
   // Q tile -> LDS hi/lo (row r = p - p0, zero outside the grid and for k >= K3)
   {
@@ -225,7 +227,7 @@ __global__ __launch_bounds__(256) void stage1_x3_lds(
     }
   }
   const int ntiles = (nrows + 15) / 16;
-  const int per = (ntiles + kS1Split - 1) / kS1Split;
+  const int per = (ntiles + nsplit - 1) / nsplit;
   const int t0 = split * per, t1 = min(ntiles, t0 + per);
   auto loadc = [&](int t, v8 (&bh)[NK], v8 (&bl)[NK]) {
     const int n = 16 * t + m;
@@ -894,8 +896,9 @@ hipError_t launch_s1_x3(const SkpArgs& a, const double* qscale, float sy, hipStr
   const int nrows = a.r0 * a.K[2];
   const int ntiles = (nrows + 15) / 16;
   const unsigned ptiles = static_cast<unsigned>(slab / 64);
+  const unsigned s1split = static_cast<unsigned>(std::max(1, std::min(a.s1_split, ntiles)));
 #define KPME_S1(NK)                                                                        \
-  hipLaunchKernelGGL((stage1_x3_lds<H, NK>), dim3(kS1Split, ptiles), dim3(256), 0, st,    \
+  hipLaunchKernelGGL((stage1_x3_lds<H, NK>), dim3(s1split, ptiles), dim3(256), 0, st,     \
                      static_cast<const float*>(a.Q), static_cast<const H*>(a.C[0]),        \
                      static_cast<const H*>(a.C[1]), static_cast<H*>(a.Y[0]),               \
                      static_cast<H*>(a.Y[1]), a.K[0], a.K[1], a.K[2], a.K2P, slab, nrows,  \

@@ -84,6 +84,8 @@ def lib():
         L.kpme_device_count.restype = ctypes.c_int
         L.kpme_plan_stage2_parts.argtypes = [_P]
         L.kpme_plan_stage2_parts.restype = ctypes.c_int
+        L.kpme_plan_stage1_split.argtypes = [_P]
+        L.kpme_plan_stage1_split.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -230,12 +232,16 @@ class Plan:
         return e4, pot, frc
 
     def autotune(self):
-        """Run the library's stage-2 autotuner on the current stream; returns the split."""
+        """Run the library's autotuner (stage-2 and stage-1 splits) on the current
+        stream; returns the stage-2 split."""
         _check(lib().kpme_plan_autotune(self._h, _stream()))
         return self.stage2_parts()
 
     def stage2_parts(self):
         return lib().kpme_plan_stage2_parts(self._h)
+
+    def stage1_split(self):
+        return lib().kpme_plan_stage1_split(self._h)
 
     def profile(self, enable=True):
         """Switch the library's per-stage hipEvent timers on or off."""
