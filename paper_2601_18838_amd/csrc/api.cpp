@@ -267,6 +267,7 @@ kpme_status validate_params(const double box[3], const int grid[3], int p, doubl
 }
 
 constexpr int kMaxParts = 8;  // stage-2 partial-slab buffers per plan
+constexpr int kFoldedSums = 2048;  // grid-sum partials reduced inside stage 1
 
 // ---- tuning cache: "key nparts" lines, in memory and in $KPME_TUNE_CACHE ----
 std::mutex g_tune_mu;
@@ -846,11 +847,21 @@ kpme_status do_skp(kpme_plan_t plan, const void* in, void* out, hipStream_t st,
   a.sy = plan->sy;
   a.st = plan->st;
   a.const_scale = plan->const_scale;
-  hipError_t e;
+  // the split stage-1 kernels reduce up to kFoldedSums (sum, max) partials
+  // themselves (every workgroup reads them all); more go through sum_final
+  const int np = sum_ready ? plan->bins.geom.nbricks : kSumBlocks;
+  const bool s1_reduces = (plan->prec == PREC_BF16X3 || plan->prec == PREC_FP16X3) &&
+                          np <= kFoldedSums;
+  a.sum_part = s1_reduces ? (sum_ready ? part2 : plan->scratch) : nullptr;
+  a.sum_np = s1_reduces ? np : 0;
+  hipError_t e = hipSuccess;
   {
     StageTimer tm(plan, KPME_STAGE_GRID_SUM, st);
-    e = sum_ready ? launch_sum_final(part2, plan->bins.geom.nbricks, scalars, st)
-                  : launch_skp_sum(a, st);
+    if (s1_reduces)
+      e = sum_ready ? hipSuccess : launch_sum_partials(a, st);
+    else
+      e = sum_ready ? launch_sum_final(part2, plan->bins.geom.nbricks, scalars, st)
+                    : launch_skp_sum(a, st);
   }
   if (e == hipSuccess) {
     StageTimer tm(plan, KPME_STAGE_SKP1, st);

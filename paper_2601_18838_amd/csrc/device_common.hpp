@@ -82,4 +82,31 @@ __device__ __forceinline__ int linear_block() {
 }
 __device__ __forceinline__ int num_blocks() { return gridDim.x * gridDim.y * gridDim.z; }
 
+// Workgroup reduction in a fixed order: sums of v[0..NS) and maxima of
+// v[NS..NV), by a butterfly within each wave and then over the waves in wave
+// order; the result is in thread 0's v.  The workgroup is whole waves, at
+// most 16; red holds 16 * NV doubles of LDS.  Every thread must call it.
+template <int NS, int NV>
+__device__ __forceinline__ void block_reduce(double (&v)[NV], double* red) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      const double x = __shfl_xor(v[k], o, 64);
+      v[k] = k < NS ? v[k] + x : fmax(v[k], x);
+    }
+  const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) red[16 * k + wv] = v[k];
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      double a = red[16 * k];
+      for (int w = 1; w < nw; ++w) a = k < NS ? a + red[16 * k + w] : fmax(a, red[16 * k + w]);
+      v[k] = a;
+    }
+}
+
 }  // namespace kpme

@@ -276,6 +276,65 @@ __global__ __launch_bounds__(1024) void bin_scan(int* __restrict__ count, int nb
   if (t == 1023) offset[nbricks] = wsum[15];
 }
 
+// Scatter with the scan folded in (nbricks <= kLdsHist, and few workgroups
+// times bricks): every workgroup takes the exclusive prefix of the brick
+// counts into LDS (workgroup 0 also stores it to offset[0..nbricks]) and
+// scatters kBinPer particles per thread; the counts are cleared later, by
+// the spread (one workgroup per brick), for the next binning.
+template <typename T>
+__global__ __launch_bounds__(256) void bin_scan_scatter(long n, const T* __restrict__ pos,
+                                                        const T* __restrict__ q,
+                                                        const int* __restrict__ brick_of,
+                                                        const int* __restrict__ slot,
+                                                        const int* __restrict__ count,
+                                                        int nbricks, int* __restrict__ offset,
+                                                        T* __restrict__ sorted,
+                                                        int* __restrict__ perm) {
+  __shared__ int off[kLdsHist + 1];
+  __shared__ int wsum[4];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int per = (nbricks + 255) / 256;
+  const int b0 = min(t * per, nbricks), b1 = min(b0 + per, nbricks);
+  int s = 0;
+  for (int c0 = b0; c0 < b1; c0 += 8) {  // eight loads in flight at a time
+    int c[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) c[u] = c0 + u < b1 ? count[c0 + u] : 0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (c0 + u < b1) {
+        off[c0 + u] = s;
+        s += c[u];
+      }
+  }
+  int inc = s;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int v = __shfl_up(inc, d, 64);
+    if (lane >= d) inc += v;
+  }
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  int base = inc - s;
+  for (int k = 0; k < w; ++k) base += wsum[k];
+  for (int b = b0; b < b1; ++b) off[b] += base;
+  if (t == 255) off[nbricks] = base + s;  // thread 255's range ends at nbricks
+  __syncthreads();
+  if (blockIdx.x == 0)
+    for (int b = t; b <= nbricks; b += 256) offset[b] = off[b];
+#pragma unroll
+  for (int k = 0; k < kBinPer; ++k) {
+    const long i = (blockIdx.x * static_cast<long>(kBinPer) + k) * 256 + t;
+    if (i >= n) break;
+    const long d = off[brick_of[i]] + slot[i];
+    sorted[4 * d + 0] = pos[3 * i + 0];
+    sorted[4 * d + 1] = pos[3 * i + 1];
+    sorted[4 * d + 2] = pos[3 * i + 2];
+    sorted[4 * d + 3] = q[i];
+    perm[d] = static_cast<int>(i);
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void bin_scatter(long n, const T* __restrict__ pos,
                                                    const T* __restrict__ q,
@@ -309,15 +368,17 @@ __global__ __launch_bounds__(256) void spread_brick(const T* __restrict__ sorted
                                                     const int* __restrict__ offset,
                                                     const int* __restrict__ nbr,
                                                     T* __restrict__ grid,
-                                                    double* __restrict__ part2, GridGeom g,
+                                                    double* __restrict__ part2,
+                                                    int* __restrict__ count, GridGeom g,
                                                     BinGeom bg) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   double* tile = reinterpret_cast<double*>(smem);
   __shared__ int hstart[64], hpre[65];
-  __shared__ double red[256], mx[256];
+  __shared__ double red[32];
   const int E0 = bg.edge[0], E1 = bg.edge[1], E2 = bg.edge[2];
   // neighbouring bricks (which read overlapping particle lists) share an XCD
   const int brick = xcd_order(blockIdx.x, gridDim.x);
+  if (threadIdx.x == 0) count[brick] = 0;  // the scatter has read it: ready for the next binning
   int own[3], rest = brick;
   own[2] = rest % bg.nb[2]; rest /= bg.nb[2];
   own[1] = rest % bg.nb[1];
@@ -333,17 +394,29 @@ __global__ __launch_bounds__(256) void spread_brick(const T* __restrict__ sorted
   const int* n0 = nbr + kNbrRec * (0 * bg.nbmax + own[0]);
   const int* n1 = nbr + kNbrRec * (1 * bg.nbmax + own[1]);
   const int* n2 = nbr + kNbrRec * (2 * bg.nbmax + own[2]);
-  const int nh = n0[0] * n1[0] * n2[0];
-  if (threadIdx.x == 0) {
-    int acc = 0;
-    for (int c = 0; c < nh; ++c) {
+  const int nh = n0[0] * n1[0] * n2[0];  // <= 64 home bricks
+  if (threadIdx.x < 64) {
+    // lane c loads home brick c's particle range; exclusive prefix of the
+    // range lengths by shuffles (lanes >= nh add nothing)
+    const int c = threadIdx.x;
+    int start = 0, cnt = 0;
+    if (c < nh) {
       const int a2 = c % n2[0], a1 = (c / n2[0]) % n1[0], a0 = c / (n1[0] * n2[0]);
       const int hb = (n0[1 + a0] * bg.nb[1] + n1[1 + a1]) * bg.nb[2] + n2[1 + a2];
-      hstart[c] = offset[hb];
-      hpre[c] = acc;
-      acc += offset[hb + 1] - offset[hb];
+      start = offset[hb];
+      cnt = offset[hb + 1] - start;
     }
-    hpre[nh] = acc;
+    int inc = cnt;
+#pragma unroll
+    for (int dl = 1; dl < 64; dl <<= 1) {
+      const int v = __shfl_up(inc, dl, 64);
+      if (c >= dl) inc += v;
+    }
+    if (c < nh) {
+      hstart[c] = start;
+      hpre[c] = inc - cnt;
+    }
+    if (c == 63) hpre[nh] = inc;
   }
   __syncthreads();
   const int total = hpre[nh];
@@ -391,19 +464,11 @@ __global__ __launch_bounds__(256) void spread_brick(const T* __restrict__ sorted
       m = fmax(m, fabs(static_cast<double>(v)));
     }
   }
-  red[threadIdx.x] = s;
-  mx[threadIdx.x] = m;
-  __syncthreads();
-  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
-      red[threadIdx.x] += red[threadIdx.x + w];
-      mx[threadIdx.x] = fmax(mx[threadIdx.x], mx[threadIdx.x + w]);
-    }
-    __syncthreads();
-  }
+  double v[2] = {s, m};
+  block_reduce<1, 2>(v, red);
   if (threadIdx.x == 0) {
-    part2[2 * brick] = red[0];
-    part2[2 * brick + 1] = mx[0];
+    part2[2 * brick] = v[0];
+    part2[2 * brick + 1] = v[1];
   }
 }
 
@@ -417,10 +482,12 @@ __global__ __launch_bounds__(256) void spread_brick(const T* __restrict__ sorted
 template <typename T, int P>
 __global__ __launch_bounds__(64) void spread_home(const T* __restrict__ sorted,
                                                   const int* __restrict__ offset,
-                                                  T* __restrict__ tiles, GridGeom g, BinGeom bg) {
+                                                  T* __restrict__ tiles,
+                                                  int* __restrict__ count, GridGeom g, BinGeom bg) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   double* tile = reinterpret_cast<double*>(smem);
   const int brick = xcd_order(blockIdx.x, gridDim.x);
+  if (threadIdx.x == 0) count[brick] = 0;  // the scatter has read it: ready for the next binning
   int own[3], rest = brick;
   own[2] = rest % bg.nb[2]; rest /= bg.nb[2];
   own[1] = rest % bg.nb[1];
@@ -479,7 +546,7 @@ __global__ __launch_bounds__(512) void spread_combine(const T* __restrict__ tile
                                                       T* __restrict__ grid,
                                                       double* __restrict__ part2, GridGeom g,
                                                       BinGeom bg) {
-  __shared__ double red[512], mx[512];
+  __shared__ double red[32];
   __shared__ int dlt[3][kNbrRec], hid[3][kNbrRec];
   const int brick = xcd_order(blockIdx.x, gridDim.x);
   int own[3], rest = brick;
@@ -536,19 +603,11 @@ __global__ __launch_bounds__(512) void spread_combine(const T* __restrict__ tile
     s += static_cast<double>(v);
     m = fmax(m, fabs(static_cast<double>(v)));
   }
-  red[threadIdx.x] = s;
-  mx[threadIdx.x] = m;
-  __syncthreads();
-  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
-      red[threadIdx.x] += red[threadIdx.x + w];
-      mx[threadIdx.x] = fmax(mx[threadIdx.x], mx[threadIdx.x + w]);
-    }
-    __syncthreads();
-  }
+  double v[2] = {s, m};
+  block_reduce<1, 2>(v, red);
   if (threadIdx.x == 0) {
-    part2[2 * brick] = red[0];
-    part2[2 * brick + 1] = mx[0];
+    part2[2 * brick] = v[0];
+    part2[2 * brick + 1] = v[1];
   }
 }
 
@@ -563,7 +622,7 @@ __global__ __launch_bounds__(256) void gather_sorted(long n, const T* __restrict
                                                      T* __restrict__ pot,
                                                      T* __restrict__ force,
                                                      double* __restrict__ part3, GridGeom g) {
-  __shared__ double red[3][256];
+  __shared__ double red[48];
   // neighbouring particle blocks (neighbouring bricks) share an XCD's L2
   const int blk = xcd_order(blockIdx.x, gridDim.x);
   const long s = blk * static_cast<long>(blockDim.x) + threadIdx.x;
@@ -627,17 +686,10 @@ __global__ __launch_bounds__(256) void gather_sorted(long n, const T* __restrict
     e2 = qd * qd;
   }
   if (part3) {
-    red[0][threadIdx.x] = e0;
-    red[1][threadIdx.x] = e1;
-    red[2][threadIdx.x] = e2;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if (threadIdx.x < w)
-        for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
-      __syncthreads();
-    }
+    double v[3] = {e0, e1, e2};
+    block_reduce<3, 3>(v, red);
     if (threadIdx.x == 0)
-      for (int k = 0; k < 3; ++k) part3[3 * blk + k] = red[k][0];
+      for (int k = 0; k < 3; ++k) part3[3 * blk + k] = v[k];
   }
 }
 
@@ -658,7 +710,7 @@ __global__ __launch_bounds__(256) void gather_brick(const T* __restrict__ sorted
                                                     BinGeom bg) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   T* tile = reinterpret_cast<T*>(smem);
-  __shared__ double red[3][256];
+  __shared__ double red[48];
   const int brick = xcd_order(blockIdx.x, gridDim.x);
   int own[3], rest = brick;
   own[2] = rest % bg.nb[2]; rest /= bg.nb[2];
@@ -735,17 +787,10 @@ __global__ __launch_bounds__(256) void gather_brick(const T* __restrict__ sorted
     e2 += qd * qd;
   }
   if (part3) {
-    red[0][threadIdx.x] = e0;
-    red[1][threadIdx.x] = e1;
-    red[2][threadIdx.x] = e2;
-    __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-      if (threadIdx.x < w)
-        for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
-      __syncthreads();
-    }
+    double v[3] = {e0, e1, e2};
+    block_reduce<3, 3>(v, red);
     if (threadIdx.x == 0)
-      for (int k = 0; k < 3; ++k) part3[3 * brick + k] = red[k][0];
+      for (int k = 0; k < 3; ++k) part3[3 * brick + k] = v[k];
   }
 }
 
@@ -849,7 +894,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void energy_partial(long n, const T* __restrict__ q,
                                                       const T* __restrict__ pot,
                                                       double* __restrict__ part) {
-  __shared__ double red[3][256];
+  __shared__ double red[48];
   const long per = (n + gridDim.x - 1) / gridDim.x;
   const long b = per * blockIdx.x, e = (b + per < n) ? b + per : n;
   double s0 = 0, s1 = 0, s2 = 0;
@@ -859,38 +904,34 @@ __global__ __launch_bounds__(256) void energy_partial(long n, const T* __restric
     s1 += qi;
     s2 += qi * qi;
   }
-  red[0][threadIdx.x] = s0;
-  red[1][threadIdx.x] = s1;
-  red[2][threadIdx.x] = s2;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w)
-      for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
-    __syncthreads();
-  }
+  double v[3] = {s0, s1, s2};
+  block_reduce<3, 3>(v, red);
   if (threadIdx.x == 0)
-    for (int k = 0; k < 3; ++k) part[3 * blockIdx.x + k] = red[k][0];
+    for (int k = 0; k < 3; ++k) part[3 * blockIdx.x + k] = v[k];
 }
 
 __global__ __launch_bounds__(256) void energy_final(const double* __restrict__ part, int nb,
                                                     double beta, double volume,
                                                     double* __restrict__ e4) {
-  __shared__ double red[3][256];
+  __shared__ double red[48];
   double s[3] = {0, 0, 0};
-  for (int i = threadIdx.x; i < nb; i += 256)
-    for (int k = 0; k < 3; ++k) s[k] += part[3 * i + k];
-  for (int k = 0; k < 3; ++k) red[k][threadIdx.x] = s[k];
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w)
-      for (int k = 0; k < 3; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + w];
-    __syncthreads();
+  for (int i0 = threadIdx.x; i0 < nb; i0 += 4 * 256) {  // four triples in flight
+    double x[4][3];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) x[u][k] = i0 + 256 * u < nb ? part[3 * (i0 + 256 * u) + k] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) s[k] += x[u][k];
   }
+  block_reduce<3, 3>(s, red);
   if (threadIdx.x == 0) {
     const double pi = 3.141592653589793238462643383279502884;
-    const double e_rec = 0.5 * red[0][0];
-    const double e_self = -beta / sqrt(pi) * red[2][0];
-    const double e_neu = -pi * red[1][0] * red[1][0] / (2.0 * volume * beta * beta);
+    const double e_rec = 0.5 * s[0];
+    const double e_self = -beta / sqrt(pi) * s[2];
+    const double e_neu = -pi * s[1] * s[1] / (2.0 * volume * beta * beta);
     e4[0] = e_rec;
     e4[1] = e_self;
     e4[2] = e_neu;
@@ -969,6 +1010,19 @@ hipError_t launch_gather_direct(int prec, const GridGeom& g, int64_t n, const vo
 
 namespace {
 
+// Workgroups of the folded scan-and-scatter kernel (at least one).
+int64_t scatter_blocks(int64_t n) {
+  const int64_t per = 256 * kBinPer;
+  return std::max<int64_t>(1, (n + per - 1) / per);
+}
+
+// The scan goes into the scatter when the LDS histogram is used and the
+// workgroups' copies of the scan read at most 2^21 counts in all; otherwise
+// one workgroup scans.
+bool scan_in_scatter(const Bins& b, int64_t n) {
+  return b.geom.nbricks <= kLdsHist && scatter_blocks(n) * b.geom.nbricks <= (int64_t(1) << 21);
+}
+
 template <typename T>
 hipError_t bin_t(const GridGeom& g, const Bins& b, int64_t n, const void* pos, hipStream_t st) {
   if (n > 0) {
@@ -984,12 +1038,22 @@ hipError_t bin_t(const GridGeom& g, const Bins& b, int64_t n, const void* pos, h
                          static_cast<const T*>(pos), g, b.geom, b.brick_of, b.slot, b.count);
     }
   }
-  hipLaunchKernelGGL(bin_scan, dim3(1), dim3(1024), 0, st, b.count, b.geom.nbricks, b.offset);
+  if (!scan_in_scatter(b, n))
+    hipLaunchKernelGGL(bin_scan, dim3(1), dim3(1024), 0, st, b.count, b.geom.nbricks, b.offset);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t scatter_t(const Bins& b, int64_t n, const void* pos, const void* q, hipStream_t st) {
+  if (scan_in_scatter(b, n)) {
+    // at least one workgroup: it stores the offsets also for n = 0
+    const unsigned blocks = static_cast<unsigned>(scatter_blocks(n));
+    hipLaunchKernelGGL((bin_scan_scatter<T>), dim3(blocks), dim3(256), 0, st,
+                       static_cast<long>(n), static_cast<const T*>(pos), static_cast<const T*>(q),
+                       b.brick_of, b.slot, b.count, b.geom.nbricks, b.offset,
+                       static_cast<T*>(b.sorted), b.perm);
+    return hipGetLastError();
+  }
   if (n == 0) return hipSuccess;
   const unsigned blocks = static_cast<unsigned>((n + 255) / 256);
   hipLaunchKernelGGL((bin_scatter<T>), dim3(blocks), dim3(256), 0, st, static_cast<long>(n),
@@ -1008,13 +1072,13 @@ hipError_t spread_brick_p(const GridGeom& g, const Bins& b, const void* src, voi
   if (P <= 4) {
     const size_t lds = sizeof(double) * b.geom.edge[0] * b.geom.edge[1] * b.geom.edge[2];
     hipLaunchKernelGGL((spread_brick<T, P>), dim3(b.geom.nbricks), dim3(256), lds, st, srt,
-                       b.offset, b.nbr, static_cast<T*>(grid), part2, g, b.geom);
+                       b.offset, b.nbr, static_cast<T*>(grid), part2, b.count, g, b.geom);
     return hipGetLastError();
   }
   const int ntile = (b.geom.edge[0] + P - 1) * (b.geom.edge[1] + P - 1) * (b.geom.edge[2] + P - 1);
   hipLaunchKernelGGL((spread_home<T, P>), dim3(b.geom.nbricks), dim3(64),
-                     sizeof(double) * ntile, st, srt, b.offset, static_cast<T*>(b.tiles), g,
-                     b.geom);
+                     sizeof(double) * ntile, st, srt, b.offset, static_cast<T*>(b.tiles), b.count,
+                     g, b.geom);
   hipLaunchKernelGGL((spread_combine<T, P>), dim3(b.geom.nbricks), dim3(512), 0, st,
                      static_cast<const T*>(b.tiles), b.nbr, static_cast<T*>(grid), part2, g,
                      b.geom);

@@ -37,6 +37,9 @@ struct SkpArgs {
   const int* step_group; // [nsteps]
   const int* step_begin; // [nparts + 1]
   double* scratch;       // >= kSumBlocks doubles
+  // split precisions: stage 1 reduces these (sum, max) pairs into sumQ
+  const double* sum_part;
+  int sum_np;
   double* sumQ;          // 2 doubles: sum(Q), then the FP16X3 grid scale
   double c0;             // theta_hat_R(0)
   float sy, st;          // FP16X3 powers of two applied to Y and T before splits
@@ -65,6 +68,8 @@ constexpr int x3_ct(int K1P, int K2P) { return (K1P == 96 && K2P == 96) ? 3 : 2;
 constexpr int x3_streams(int K1P, int K2P) { return (K1P == 96 && K2P == 96) ? 2 : 1; }
 
 hipError_t launch_skp_sum(const SkpArgs& a, hipStream_t st);
+// the per-block (sum, max) pairs of launch_skp_sum only, into a.scratch
+hipError_t launch_sum_partials(const SkpArgs& a, hipStream_t st);
 hipError_t launch_skp_stage1(const SkpArgs& a, hipStream_t st);
 hipError_t launch_skp_stage2(const SkpArgs& a, hipStream_t st);
 hipError_t launch_skp_finalize(const SkpArgs& a, hipStream_t st);

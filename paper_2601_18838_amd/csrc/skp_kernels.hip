@@ -37,16 +37,60 @@ constexpr int S1 = 64;  // stage-1 output tile (rows and columns)
 // The 64 positions are dealt to the four 16-row MFMA tiles so that tile u,
 // accumulator row 4a + r, holds position 16a + 4u + r: a lane then owns 16
 // consecutive positions of one output row and stores them as 32 bytes per
-// plane.  Q is multiplied by *qscale (a power of two, FP16X3) before its
-// split, the FP32 result by sy (a power of two) before Y's split.
+// plane.  Q is multiplied by the grid scale (a power of two, FP16X3) before
+// its split, the FP32 result by sy (a power of two) before Y's split.
 // C hi/lo: [nrows][K3P] (pre-scaled, zero-padded); Y hi/lo: [nrows][slab].
 constexpr int kS1Tiles = 4;
+
+// Grid sum and FP16X3 grid scale from np partial (sum, max|.|) pairs, which
+// the split stage-1 kernels reduce themselves when there are few of them (no
+// separate launch): the scale 2^(13 - floor(log2 max)) brings the largest
+// grid value into [2^13, 2^14) (1 for an all-zero or non-finite grid).  With
+// `store` the workgroup writes (sum, scale) to sums[0..1] for the later
+// stages.  part == nullptr: sums[0..1] were computed before; nothing is
+// reduced.  Returns the scale when `want_scale`, else 1.  Every thread of the
+// workgroup calls it, with the same arguments.
+__device__ float grid_scalars(const double* __restrict__ part, int np, double* __restrict__ sums,
+                              bool want_scale, bool store) {
+  __shared__ double red[32];
+  __shared__ double scale;
+  if (!part) return want_scale ? static_cast<float>(sums[1]) : 1.0f;
+  if (!want_scale && !store) return 1.0f;
+  double v[2] = {0.0, 0.0};
+  // eight pairs per thread in flight at a time (the partials come from
+  // another kernel, most of them from other XCDs' caches)
+  for (int i0 = threadIdx.x; i0 < np; i0 += 8 * blockDim.x) {
+    double2 x[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = i0 + u * blockDim.x;
+      x[u] = i < np ? *reinterpret_cast<const double2*>(&part[2 * i]) : double2{0.0, 0.0};
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      v[0] += x[u].x;
+      v[1] = fmax(v[1], x[u].y);
+    }
+  }
+  block_reduce<1, 2>(v, red);
+  if (threadIdx.x == 0) {
+    const double m = v[1];
+    scale = (m > 0.0 && m < 1e300) ? ldexp(1.0, 13 - ilogb(m)) : 1.0;
+    if (store) {
+      sums[0] = v[0];
+      sums[1] = scale;
+    }
+  }
+  __syncthreads();
+  return want_scale ? static_cast<float>(scale) : 1.0f;
+}
 
 template <typename H>
 __global__ __launch_bounds__(64) void stage1_x3(
     const float* __restrict__ Q, const H* __restrict__ Chi, const H* __restrict__ Clo,
     H* __restrict__ Yhi, H* __restrict__ Ylo, int K1, int K2, int K3, int K3P, int K2P,
-    long slab, int nrows, const double* __restrict__ qscale, float sy) {
+    long slab, int nrows, const double* __restrict__ part, int np, double* __restrict__ sums,
+    int scale_q, float sy) {
   typedef typename HVec<H>::v8 v8;
   const int lane = threadIdx.x, q = lane >> 4, m = lane & 15;
   // logical order: the n splits of one position tile are consecutive (and so
@@ -54,7 +98,7 @@ __global__ __launch_bounds__(64) void stage1_x3(
   const int L = xcd_order(linear_block(), num_blocks());
   const long p0 = static_cast<long>(L / gridDim.x) * 64;
   const int nt0 = (L % gridDim.x) * kS1Tiles;
-  const float sq = qscale ? static_cast<float>(*qscale) : 1.0f;
+  const float sq = grid_scalars(part, np, sums, scale_q != 0, linear_block() == 0);
   const bool vec4 = (K3 & 3) == 0;  // rows 16-byte aligned, 4-float groups all in or out
   // Q rows of this lane's A-operand rows: tile u holds p = p0 + 16 (m / 4) + 4 u + m % 4
   const float* row[4];
@@ -174,7 +218,8 @@ template <typename H, int NK>
 __global__ __launch_bounds__(256) void stage1_x3_lds(
     const float* __restrict__ Q, const H* __restrict__ Chi, const H* __restrict__ Clo,
     H* __restrict__ Yhi, H* __restrict__ Ylo, int K1, int K2, int K3, int K2P, long slab,
-    int nrows, const double* __restrict__ qscale, float sy) {
+    int nrows, const double* __restrict__ part, int np, double* __restrict__ sums, int scale_q,
+    float sy) {
   typedef typename HVec<H>::v8 v8;
   constexpr int K3P = 32 * NK, QSTR = K3P + 8;
   __shared__ __attribute__((aligned(16))) H Qh[64 * QSTR], Ql[64 * QSTR];
@@ -184,33 +229,42 @@ __global__ __launch_bounds__(256) void stage1_x3_lds(
   const int nsplit = gridDim.x;
   const long p0 = static_cast<long>(L / nsplit) * 64;
   const int split = L % nsplit;
-  const float sq = qscale ? static_cast<float>(*qscale) : 1.0f;
-  // Q tile -> LDS hi/lo (row r = p - p0, zero outside the grid and for k >= K3)
-  {
-    constexpr int c4n = K3P / 4;
-    for (int e = tid; e < 64 * c4n; e += 256) {
-      const int r = e / c4n, k = 4 * (e % c4n);
-      const long p = p0 + r;
-      const int g1 = static_cast<int>(p / K2P), g2 = static_cast<int>(p % K2P);
-      const bool valid = g1 < K1 && g2 < K2;
-      const float* row = Q + (static_cast<long>(valid ? g1 : 0) * K2 + (valid ? g2 : 0)) * K3;
-      float x[4] = {0.f, 0.f, 0.f, 0.f};
-      if ((K3 & 3) == 0) {
-        if (valid && k < K3) {
-          const float4 v = *reinterpret_cast<const float4*>(&row[k]);
-          x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
-        }
-      } else {
+  // Q tile (row r = p - p0, zero outside the grid and for k >= K3) into
+  // registers; the loads are in flight while the grid scalars are reduced
+  constexpr int c4n = K3P / 4, QIT = 64 * c4n / 256;
+  float x[QIT][4];
 #pragma unroll
-        for (int h = 0; h < 4; ++h) x[h] = (valid && k + h < K3) ? row[k + h] : 0.f;
-      }
+  for (int it = 0; it < QIT; ++it) {
+    const int e = tid + 256 * it;
+    const int r = e / c4n, k = 4 * (e % c4n);
+    const long p = p0 + r;
+    const int g1 = static_cast<int>(p / K2P), g2 = static_cast<int>(p % K2P);
+    const bool valid = g1 < K1 && g2 < K2;
+    const float* row = Q + (static_cast<long>(valid ? g1 : 0) * K2 + (valid ? g2 : 0)) * K3;
 #pragma unroll
-      for (int h = 0; h < 4; ++h) {
-        H hi, lo;
-        split_h<H>(sq * x[h], hi, lo);
-        Qh[r * QSTR + k + h] = hi;
-        Ql[r * QSTR + k + h] = lo;
+    for (int h = 0; h < 4; ++h) x[it][h] = 0.f;
+    if ((K3 & 3) == 0) {
+      if (valid && k < K3) {
+        const float4 v = *reinterpret_cast<const float4*>(&row[k]);
+        x[it][0] = v.x; x[it][1] = v.y; x[it][2] = v.z; x[it][3] = v.w;
       }
+    } else {
+#pragma unroll
+      for (int h = 0; h < 4; ++h) x[it][h] = (valid && k + h < K3) ? row[k + h] : 0.f;
+    }
+  }
+  const float sq = grid_scalars(part, np, sums, scale_q != 0, linear_block() == 0);
+  // scaled and split into LDS hi/lo
+#pragma unroll
+  for (int it = 0; it < QIT; ++it) {
+    const int e = tid + 256 * it;
+    const int r = e / c4n, k = 4 * (e % c4n);
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      H hi, lo;
+      split_h<H>(sq * x[it][h], hi, lo);
+      Qh[r * QSTR + k + h] = hi;
+      Ql[r * QSTR + k + h] = lo;
     }
   }
   __syncthreads();
@@ -741,7 +795,7 @@ __global__ __launch_bounds__(256) void finalize(const A* __restrict__ part, int 
 template <typename T>
 __global__ __launch_bounds__(256) void sum_partial(const T* __restrict__ x, long n,
                                                    double* __restrict__ part) {
-  __shared__ double red[256], mx[256];
+  __shared__ double red[32];
   const long per = (n + gridDim.x - 1) / gridDim.x;
   const long b = per * blockIdx.x, e = (b + per < n) ? b + per : n;
   double acc = 0.0, amax = 0.0;
@@ -750,19 +804,11 @@ __global__ __launch_bounds__(256) void sum_partial(const T* __restrict__ x, long
     acc += v;
     amax = fmax(amax, fabs(v));
   }
-  red[threadIdx.x] = acc;
-  mx[threadIdx.x] = amax;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
-      red[threadIdx.x] += red[threadIdx.x + w];
-      mx[threadIdx.x] = fmax(mx[threadIdx.x], mx[threadIdx.x + w]);
-    }
-    __syncthreads();
-  }
+  double v[2] = {acc, amax};
+  block_reduce<1, 2>(v, red);
   if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = red[0];
-    part[2 * blockIdx.x + 1] = mx[0];
+    part[2 * blockIdx.x] = v[0];
+    part[2 * blockIdx.x + 1] = v[1];
   }
 }
 
@@ -771,25 +817,25 @@ __global__ __launch_bounds__(256) void sum_partial(const T* __restrict__ x, long
 // (1 for an all-zero or non-finite grid).
 __global__ __launch_bounds__(256) void sum_final(const double* __restrict__ part, int np,
                                                  double* __restrict__ out) {
-  __shared__ double red[256], mx[256];
-  double acc = 0.0, amax = 0.0;
-  for (int i = threadIdx.x; i < np; i += 256) {
-    acc += part[2 * i];
-    amax = fmax(amax, part[2 * i + 1]);
-  }
-  red[threadIdx.x] = acc;
-  mx[threadIdx.x] = amax;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
-      red[threadIdx.x] += red[threadIdx.x + w];
-      mx[threadIdx.x] = fmax(mx[threadIdx.x], mx[threadIdx.x + w]);
+  __shared__ double red[32];
+  double v[2] = {0.0, 0.0};
+  for (int i0 = threadIdx.x; i0 < np; i0 += 8 * 256) {  // eight pairs in flight
+    double2 x[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = i0 + 256 * u;
+      x[u] = i < np ? *reinterpret_cast<const double2*>(&part[2 * i]) : double2{0.0, 0.0};
     }
-    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      v[0] += x[u].x;
+      v[1] = fmax(v[1], x[u].y);
+    }
   }
+  block_reduce<1, 2>(v, red);
   if (threadIdx.x == 0) {
-    out[0] = red[0];
-    const double m = mx[0];
+    out[0] = v[0];
+    const double m = v[1];
     out[1] = (m > 0.0 && m < 1e300) ? ldexp(1.0, 13 - ilogb(m)) : 1.0;
   }
 }
@@ -885,13 +931,24 @@ hipError_t launch_skp_sum(const SkpArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+hipError_t launch_sum_partials(const SkpArgs& a, hipStream_t st) {
+  const long G = static_cast<long>(a.K[0]) * a.K[1] * a.K[2];
+  if (a.prec == PREC_FP64)
+    hipLaunchKernelGGL((sum_partial<double>), dim3(kSumBlocks), dim3(256), 0, st,
+                       static_cast<const double*>(a.Q), G, a.scratch);
+  else
+    hipLaunchKernelGGL((sum_partial<float>), dim3(kSumBlocks), dim3(256), 0, st,
+                       static_cast<const float*>(a.Q), G, a.scratch);
+  return hipGetLastError();
+}
+
 hipError_t launch_sum_final(const double* part2, int np, double* out, hipStream_t st) {
   hipLaunchKernelGGL(sum_final, dim3(1), dim3(256), 0, st, part2, np, out);
   return hipGetLastError();
 }
 
 template <typename H>
-hipError_t launch_s1_x3(const SkpArgs& a, const double* qscale, float sy, hipStream_t st) {
+hipError_t launch_s1_x3(const SkpArgs& a, int scale_q, float sy, hipStream_t st) {
   const long slab = static_cast<long>(a.K1P) * a.K2P;
   const int nrows = a.r0 * a.K[2];
   const int ntiles = (nrows + 15) / 16;
@@ -902,7 +959,7 @@ hipError_t launch_s1_x3(const SkpArgs& a, const double* qscale, float sy, hipStr
                      static_cast<const float*>(a.Q), static_cast<const H*>(a.C[0]),        \
                      static_cast<const H*>(a.C[1]), static_cast<H*>(a.Y[0]),               \
                      static_cast<H*>(a.Y[1]), a.K[0], a.K[1], a.K[2], a.K2P, slab, nrows,  \
-                     qscale, sy)
+                     a.sum_part, a.sum_np, a.sumQ, scale_q, sy)
   switch (a.K3P) {
     case 32: KPME_S1(1); return hipGetLastError();
     case 64: KPME_S1(2); return hipGetLastError();
@@ -915,7 +972,7 @@ hipError_t launch_s1_x3(const SkpArgs& a, const double* qscale, float sy, hipStr
   hipLaunchKernelGGL((stage1_x3<H>), grid, dim3(64), 0, st, static_cast<const float*>(a.Q),
                      static_cast<const H*>(a.C[0]), static_cast<const H*>(a.C[1]),
                      static_cast<H*>(a.Y[0]), static_cast<H*>(a.Y[1]), a.K[0], a.K[1], a.K[2],
-                     a.K3P, a.K2P, slab, nrows, qscale, sy);
+                     a.K3P, a.K2P, slab, nrows, a.sum_part, a.sum_np, a.sumQ, scale_q, sy);
   return hipGetLastError();
 }
 
@@ -923,8 +980,8 @@ hipError_t launch_skp_stage1(const SkpArgs& a, hipStream_t st) {
   const long slab = static_cast<long>(a.K1P) * a.K2P;
   const int nrows = a.r0 * a.K[2];
   dim3 g1(static_cast<unsigned>(slab / S1), (nrows + S1 - 1) / S1);
-  if (a.prec == PREC_BF16X3) return launch_s1_x3<bf16>(a, nullptr, 1.0f, st);
-  if (a.prec == PREC_FP16X3) return launch_s1_x3<f16>(a, a.sumQ + 1, a.sy, st);
+  if (a.prec == PREC_BF16X3) return launch_s1_x3<bf16>(a, 0, 1.0f, st);
+  if (a.prec == PREC_FP16X3) return launch_s1_x3<f16>(a, 1, a.sy, st);
   if (a.prec == PREC_FP32)
     hipLaunchKernelGGL((stage1_k4<float>), g1, dim3(256), 0, st, static_cast<const float*>(a.Q),
                        static_cast<const float*>(a.C[0]), static_cast<float*>(a.Y[0]), a.K[0],
