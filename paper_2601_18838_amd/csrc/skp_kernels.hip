@@ -510,23 +510,35 @@ __attribute__((amdgpu_waves_per_eu(RT >= 8 ? 1 : 2))) void stage2_x3(
     for (int i = 0; i < RT; ++i)
 #pragma unroll
       for (int j = 0; j < CT; ++j) acc1[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    // (kc, i) steps; each loads the next step's Y fragment, and the last i of
+    // a kc also the next kc's B fragments
+    v8 bh[CT], bl[CT];
+#pragma unroll
+    for (int j = 0; j < CT; ++j) {
+      bh[j] = *reinterpret_cast<const v8*>(&Bvh[16 * (1 - j)]);
+      bl[j] = *reinterpret_cast<const v8*>(&Bvl[16 * (1 - j)]);
+    }
+    v8 ah = *reinterpret_cast<const v8*>(&Ysh[m * YSTR + 8 * q]);
+    v8 al = *reinterpret_cast<const v8*>(&Ysl[m * YSTR + 8 * q]);
 #pragma unroll
     for (int kc = 0; kc < NKC; ++kc) {
-      v8 bh[CT], bl[CT];
-#pragma unroll
-      for (int j = 0; j < CT; ++j) {
-        bh[j] = *reinterpret_cast<const v8*>(&Bvh[32 * kc + 16 * (1 - j)]);
-        bl[j] = *reinterpret_cast<const v8*>(&Bvl[32 * kc + 16 * (1 - j)]);
-      }
-      const int yo = m * YSTR + 32 * kc + 8 * q;
-      v8 ah = *reinterpret_cast<const v8*>(&Ysh[yo]);
-      v8 al = *reinterpret_cast<const v8*>(&Ysl[yo]);
 #pragma unroll
       for (int i = 0; i < RT; ++i) {
-        v8 nh = ah, nl = al;
+        v8 nh = ah, nl = al, nbh[CT], nbl[CT];
+        const bool next_kc = (i + 1 == RT) && (kc + 1 < NKC);
         if (i + 1 < RT) {
-          nh = *reinterpret_cast<const v8*>(&Ysh[yo + 16 * (i + 1) * YSTR]);
-          nl = *reinterpret_cast<const v8*>(&Ysl[yo + 16 * (i + 1) * YSTR]);
+          const int yo = (m + 16 * (i + 1)) * YSTR + 32 * kc + 8 * q;
+          nh = *reinterpret_cast<const v8*>(&Ysh[yo]);
+          nl = *reinterpret_cast<const v8*>(&Ysl[yo]);
+        } else if (next_kc) {
+          const int yo = m * YSTR + 32 * (kc + 1) + 8 * q;
+          nh = *reinterpret_cast<const v8*>(&Ysh[yo]);
+          nl = *reinterpret_cast<const v8*>(&Ysl[yo]);
+#pragma unroll
+          for (int j = 0; j < CT; ++j) {
+            nbh[j] = *reinterpret_cast<const v8*>(&Bvh[32 * (kc + 1) + 16 * (1 - j)]);
+            nbl[j] = *reinterpret_cast<const v8*>(&Bvl[32 * (kc + 1) + 16 * (1 - j)]);
+          }
         }
 #pragma unroll
         for (int j = 0; j < CT; ++j) acc1[i][j] = mfma_h(ah, bh[j], acc1[i][j]);
@@ -536,6 +548,13 @@ __attribute__((amdgpu_waves_per_eu(RT >= 8 ? 1 : 2))) void stage2_x3(
         for (int j = 0; j < CT; ++j) acc1[i][j] = mfma_h(al, bh[j], acc1[i][j]);
         ah = nh;
         al = nl;
+        if (next_kc) {
+#pragma unroll
+          for (int j = 0; j < CT; ++j) {
+            bh[j] = nbh[j];
+            bl[j] = nbl[j];
+          }
+        }
         __builtin_amdgcn_sched_barrier(0);
       }
     }
@@ -568,7 +587,8 @@ __attribute__((amdgpu_waves_per_eu(RT >= 8 ? 1 : 2))) void stage2_x3(
       return cat44<v4, v8>(*reinterpret_cast<const v4*>(&base[16 * dd]),
                            *reinterpret_cast<const v4*>(&base[16 * dd + 16]));
     };
-    v8 ah = afrag(Avh, 0), al = afrag(Avl, 0);
+    ah = afrag(Avh, 0);
+    al = afrag(Avl, 0);
 #pragma unroll
     for (int dd = 0; dd < 2 * RT - 2; ++dd) {
       v8 nh = ah, nl = al;
