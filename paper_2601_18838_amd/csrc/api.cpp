@@ -125,7 +125,7 @@ struct kpme_plan_s {
   void* Q2g = nullptr;        // adjoint: spread of the upstream potential gradient
   void* Psig = nullptr;       // adjoint: Theta applied to it
   void* sorted2 = nullptr;    // adjoint: binned (x, y, z, g_pot)
-  double* part3 = nullptr;    // energy partial sums of the binned gather (per brick)
+  double* part3 = nullptr;    // energy partial sums of the binned gather (per workgroup)
   int gather_blocks = 0;
   // per-stage hipEvent pairs recorded on the calling stream while profiling
   bool prof_on = false;
@@ -755,7 +755,7 @@ kpme_status kpme_plan_create(kpme_plan_t* plan, const double box[3], const int g
     pl->part2 = static_cast<double*>(tmp);  // two (sum, max) sets: forward, adjoint
     // energy partials of the binned gather: one triple per brick or per 256
     // particles (gather_partials)
-    pl->gather_blocks = std::max(static_cast<int>((max_particles + 255) / 256), bg.nbricks);
+    pl->gather_blocks = std::max(static_cast<int>((max_particles + 63) / 64), bg.nbricks);
     if ((e = plan_alloc(pl, &tmp, 3 * static_cast<size_t>(pl->gather_blocks) * sizeof(double))) != hipSuccess) break;
     pl->part3 = static_cast<double*>(tmp);
     if ((e = plan_alloc(pl, &pl->Q2g, G * es)) != hipSuccess) break;

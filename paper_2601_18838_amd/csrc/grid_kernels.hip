@@ -693,6 +693,105 @@ __global__ __launch_bounds__(256) void gather_sorted(long n, const T* __restrict
   }
 }
 
+// Gather in binned order with P lanes per particle (spline orders up to 4):
+// lane a of a particle's group takes the stencil plane k1 = base0 - a (P^2
+// loads), and the group's plane sums are added by shuffles.  Four times the
+// threads of gather_sorted keep more loads in flight.  Partial sums per
+// workgroup as in gather_sorted.
+template <typename T, int P>
+__global__ __launch_bounds__(256) void gather_sorted_planes(long n, const T* __restrict__ sorted,
+                                                            const int* __restrict__ perm,
+                                                            const T* __restrict__ grid,
+                                                            T* __restrict__ pot,
+                                                            T* __restrict__ force,
+                                                            double* __restrict__ part3,
+                                                            GridGeom g) {
+  static_assert(P == 4, "one lane per plane, four lanes per particle");
+  __shared__ double red[48];
+  const int blk = xcd_order(blockIdx.x, gridDim.x);
+  const long s = (blk * static_cast<long>(blockDim.x) + threadIdx.x) / P;
+  const int a = threadIdx.x % P;
+  double e0 = 0, e1 = 0, e2 = 0;
+  T phi = 0, g0 = 0, g1 = 0, g2 = 0;
+  const bool live = s < n;
+  T qi = 0;
+  if (live) {
+    T w[3][P], dw[3][P];
+    int base[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const T f = scaled(sorted[4 * s + j], g.L[j], g.K[j], base[j]);
+      bspline<T, P>(f, w[j], dw[j]);
+    }
+    qi = sorted[4 * s + 3];
+    const int K1 = g.K[0], K2 = g.K[1], K3 = g.K[2];
+    int kc[P];
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+      kc[c] = base[2] - c;
+      if (kc[c] < 0) kc[c] += K3;
+    }
+    int ka = base[0] - a;
+    if (ka < 0) ka += K1;
+    // this lane's weights of axis 0 (a runtime index into the unrolled array)
+    T wa = w[0][0], dwa = dw[0][0];
+#pragma unroll
+    for (int t = 1; t < P; ++t)
+      if (a == t) {
+        wa = w[0][t];
+        dwa = dw[0][t];
+      }
+    T sa = 0, sa1 = 0, sa2 = 0;
+#pragma unroll
+    for (int b = 0; b < P; ++b) {
+      int kb = base[1] - b;
+      if (kb < 0) kb += K2;
+      const T* row = grid + (static_cast<long>(ka) * K2 + kb) * K3;
+      T sv = 0, s2 = 0;
+#pragma unroll
+      for (int c = 0; c < P; ++c) {
+        const T v = row[kc[c]];
+        sv += w[2][c] * v;
+        s2 += dw[2][c] * v;
+      }
+      sa += w[1][b] * sv;
+      sa1 += dw[1][b] * sv;
+      sa2 += w[1][b] * s2;
+    }
+    phi = wa * sa;
+    g0 = dwa * sa;
+    g1 = wa * sa1;
+    g2 = wa * sa2;
+  }
+  // sums over the particle's P lanes (aligned groups of the wave)
+#pragma unroll
+  for (int o = 1; o < P; o <<= 1) {
+    phi += __shfl_xor(phi, o, 64);
+    g0 += __shfl_xor(g0, o, 64);
+    g1 += __shfl_xor(g1, o, 64);
+    g2 += __shfl_xor(g2, o, 64);
+  }
+  if (live && a == 0) {
+    const long i = perm[s];
+    if (pot) pot[i] = phi;
+    if (force) {
+      force[3 * i + 0] = -qi * g0 * static_cast<T>(g.K[0] / g.L[0]);
+      force[3 * i + 1] = -qi * g1 * static_cast<T>(g.K[1] / g.L[1]);
+      force[3 * i + 2] = -qi * g2 * static_cast<T>(g.K[2] / g.L[2]);
+    }
+    const double qd = static_cast<double>(qi);
+    e0 = qd * static_cast<double>(phi);
+    e1 = qd;
+    e2 = qd * qd;
+  }
+  if (part3) {
+    double v[3] = {e0, e1, e2};
+    block_reduce<3, 3>(v, red);
+    if (threadIdx.x == 0)
+      for (int k = 0; k < 3; ++k) part3[3 * blk + k] = v[k];
+  }
+}
+
 // Gather by brick: one workgroup per grid brick stages in LDS the potential
 // values that the stencils of the particles binned in it read -- the brick
 // and the P - 1 planes below it on each axis, H_j = edge_j + P - 1 points,
@@ -1098,6 +1197,12 @@ hipError_t gather_brick_p(const GridGeom& g, const Bins& b, int64_t n, const voi
                        st, static_cast<const T*>(b.sorted), b.offset, b.perm,
                        static_cast<const T*>(grid), static_cast<T*>(pot), static_cast<T*>(force),
                        part3, g, b.geom);
+  } else if (P == 4) {
+    const unsigned blocks = static_cast<unsigned>((n + 63) / 64);
+    hipLaunchKernelGGL((gather_sorted_planes<T, 4>), dim3(blocks), dim3(256), 0, st,
+                       static_cast<long>(n), static_cast<const T*>(b.sorted), b.perm,
+                       static_cast<const T*>(grid), static_cast<T*>(pot), static_cast<T*>(force),
+                       part3, g);
   } else {
     const unsigned blocks = static_cast<unsigned>((n + 255) / 256);
     hipLaunchKernelGGL((gather_sorted<T, P>), dim3(blocks), dim3(256), 0, st,
@@ -1113,7 +1218,8 @@ hipError_t gather_brick_p(const GridGeom& g, const Bins& b, int64_t n, const voi
 
 // Number of energy partial-sum triples the binned gather writes.
 int gather_partials(int prec, int p, const Bins& b, int64_t n) {
-  return (prec != PREC_FP64 && p > 4) ? b.geom.nbricks : static_cast<int>((n + 255) / 256);
+  if (prec != PREC_FP64 && p > 4) return b.geom.nbricks;
+  return static_cast<int>(p == 4 ? (n + 63) / 64 : (n + 255) / 256);
 }
 
 hipError_t launch_bin(int prec, const GridGeom& g, const Bins& b, int64_t n, const void* pos,
