@@ -1,0 +1,80 @@
+"""GPU checks of the work splits of the Kronecker operator.
+
+* The stage-1 split (workgroups per 64-position tile, chosen per plan and by
+  the autotuner) only changes which workgroup computes which output tile, and
+  the grid-sum partials are reduced by one fixed workgroup whatever the split:
+  the operator's output is bit-identical for every split.
+* The stage-2 split (term ranges per slab, and for 96 x 96 slabs pairs of
+  terms per step) changes which terms share an FP32 accumulator and the
+  order in which the partial slabs are summed: results agree within 1e-5 of
+  the largest value, the FP16X3 grid tolerance of the parity tests (the
+  per-term contributions exceed the result by the kernel's cancellation, so
+  FP32 reordering moves it by a few 1e-6; measured 1.4e-6 on a 96^3 grid).
+Both on a 96^3 grid (two-stream stage 2) and a non-cubic one (one stream).
+"""
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+SHAPES = [((96.0, 96.0, 96.0), (96, 96, 96), 24), ((40.0, 50.0, 60.0), (40, 50, 60), 16)]
+
+
+def make_plan(box, grid, rank, prec, env):
+    from paper_2601_18838_amd import kpme
+    saved = {k: os.environ.get(k) for k in env}
+    os.environ.update({k: str(v) for k, v in env.items()})
+    try:
+        return kpme.Plan(box, grid, 4, 0.34, rank=rank, precision=prec, max_particles=16)
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+def random_grid(grid, seed):
+    rng = np.random.default_rng(seed)
+    return torch.tensor(rng.standard_normal(grid), dtype=torch.float32, device="cuda")
+
+
+@pytest.mark.parametrize("prec", ["fp16x3", "bf16x3"])
+@pytest.mark.parametrize("shape", SHAPES, ids=["96cubed", "40x50x60"])
+def test_stage1_split_is_bit_invariant(shape, prec):
+    box, grid, rank = shape
+    print(f"[splits] stage 1 {grid} {prec}", flush=True)
+    q = random_grid(grid, 11)
+    outs = []
+    for s in (1, 2, 3, 6):
+        pl = make_plan(box, grid, rank, prec, {"KPME_STAGE1_SPLIT": s, "KPME_STAGE2_PARTS": 3})
+        assert pl.stage1_split() == s
+        outs.append(pl.skp_apply(q).cpu().numpy())
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=["96cubed", "40x50x60"])
+def test_stage2_parts_agree(shape):
+    box, grid, rank = shape
+    print(f"[splits] stage 2 {grid}", flush=True)
+    q = random_grid(grid, 12)
+    outs = []
+    for parts in (1, 2, 3, 5, 8):
+        pl = make_plan(box, grid, rank, "fp16x3", {"KPME_STAGE2_PARTS": parts})
+        assert pl.stage2_parts() == min(parts, rank, 8)
+        outs.append(pl.skp_apply(q).cpu().double().numpy())
+    ref = outs[0]
+    scale = np.abs(ref).max()
+    for o in outs[1:]:
+        assert np.abs(o - ref).max() <= 1e-5 * scale
