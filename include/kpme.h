@@ -156,8 +156,10 @@ kpme_status kpme_energy(kpme_plan_t plan, int64_t n, const void* q,
 /* The whole reciprocal path in one call (Alg. 4 on one device): bin the
  * particles by grid brick once, spread, apply the Kronecker operator with its
  * correction, gather potentials and forces, reduce the energies.  pot, force
- * and energy4 as above (pot and force may be NULL; energy4 may be NULL).
- * Uses the plan's internal grids. */
+ * and energy4 as above (pot and force may be NULL; energy4 may be NULL);
+ * here E_rec is taken as 1/2 sum_k Q(k) Phi(k) over the grid, which equals
+ * 1/2 sum_i q_i pot_i because each particle's B-spline weights sum to one
+ * (the same value up to rounding).  Uses the plan's internal grids. */
 kpme_status kpme_evaluate(kpme_plan_t plan, int64_t n, const void* pos,
                           const void* q, void* pot, void* force,
                           double* energy4, void* stream);

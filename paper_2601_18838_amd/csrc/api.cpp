@@ -125,8 +125,8 @@ struct kpme_plan_s {
   void* Q2g = nullptr;        // adjoint: spread of the upstream potential gradient
   void* Psig = nullptr;       // adjoint: Theta applied to it
   void* sorted2 = nullptr;    // adjoint: binned (x, y, z, g_pot)
-  double* part3 = nullptr;    // energy partial sums of the binned gather (per workgroup)
-  int gather_blocks = 0;
+  double* epart = nullptr;    // finalize: per-workgroup sums of Q * Phi
+  double* qpart = nullptr;    // scatter: per-workgroup (sum q, sum q^2)
   // per-stage hipEvent pairs recorded on the calling stream while profiling
   bool prof_on = false;
   std::vector<hipEvent_t> prof_ev[KPME_NUM_STAGES][2];
@@ -753,11 +753,14 @@ kpme_status kpme_plan_create(kpme_plan_t* plan, const double box[3], const int g
     if ((e = hipMemset(bn.count, 0, nb1 * sizeof(int))) != hipSuccess) break;
     if ((e = plan_alloc(pl, &tmp, 4 * static_cast<size_t>(bg.nbricks) * sizeof(double))) != hipSuccess) break;
     pl->part2 = static_cast<double*>(tmp);  // two (sum, max) sets: forward, adjoint
-    // energy partials of the binned gather: one triple per brick or per 256
-    // particles (gather_partials)
-    pl->gather_blocks = std::max(static_cast<int>((max_particles + 63) / 64), bg.nbricks);
-    if ((e = plan_alloc(pl, &tmp, 3 * static_cast<size_t>(pl->gather_blocks) * sizeof(double))) != hipSuccess) break;
-    pl->part3 = static_cast<double*>(tmp);
+    // energy partials: finalize (one per workgroup) and the scatter (one pair
+    // per workgroup, at most one per 256 particles or one in all)
+    const size_t nfin = static_cast<size_t>(finalize_blocks(grid[0], grid[1], grid[2]));
+    if ((e = plan_alloc(pl, &tmp, nfin * sizeof(double))) != hipSuccess) break;
+    pl->epart = static_cast<double*>(tmp);
+    const size_t nq = std::max<size_t>(1, static_cast<size_t>((max_particles + 255) / 256));
+    if ((e = plan_alloc(pl, &tmp, 2 * nq * sizeof(double))) != hipSuccess) break;
+    pl->qpart = static_cast<double*>(tmp);
     if ((e = plan_alloc(pl, &pl->Q2g, G * es)) != hipSuccess) break;
     if ((e = plan_alloc(pl, &pl->Psig, G * es)) != hipSuccess) break;
     if ((e = plan_alloc(pl, &pl->sorted2, nmax * 4 * es)) != hipSuccess) break;
@@ -811,16 +814,17 @@ kpme_status check_n(kpme_plan_t plan, int64_t n) {
 kpme_status do_spread(kpme_plan_t plan, int64_t n, const void* pos, const void* q, void* grid,
                       hipStream_t st) {
   StageTimer tm(plan, KPME_STAGE_SPREAD, st);
-  hipError_t e = launch_bin(plan->prec, plan->geom(), plan->bins, n, pos, q, st);
+  hipError_t e = launch_bin(plan->prec, plan->geom(), plan->bins, n, pos, q, plan->qpart, st);
   if (e == hipSuccess)
     e = launch_spread_binned(plan->prec, plan->geom(), plan->bins, grid, plan->part2, st);
   return from_hip(e, "spread");
 }
 
 // sum_ready: the spread has already left (sum, scale) of `in` in scalars[0..1].
+// epart (may be NULL): finalize's per-workgroup sums of in * out.
 kpme_status do_skp(kpme_plan_t plan, const void* in, void* out, hipStream_t st,
                    bool sum_ready = false, double* scalars = nullptr,
-                   const double* part2 = nullptr) {
+                   const double* part2 = nullptr, double* epart = nullptr) {
   if (!scalars) scalars = plan->scalars;
   if (!part2) part2 = plan->part2;
   SkpArgs a;
@@ -830,6 +834,8 @@ kpme_status do_skp(kpme_plan_t plan, const void* in, void* out, hipStream_t st,
   a.r0 = plan->r0; a.R = plan->R; a.nparts = plan->nparts;
   a.s1_split = plan->s1_split;
   a.Q = in; a.Phi = out;
+  a.eQ = in;
+  a.epart = epart;
   for (int k = 0; k < 2; ++k) { a.A[k] = plan->A[k]; a.B[k] = plan->B[k]; a.C[k] = plan->C[k]; a.Y[k] = plan->Y[k]; }
   a.Phi_part = plan->Phi_part;
   a.vec = plan->vec;
@@ -1035,20 +1041,32 @@ kpme_status kpme_evaluate(kpme_plan_t plan, int64_t n, const void* pos, const vo
   if (n > 0 && (!pos || !q)) return fail(KPME_ERROR_INVALID_VALUE, "pos and q must not be NULL");
   hipStream_t st = static_cast<hipStream_t>(stream);
   if ((s = do_spread(plan, n, pos, q, plan->Qg, st)) != KPME_SUCCESS) return s;
-  if ((s = do_skp(plan, plan->Qg, plan->Phig, st, true)) != KPME_SUCCESS) return s;
-  const int nblk = n > 0 ? gather_partials(plan->prec, plan->p, plan->bins, n) : 0;
-  if (pot || force || energy4) {
-    // the particles are still binned from the spread: gather in binned order,
-    // with the energy partial sums of each workgroup
+  // energies from the grid: finalize leaves the sums of Q * Phi, the scatter
+  // those of q and q^2; the gather's first workgroup (or, without a gather, a
+  // one-workgroup kernel) combines them
+  if ((s = do_skp(plan, plan->Qg, plan->Phig, st, true, nullptr, nullptr,
+                  energy4 ? plan->epart : nullptr)) != KPME_SUCCESS)
+    return s;
+  EnergyJob ej;
+  if (energy4) {
+    ej.epart = plan->epart;
+    ej.nfin = finalize_blocks(plan->K[0], plan->K[1], plan->K[2]);
+    ej.qpart = plan->qpart;
+    ej.nq = scatter_partials(plan->bins, n);
+    ej.beta = plan->beta;
+    ej.volume = plan->box[0] * plan->box[1] * plan->box[2];
+    ej.e4 = energy4;
+  }
+  const bool gather = (pot || force) && n > 0;
+  if (gather) {
+    // the particles are still binned from the spread: gather in binned order
     StageTimer tm(plan, KPME_STAGE_GATHER, st);
     hipError_t e = launch_gather_binned(plan->prec, plan->geom(), plan->bins, n, plan->Phig,
-                                        pot, force, energy4 ? plan->part3 : nullptr, st);
+                                        pot, force, ej, st);
     if ((s = from_hip(e, "gather")) != KPME_SUCCESS) return s;
-  }
-  if (energy4) {
+  } else if (energy4) {
     StageTimer tm(plan, KPME_STAGE_ENERGY, st);
-    const double V = plan->box[0] * plan->box[1] * plan->box[2];
-    return from_hip(launch_energy_final(plan->part3, nblk, plan->beta, V, energy4, st), "energy");
+    return from_hip(launch_energy_job(ej, st), "energy");
   }
   return KPME_SUCCESS;
 }

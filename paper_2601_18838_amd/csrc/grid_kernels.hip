@@ -59,6 +59,57 @@ __global__ void zero_kernel(T* p, long n) {
     p[i] = T(0);
 }
 
+// The energy job of an evaluation (see EnergyJob), in a fixed order; one
+// workgroup, every thread calls it.
+__device__ void run_energy_job(const EnergyJob& ej) {
+  __shared__ double red[48];
+  double v[3] = {0.0, 0.0, 0.0};  // sum Q Phi, sum q, sum q^2
+  const int nt = blockDim.x;
+  for (int i0 = threadIdx.x; i0 < ej.nfin; i0 += 4 * nt) {  // four loads in flight
+    double x[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) x[u] = i0 + u * nt < ej.nfin ? ej.epart[i0 + u * nt] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[0] += x[u];
+  }
+  for (int i0 = threadIdx.x; i0 < ej.nq; i0 += 4 * nt) {
+    double2 x[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      x[u] = i0 + u * nt < ej.nq ? *reinterpret_cast<const double2*>(&ej.qpart[2 * (i0 + u * nt)])
+                                 : double2{0.0, 0.0};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      v[1] += x[u].x;
+      v[2] += x[u].y;
+    }
+  }
+  block_reduce<3, 3>(v, red);
+  if (threadIdx.x == 0) {
+    const double pi = 3.141592653589793238462643383279502884;
+    const double e_rec = 0.5 * v[0];
+    const double e_self = -ej.beta / sqrt(pi) * v[2];
+    const double e_neu = -pi * v[1] * v[1] / (2.0 * ej.volume * ej.beta * ej.beta);
+    ej.e4[0] = e_rec;
+    ej.e4[1] = e_self;
+    ej.e4[2] = e_neu;
+    ej.e4[3] = e_rec + e_self + e_neu;
+  }
+}
+
+__global__ __launch_bounds__(256) void energy_job_kernel(EnergyJob ej) { run_energy_job(ej); }
+
+// Per-workgroup FP64 (sum q, sum q^2) of the scatter.  Every thread calls it.
+__device__ void charge_partials(double s1, double s2, double* qpart) {
+  __shared__ double red[32];
+  double v[2] = {s1, s2};
+  block_reduce<2, 2>(v, red);
+  if (threadIdx.x == 0) {
+    qpart[2 * blockIdx.x] = v[0];
+    qpart[2 * blockIdx.x + 1] = v[1];
+  }
+}
+
 template <typename T, int P>
 __global__ __launch_bounds__(256) void spread_atomic(long n, const T* __restrict__ pos,
                                                      const T* __restrict__ q,
@@ -289,7 +340,8 @@ __global__ __launch_bounds__(256) void bin_scan_scatter(long n, const T* __restr
                                                         const int* __restrict__ count,
                                                         int nbricks, int* __restrict__ offset,
                                                         T* __restrict__ sorted,
-                                                        int* __restrict__ perm) {
+                                                        int* __restrict__ perm,
+                                                        double* __restrict__ qpart) {
   __shared__ int off[kLdsHist + 1];
   __shared__ int wsum[4];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -322,17 +374,22 @@ __global__ __launch_bounds__(256) void bin_scan_scatter(long n, const T* __restr
   __syncthreads();
   if (blockIdx.x == 0)
     for (int b = t; b <= nbricks; b += 256) offset[b] = off[b];
+  double s1 = 0.0, s2 = 0.0;
 #pragma unroll
   for (int k = 0; k < kBinPer; ++k) {
     const long i = (blockIdx.x * static_cast<long>(kBinPer) + k) * 256 + t;
     if (i >= n) break;
     const long d = off[brick_of[i]] + slot[i];
+    const T qi = q[i];
     sorted[4 * d + 0] = pos[3 * i + 0];
     sorted[4 * d + 1] = pos[3 * i + 1];
     sorted[4 * d + 2] = pos[3 * i + 2];
-    sorted[4 * d + 3] = q[i];
+    sorted[4 * d + 3] = qi;
     perm[d] = static_cast<int>(i);
+    s1 += static_cast<double>(qi);
+    s2 += static_cast<double>(qi) * static_cast<double>(qi);
   }
+  if (qpart) charge_partials(s1, s2, qpart);
 }
 
 template <typename T>
@@ -342,15 +399,22 @@ __global__ __launch_bounds__(256) void bin_scatter(long n, const T* __restrict__
                                                    const int* __restrict__ slot,
                                                    const int* __restrict__ offset,
                                                    T* __restrict__ sorted,
-                                                   int* __restrict__ perm) {
+                                                   int* __restrict__ perm,
+                                                   double* __restrict__ qpart) {
   const long i = blockIdx.x * static_cast<long>(blockDim.x) + threadIdx.x;
-  if (i >= n) return;
-  const long d = offset[brick_of[i]] + slot[i];
-  sorted[4 * d + 0] = pos[3 * i + 0];
-  sorted[4 * d + 1] = pos[3 * i + 1];
-  sorted[4 * d + 2] = pos[3 * i + 2];
-  sorted[4 * d + 3] = q[i];
-  perm[d] = static_cast<int>(i);
+  double s1 = 0.0, s2 = 0.0;
+  if (i < n) {
+    const long d = offset[brick_of[i]] + slot[i];
+    const T qi = q[i];
+    sorted[4 * d + 0] = pos[3 * i + 0];
+    sorted[4 * d + 1] = pos[3 * i + 1];
+    sorted[4 * d + 2] = pos[3 * i + 2];
+    sorted[4 * d + 3] = qi;
+    perm[d] = static_cast<int>(i);
+    s1 = static_cast<double>(qi);
+    s2 = s1 * s1;
+  }
+  if (qpart) charge_partials(s1, s2, qpart);
 }
 
 // Owner-computes spread: one workgroup per grid brick.  It visits the
@@ -614,19 +678,18 @@ __global__ __launch_bounds__(512) void spread_combine(const T* __restrict__ tile
 // Gather in binned order (neighbouring threads read neighbouring grid
 // values); results are written back to the caller's order through perm.
 // Each workgroup also writes its FP64 partial sums (q pot, q, q^2) to
-// part3[block] for the energy reduction.
+// (The first workgroup also runs the evaluation's energy job.)
 template <typename T, int P>
 __global__ __launch_bounds__(256) void gather_sorted(long n, const T* __restrict__ sorted,
                                                      const int* __restrict__ perm,
                                                      const T* __restrict__ grid,
                                                      T* __restrict__ pot,
                                                      T* __restrict__ force,
-                                                     double* __restrict__ part3, GridGeom g) {
-  __shared__ double red[48];
+                                                     EnergyJob ej, GridGeom g) {
+  if (ej.e4 && blockIdx.x == 0) run_energy_job(ej);
   // neighbouring particle blocks (neighbouring bricks) share an XCD's L2
   const int blk = xcd_order(blockIdx.x, gridDim.x);
   const long s = blk * static_cast<long>(blockDim.x) + threadIdx.x;
-  double e0 = 0, e1 = 0, e2 = 0;
   if (s < n) {
     T w[3][P], dw[3][P];
     int base[3];
@@ -680,16 +743,6 @@ __global__ __launch_bounds__(256) void gather_sorted(long n, const T* __restrict
       force[3 * i + 1] = -qi * g1 * static_cast<T>(K2 / g.L[1]);
       force[3 * i + 2] = -qi * g2 * static_cast<T>(K3 / g.L[2]);
     }
-    const double qd = static_cast<double>(qi);
-    e0 = qd * static_cast<double>(phi);
-    e1 = qd;
-    e2 = qd * qd;
-  }
-  if (part3) {
-    double v[3] = {e0, e1, e2};
-    block_reduce<3, 3>(v, red);
-    if (threadIdx.x == 0)
-      for (int k = 0; k < 3; ++k) part3[3 * blk + k] = v[k];
   }
 }
 
@@ -704,14 +757,12 @@ __global__ __launch_bounds__(256) void gather_sorted_planes(long n, const T* __r
                                                             const T* __restrict__ grid,
                                                             T* __restrict__ pot,
                                                             T* __restrict__ force,
-                                                            double* __restrict__ part3,
-                                                            GridGeom g) {
+                                                            EnergyJob ej, GridGeom g) {
   static_assert(P == 4, "one lane per plane, four lanes per particle");
-  __shared__ double red[48];
+  if (ej.e4 && blockIdx.x == 0) run_energy_job(ej);
   const int blk = xcd_order(blockIdx.x, gridDim.x);
   const long s = (blk * static_cast<long>(blockDim.x) + threadIdx.x) / P;
   const int a = threadIdx.x % P;
-  double e0 = 0, e1 = 0, e2 = 0;
   T phi = 0, g0 = 0, g1 = 0, g2 = 0;
   const bool live = s < n;
   T qi = 0;
@@ -779,16 +830,6 @@ __global__ __launch_bounds__(256) void gather_sorted_planes(long n, const T* __r
       force[3 * i + 1] = -qi * g1 * static_cast<T>(g.K[1] / g.L[1]);
       force[3 * i + 2] = -qi * g2 * static_cast<T>(g.K[2] / g.L[2]);
     }
-    const double qd = static_cast<double>(qi);
-    e0 = qd * static_cast<double>(phi);
-    e1 = qd;
-    e2 = qd * qd;
-  }
-  if (part3) {
-    double v[3] = {e0, e1, e2};
-    block_reduce<3, 3>(v, red);
-    if (threadIdx.x == 0)
-      for (int k = 0; k < 3; ++k) part3[3 * blk + k] = v[k];
   }
 }
 
@@ -798,18 +839,18 @@ __global__ __launch_bounds__(256) void gather_sorted_planes(long n, const T* __r
 // wrapped periodically -- then interpolates those particles from LDS (every
 // stencil point is inside the tile: no masking).  Results go back to the
 // caller's order through perm; each workgroup writes its FP64 partial sums
-// (q pot, q, q^2) to part3[brick] for the energy reduction.
+// (The first workgroup also runs the evaluation's energy job.)
 template <typename T, int P>
 __global__ __launch_bounds__(256) void gather_brick(const T* __restrict__ sorted,
                                                     const int* __restrict__ offset,
                                                     const int* __restrict__ perm,
                                                     const T* __restrict__ grid,
                                                     T* __restrict__ pot, T* __restrict__ force,
-                                                    double* __restrict__ part3, GridGeom g,
+                                                    EnergyJob ej, GridGeom g,
                                                     BinGeom bg) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   T* tile = reinterpret_cast<T*>(smem);
-  __shared__ double red[48];
+  if (ej.e4 && blockIdx.x == 0) run_energy_job(ej);
   const int brick = xcd_order(blockIdx.x, gridDim.x);
   int own[3], rest = brick;
   own[2] = rest % bg.nb[2]; rest /= bg.nb[2];
@@ -835,7 +876,6 @@ __global__ __launch_bounds__(256) void gather_brick(const T* __restrict__ sorted
     tile[e] = grid[(static_cast<long>(k0) * K2 + k1) * K3 + k2];
   }
   __syncthreads();
-  double e0 = 0, e1 = 0, e2 = 0;
   const int i0 = offset[brick], i1 = offset[brick + 1];
   for (int s = i0 + threadIdx.x; s < i1; s += blockDim.x) {
     T w[3][P], dw[3][P];
@@ -880,16 +920,6 @@ __global__ __launch_bounds__(256) void gather_brick(const T* __restrict__ sorted
       force[3 * i + 1] = -qi * g1 * static_cast<T>(K2 / g.L[1]);
       force[3 * i + 2] = -qi * g2 * static_cast<T>(K3 / g.L[2]);
     }
-    const double qd = static_cast<double>(qi);
-    e0 += qd * static_cast<double>(phi);
-    e1 += qd;
-    e2 += qd * qd;
-  }
-  if (part3) {
-    double v[3] = {e0, e1, e2};
-    block_reduce<3, 3>(v, red);
-    if (threadIdx.x == 0)
-      for (int k = 0; k < 3; ++k) part3[3 * brick + k] = v[k];
   }
 }
 
@@ -1143,21 +1173,22 @@ hipError_t bin_t(const GridGeom& g, const Bins& b, int64_t n, const void* pos, h
 }
 
 template <typename T>
-hipError_t scatter_t(const Bins& b, int64_t n, const void* pos, const void* q, hipStream_t st) {
+hipError_t scatter_t(const Bins& b, int64_t n, const void* pos, const void* q, double* qpart,
+                     hipStream_t st) {
   if (scan_in_scatter(b, n)) {
     // at least one workgroup: it stores the offsets also for n = 0
     const unsigned blocks = static_cast<unsigned>(scatter_blocks(n));
     hipLaunchKernelGGL((bin_scan_scatter<T>), dim3(blocks), dim3(256), 0, st,
                        static_cast<long>(n), static_cast<const T*>(pos), static_cast<const T*>(q),
                        b.brick_of, b.slot, b.count, b.geom.nbricks, b.offset,
-                       static_cast<T*>(b.sorted), b.perm);
+                       static_cast<T*>(b.sorted), b.perm, qpart);
     return hipGetLastError();
   }
   if (n == 0) return hipSuccess;
   const unsigned blocks = static_cast<unsigned>((n + 255) / 256);
   hipLaunchKernelGGL((bin_scatter<T>), dim3(blocks), dim3(256), 0, st, static_cast<long>(n),
                      static_cast<const T*>(pos), static_cast<const T*>(q), b.brick_of, b.slot,
-                     b.offset, static_cast<T*>(b.sorted), b.perm);
+                     b.offset, static_cast<T*>(b.sorted), b.perm, qpart);
   return hipGetLastError();
 }
 
@@ -1190,25 +1221,25 @@ hipError_t spread_brick_p(const GridGeom& g, const Bins& b, const void* src, voi
 // brick and smaller stencils do not amortise the staging).
 template <typename T, int P>
 hipError_t gather_brick_p(const GridGeom& g, const Bins& b, int64_t n, const void* grid,
-                          void* pot, void* force, double* part3, hipStream_t st) {
+                          void* pot, void* force, const EnergyJob& ej, hipStream_t st) {
   if (sizeof(T) == 4 && P > 4) {
     const int ntile = (b.geom.edge[0] + P - 1) * (b.geom.edge[1] + P - 1) * (b.geom.edge[2] + P - 1);
     hipLaunchKernelGGL((gather_brick<T, P>), dim3(b.geom.nbricks), dim3(128), sizeof(T) * ntile,
                        st, static_cast<const T*>(b.sorted), b.offset, b.perm,
                        static_cast<const T*>(grid), static_cast<T*>(pot), static_cast<T*>(force),
-                       part3, g, b.geom);
+                       ej, g, b.geom);
   } else if (P == 4) {
     const unsigned blocks = static_cast<unsigned>((n + 63) / 64);
     hipLaunchKernelGGL((gather_sorted_planes<T, 4>), dim3(blocks), dim3(256), 0, st,
                        static_cast<long>(n), static_cast<const T*>(b.sorted), b.perm,
                        static_cast<const T*>(grid), static_cast<T*>(pot), static_cast<T*>(force),
-                       part3, g);
+                       ej, g);
   } else {
     const unsigned blocks = static_cast<unsigned>((n + 255) / 256);
     hipLaunchKernelGGL((gather_sorted<T, P>), dim3(blocks), dim3(256), 0, st,
                        static_cast<long>(n), static_cast<const T*>(b.sorted), b.perm,
                        static_cast<const T*>(grid), static_cast<T*>(pot), static_cast<T*>(force),
-                       part3, g);
+                       ej, g);
   }
   return hipGetLastError();
 }
@@ -1216,17 +1247,18 @@ hipError_t gather_brick_p(const GridGeom& g, const Bins& b, int64_t n, const voi
 
 }  // namespace
 
-// Number of energy partial-sum triples the binned gather writes.
-int gather_partials(int prec, int p, const Bins& b, int64_t n) {
-  if (prec != PREC_FP64 && p > 4) return b.geom.nbricks;
-  return static_cast<int>(p == 4 ? (n + 63) / 64 : (n + 255) / 256);
+// Number of (sum q, sum q^2) pairs the scatter writes.
+int scatter_partials(const Bins& b, int64_t n) {
+  if (scan_in_scatter(b, n)) return static_cast<int>(scatter_blocks(n));
+  return static_cast<int>((n + 255) / 256);
 }
 
 hipError_t launch_bin(int prec, const GridGeom& g, const Bins& b, int64_t n, const void* pos,
-                      const void* q, hipStream_t st) {
+                      const void* q, double* qpart, hipStream_t st) {
   hipError_t e = prec == PREC_FP64 ? bin_t<double>(g, b, n, pos, st) : bin_t<float>(g, b, n, pos, st);
   if (e != hipSuccess) return e;
-  return prec == PREC_FP64 ? scatter_t<double>(b, n, pos, q, st) : scatter_t<float>(b, n, pos, q, st);
+  return prec == PREC_FP64 ? scatter_t<double>(b, n, pos, q, qpart, st)
+                           : scatter_t<float>(b, n, pos, q, qpart, st);
 }
 
 hipError_t launch_spread_binned(int prec, const GridGeom& g, const Bins& b, void* grid,
@@ -1242,15 +1274,15 @@ hipError_t launch_spread_binned(int prec, const GridGeom& g, const Bins& b, void
 }
 
 hipError_t launch_gather_binned(int prec, const GridGeom& g, const Bins& b, int64_t n,
-                                const void* grid, void* pot, void* force, double* part3,
+                                const void* grid, void* pot, void* force, const EnergyJob& ej,
                                 hipStream_t st) {
   if (n == 0) return hipSuccess;
   if (prec == PREC_FP64) {
-#define CALL(P) gather_brick_p<double, P>(g, b, n, grid, pot, force, part3, st)
+#define CALL(P) gather_brick_p<double, P>(g, b, n, grid, pot, force, ej, st)
     KPME_ORDER_SWITCH(g.p, CALL)
 #undef CALL
   }
-#define CALL(P) gather_brick_p<float, P>(g, b, n, grid, pot, force, part3, st)
+#define CALL(P) gather_brick_p<float, P>(g, b, n, grid, pot, force, ej, st)
   KPME_ORDER_SWITCH(g.p, CALL)
 #undef CALL
 }
@@ -1302,10 +1334,9 @@ hipError_t launch_gather_backward(int prec, const GridGeom& g, const Bins& b, in
 #undef CALL
 }
 
-hipError_t launch_energy_final(const double* part3, int nblocks, double beta, double volume,
-                               double* energy4, hipStream_t st) {
-  hipLaunchKernelGGL(energy_final, dim3(1), dim3(256), 0, st, part3, nblocks, beta, volume,
-                     energy4);
+hipError_t launch_energy_job(const EnergyJob& ej, hipStream_t st) {
+  if (!ej.e4) return hipSuccess;
+  hipLaunchKernelGGL(energy_job_kernel, dim3(1), dim3(256), 0, st, ej);
   return hipGetLastError();
 }
 

@@ -40,6 +40,10 @@ struct SkpArgs {
   // split precisions: stage 1 reduces these (sum, max) pairs into sumQ
   const double* sum_part;
   int sum_np;
+  // energy from the grid (may be NULL): finalize writes, per workgroup, the
+  // FP64 sum of eQ * Phi over the values it stores (finalize_blocks() of them)
+  const void* eQ;
+  double* epart;
   double* sumQ;          // 2 doubles: sum(Q), then the FP16X3 grid scale
   double c0;             // theta_hat_R(0)
   float sy, st;          // FP16X3 powers of two applied to Y and T before splits
@@ -112,17 +116,35 @@ hipError_t launch_spread_atomic(int prec, const GridGeom& g, int64_t n, const vo
 hipError_t launch_gather_direct(int prec, const GridGeom& g, int64_t n, const void* pos,
                                 const void* q, const void* grid, void* pot, void* force,
                                 hipStream_t st);
+// qpart: per scatter workgroup the FP64 (sum q, sum q^2), scatter_partials()
+// pairs.
 hipError_t launch_bin(int prec, const GridGeom& g, const Bins& b, int64_t n, const void* pos,
-                      const void* q, hipStream_t st);
+                      const void* q, double* qpart, hipStream_t st);
+int scatter_partials(const Bins& b, int64_t n);
+
+// Final energies of an evaluation, combined by one workgroup: E_rec = 1/2 of
+// the sum of the finalize partials (sum over grid points of Q Phi, equal to
+// 1/2 sum_i q_i phi_i since the B-spline weights of a particle sum to one),
+// E_self = -beta / sqrt(pi) sum q^2, E_neutral = -pi (sum q)^2 / (2 V beta^2),
+// their sum; e4 = NULL: nothing to do.
+struct EnergyJob {
+  const double* epart = nullptr;
+  int nfin = 0;
+  const double* qpart = nullptr;
+  int nq = 0;
+  double beta = 0, volume = 0;
+  double* e4 = nullptr;
+};
+hipError_t launch_energy_job(const EnergyJob& ej, hipStream_t st);
+int finalize_blocks(int K1, int K2, int K3);
 // part2 (2 doubles per brick): the tile's sum and largest magnitude.  src:
 // binned (x, y, z, charge) records to spread (NULL: the plan's own bins).
 hipError_t launch_spread_binned(int prec, const GridGeom& g, const Bins& b, void* grid,
                                 double* part2, hipStream_t st, const void* src = nullptr);
-// part3 (may be NULL): energy partial sums, gather_partials() triples.
+// ej.e4 != NULL: the gather's first workgroup also runs the energy job.
 hipError_t launch_gather_binned(int prec, const GridGeom& g, const Bins& b, int64_t n,
-                                const void* grid, void* pot, void* force, double* part3,
+                                const void* grid, void* pot, void* force, const EnergyJob& ej,
                                 hipStream_t st);
-int gather_partials(int prec, int p, const Bins& b, int64_t n);
 hipError_t launch_resort_charges(int prec, const Bins& b, int64_t n, const void* gval,
                                  void* sorted2, hipStream_t st);
 hipError_t launch_gather_backward(int prec, const GridGeom& g, const Bins& b, int64_t n,
@@ -130,8 +152,6 @@ hipError_t launch_gather_backward(int prec, const GridGeom& g, const Bins& b, in
                                   const void* g_pot, const double* sumq, double beta,
                                   double volume, void* grad_pos, void* grad_q,
                                   hipStream_t st);
-hipError_t launch_energy_final(const double* part3, int nblocks, double beta, double volume,
-                               double* energy4, hipStream_t st);
 // Combines np (sum, max) pairs: out[0] = sum, out[1] = FP16X3 grid scale.
 hipError_t launch_sum_final(const double* part2, int np, double* out, hipStream_t st);
 hipError_t launch_energy(int prec, int64_t n, const void* q, const void* pot, double beta,

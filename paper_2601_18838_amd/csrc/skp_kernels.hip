@@ -753,13 +753,18 @@ __global__ __launch_bounds__(512) void stage2_k4(
 // Sum the partial slabs [part][k3][k1][k2] in order, transpose to
 // [k1][k2][k3] and subtract c * sum(Q).  One workgroup per (k1, 32 x 32 tile
 // of k2 x k3); interior tiles of 4-aligned extents move float4 vectors.
+// With epart, the workgroup also writes the FP64 sum of Q * Phi over the
+// values it stores (the reciprocal energy is half the total).
 template <typename A, typename O>
 __global__ __launch_bounds__(256) void finalize(const A* __restrict__ part, int nparts,
                                                 O* __restrict__ Phi, int K1, int K2,
                                                 int K3, const double* __restrict__ sumQ,
                                                 double c0, const double* __restrict__ qscale,
-                                                double const_scale) {
+                                                double const_scale, const O* __restrict__ Q,
+                                                double* __restrict__ epart) {
   __shared__ A tile[32][33];
+  __shared__ double red[16];
+  double e = 0.0;
   const int k1 = blockIdx.z, k2b = blockIdx.x * 32, k3b = blockIdx.y * 32;
   const int t = threadIdx.x;
   const long pstride = static_cast<long>(K3) * K1 * K2;
@@ -799,16 +804,36 @@ __global__ __launch_bounds__(256) void finalize(const A* __restrict__ part, int 
     o.y = unscale * tile[c4 + 1][r] - corr;
     o.z = unscale * tile[c4 + 2][r] - corr;
     o.w = unscale * tile[c4 + 3][r] - corr;
-    *reinterpret_cast<float4*>(&Phi[(static_cast<long>(k1) * K2 + k2b + r) * K3 + k3b + c4]) = o;
+    const long at = (static_cast<long>(k1) * K2 + k2b + r) * K3 + k3b + c4;
+    *reinterpret_cast<float4*>(&Phi[at]) = o;
+    if (epart) {
+      const float4 qv = *reinterpret_cast<const float4*>(&Q[at]);
+      e = static_cast<double>(qv.x) * o.x + static_cast<double>(qv.y) * o.y +
+          static_cast<double>(qv.z) * o.z + static_cast<double>(qv.w) * o.w;
+    }
   } else {
     for (int j = t >> 5; j < 32; j += 8) {
       const int k2 = k2b + j, k3 = k3b + (t & 31);
-      if (k2 < K2 && k3 < K3)
-        Phi[(static_cast<long>(k1) * K2 + k2) * K3 + k3] =
-            static_cast<O>(unscale * tile[t & 31][j] - corr);
+      if (k2 < K2 && k3 < K3) {
+        const long at = (static_cast<long>(k1) * K2 + k2) * K3 + k3;
+        const O v = static_cast<O>(unscale * tile[t & 31][j] - corr);
+        Phi[at] = v;
+        if (epart) e += static_cast<double>(Q[at]) * static_cast<double>(v);
+      }
     }
   }
+  if (epart) {
+    double v[1] = {e};
+    block_reduce<1, 1>(v, red);
+    if (t == 0) epart[(static_cast<long>(blockIdx.z) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = v[0];
+  }
 }
+
+}  // namespace
+
+int finalize_blocks(int K1, int K2, int K3) { return ((K2 + 31) / 32) * ((K3 + 31) / 32) * K1; }
+
+namespace {
 
 // Fixed-order FP64 sum and max |x| of a grid: per-block partials, then one
 // block combines them.
@@ -1030,12 +1055,13 @@ hipError_t launch_skp_finalize(const SkpArgs& a, hipStream_t st) {
     hipLaunchKernelGGL((finalize<double, double>), gf, dim3(256), 0, st,
                        static_cast<const double*>(a.Phi_part), a.nparts,
                        static_cast<double*>(a.Phi), a.K[0], a.K[1], a.K[2], a.sumQ, a.c0,
-                       nullptr, 1.0);
+                       nullptr, 1.0, static_cast<const double*>(a.eQ), a.epart);
   else
     hipLaunchKernelGGL((finalize<float, float>), gf, dim3(256), 0, st,
                        static_cast<const float*>(a.Phi_part), a.nparts,
                        static_cast<float*>(a.Phi), a.K[0], a.K[1], a.K[2], a.sumQ, a.c0,
-                       a.prec == PREC_FP16X3 ? a.sumQ + 1 : nullptr, a.const_scale);
+                       a.prec == PREC_FP16X3 ? a.sumQ + 1 : nullptr, a.const_scale,
+                       static_cast<const float*>(a.eQ), a.epart);
   return hipGetLastError();
 }
 
