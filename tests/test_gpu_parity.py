@@ -182,6 +182,27 @@ def test_empty_and_capacity_edges(prec):
     assert abs(e_a - e_b) < 1e-5 * abs(e_a)
 
 
+@pytest.mark.parametrize("case", ["small_pm1", "ragged_noncubic"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16x3"])
+def test_energy_paths_agree(prec, case):
+    """E_rec comes from the grid (1/2 sum_k Q Phi, combined inside the gather);
+    an energy-only call combines the same partials in its own kernel, and the
+    particle-side sum 1/2 sum_i q_i pot_i of the returned potentials must
+    agree (partition of unity): to rounding, 1e-12 (FP64) or 1e-6 relative."""
+    print(f"[parity] energy paths {case} {prec}", flush=True)
+    box, grid, p, beta, rank, pos, q = make(case)
+    kpme = kp()
+    pl = kpme.Plan(box, grid, p, beta, rank=rank, precision=prec, max_particles=len(q))
+    P, Qc = dev(pos, prec), dev(q, prec)
+    e_full, pot, _ = pl.evaluate(P, Qc)
+    e_only, none_pot, none_f = pl.evaluate(P, Qc, potentials=False, forces=False)
+    assert none_pot is None and none_f is None
+    assert np.array_equal(host(e_full), host(e_only))
+    e_part = 0.5 * float((host(Qc) * host(pot)).sum())
+    tol = 1e-12 if prec == "fp64" else 1e-6
+    assert abs(host(e_full)[0] - e_part) <= tol * abs(e_part)
+
+
 def test_water_100k_mixed_paths_against_fp64():
     """The 1e5-atom water box (96^3, p=4, R from the 1e-6 rule): the mixed
     paths against the FP64 GPU path and the oracle at equal R."""
