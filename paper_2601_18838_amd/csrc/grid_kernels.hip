@@ -891,6 +891,9 @@ __global__ __launch_bounds__(256) void gather_brick(const T* __restrict__ sorted
     }
     T phi = 0, g0 = 0, g1 = 0, g2 = 0;
     constexpr int UB = P <= 8 ? P : 1;
+    // one plane at a time (P^2 values in flight): a fully unrolled stencil
+    // holds every value in registers and leaves one wave per SIMD
+#pragma unroll 1
     for (int a = 0; a < P; ++a) {
       T sa = 0, sa1 = 0, sa2 = 0;
 #pragma unroll UB
