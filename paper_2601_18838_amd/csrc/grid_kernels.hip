@@ -713,6 +713,14 @@ __global__ __launch_bounds__(256) void gather_sorted(long n, const T* __restrict
     for (int a = 0; a < P; ++a) {
       int ka = base[0] - a;
       if (ka < 0) ka += K1;
+      // plane a's weights by selection (no dynamic register indexing)
+      T wa = w[0][0], dwa = dw[0][0];
+#pragma unroll
+      for (int t = 1; t < P; ++t)
+        if (a == t) {
+          wa = w[0][t];
+          dwa = dw[0][t];
+        }
       T sa = 0, sa1 = 0, sa2 = 0;
 #pragma unroll UB
       for (int b = 0; b < P; ++b) {
@@ -730,10 +738,10 @@ __global__ __launch_bounds__(256) void gather_sorted(long n, const T* __restrict
         sa1 += dw[1][b] * sv;
         sa2 += w[1][b] * s2;
       }
-      phi += w[0][a] * sa;
-      g0 += dw[0][a] * sa;
-      g1 += w[0][a] * sa1;
-      g2 += w[0][a] * sa2;
+      phi += wa * sa;
+      g0 += dwa * sa;
+      g1 += wa * sa1;
+      g2 += wa * sa2;
     }
     const long i = perm[s];
     const T qi = sorted[4 * s + 3];
@@ -895,6 +903,13 @@ __global__ __launch_bounds__(256) void gather_brick(const T* __restrict__ sorted
     // holds every value in registers and leaves one wave per SIMD
 #pragma unroll 1
     for (int a = 0; a < P; ++a) {
+      T wa = w[0][0], dwa = dw[0][0];
+#pragma unroll
+      for (int t = 1; t < P; ++t)
+        if (a == t) {
+          wa = w[0][t];
+          dwa = dw[0][t];
+        }
       T sa = 0, sa1 = 0, sa2 = 0;
 #pragma unroll UB
       for (int b = 0; b < P; ++b) {
@@ -910,10 +925,10 @@ __global__ __launch_bounds__(256) void gather_brick(const T* __restrict__ sorted
         sa1 += dw[1][b] * sv;
         sa2 += w[1][b] * s2;
       }
-      phi += w[0][a] * sa;
-      g0 += dw[0][a] * sa;
-      g1 += w[0][a] * sa1;
-      g2 += w[0][a] * sa2;
+      phi += wa * sa;
+      g0 += dwa * sa;
+      g1 += wa * sa1;
+      g2 += wa * sa2;
     }
     const long i = perm[s];
     const T qi = sorted[4L * s + 3];
@@ -969,11 +984,20 @@ __global__ __launch_bounds__(256) void gather_backward(
   }
   // v[0]: W.grid, v[1..3]: derivatives along the three axes (in u units)
   T vf[4] = {0, 0, 0, 0}, vs[4] = {0, 0, 0, 0};
-  constexpr int UA = P <= 4 ? P : 1, UB = P <= 8 ? P : 1;  // loads in flight
-#pragma unroll UA
+  // one plane of Phi and Psi loads in flight (a whole unrolled stencil of
+  // both holds too many registers)
+  constexpr int UB = P <= 8 ? P : 1;
+#pragma unroll 1
   for (int a = 0; a < P; ++a) {
     int ka = base[0] - a;
     if (ka < 0) ka += K1;
+    T wa = w[0][0], dwa = dw[0][0];
+#pragma unroll
+    for (int t = 1; t < P; ++t)
+      if (a == t) {
+        wa = w[0][t];
+        dwa = dw[0][t];
+      }
 #pragma unroll UB
     for (int b = 0; b < P; ++b) {
       int kb = base[1] - b;
@@ -991,14 +1015,14 @@ __global__ __launch_bounds__(256) void gather_backward(
           ss2 += dw[2][c] * y;
         }
       }
-      const T wab = w[0][a] * w[1][b];
+      const T wab = wa * w[1][b];
       vf[0] += wab * sf;
-      vf[1] += dw[0][a] * w[1][b] * sf;
-      vf[2] += w[0][a] * dw[1][b] * sf;
+      vf[1] += dwa * w[1][b] * sf;
+      vf[2] += wa * dw[1][b] * sf;
       vf[3] += wab * sf2;
       vs[0] += wab * ss;
-      vs[1] += dw[0][a] * w[1][b] * ss;
-      vs[2] += w[0][a] * dw[1][b] * ss;
+      vs[1] += dwa * w[1][b] * ss;
+      vs[2] += wa * dw[1][b] * ss;
       vs[3] += wab * ss2;
     }
   }
