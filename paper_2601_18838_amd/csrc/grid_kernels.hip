@@ -111,40 +111,6 @@ __device__ void charge_partials(double s1, double s2, double* qpart) {
 }
 
 template <typename T, int P>
-__global__ __launch_bounds__(256) void spread_atomic(long n, const T* __restrict__ pos,
-                                                     const T* __restrict__ q,
-                                                     T* __restrict__ grid, GridGeom g) {
-  const long i = blockIdx.x * static_cast<long>(blockDim.x) + threadIdx.x;
-  if (i >= n) return;
-  T w[3][P], dw[P];
-  int base[3];
-#pragma unroll
-  for (int j = 0; j < 3; ++j) {
-    const T f = scaled(pos[3 * i + j], g.L[j], g.K[j], base[j]);
-    bspline<T, P>(f, w[j], dw);
-  }
-  const T qi = q[i];
-  const int K1 = g.K[0], K2 = g.K[1], K3 = g.K[2];
-  for (int a = 0; a < P; ++a) {
-    int ka = base[0] - a;
-    if (ka < 0) ka += K1;
-    const T wa = qi * w[0][a];
-    for (int b = 0; b < P; ++b) {
-      int kb = base[1] - b;
-      if (kb < 0) kb += K2;
-      const T wab = wa * w[1][b];
-      T* row = grid + (static_cast<long>(ka) * K2 + kb) * K3;
-#pragma unroll
-      for (int c = 0; c < P; ++c) {
-        int kc = base[2] - c;
-        if (kc < 0) kc += K3;
-        atomicAdd(&row[kc], wab * w[2][c]);
-      }
-    }
-  }
-}
-
-template <typename T, int P>
 __global__ __launch_bounds__(256) void gather_direct(long n, const T* __restrict__ pos,
                                                      const T* __restrict__ q,
                                                      const T* __restrict__ grid,
@@ -1096,16 +1062,6 @@ __global__ __launch_bounds__(256) void energy_final(const double* __restrict__ p
 }
 
 template <typename T, int P>
-hipError_t spread_p(const GridGeom& g, int64_t n, const void* pos, const void* q, void* grid,
-                    hipStream_t st) {
-  const unsigned blocks = static_cast<unsigned>((n + 255) / 256);
-  hipLaunchKernelGGL((spread_atomic<T, P>), dim3(blocks), dim3(256), 0, st,
-                     static_cast<long>(n), static_cast<const T*>(pos),
-                     static_cast<const T*>(q), static_cast<T*>(grid), g);
-  return hipGetLastError();
-}
-
-template <typename T, int P>
 hipError_t gather_p(const GridGeom& g, int64_t n, const void* pos, const void* q,
                     const void* grid, void* pot, void* force, hipStream_t st) {
   const unsigned blocks = static_cast<unsigned>((n + 255) / 256);
@@ -1135,19 +1091,6 @@ hipError_t launch_zero(void* p, size_t bytes, hipStream_t st) {
   hipLaunchKernelGGL((zero_kernel<float>), dim3(blocks), dim3(256), 0, st,
                      static_cast<float*>(p), n);
   return hipGetLastError();
-}
-
-hipError_t launch_spread_atomic(int prec, const GridGeom& g, int64_t n, const void* pos,
-                                const void* q, void* grid, hipStream_t st) {
-  if (n == 0) return hipSuccess;
-  if (prec == PREC_FP64) {
-#define CALL(P) spread_p<double, P>(g, n, pos, q, grid, st)
-    KPME_ORDER_SWITCH(g.p, CALL)
-#undef CALL
-  }
-#define CALL(P) spread_p<float, P>(g, n, pos, q, grid, st)
-  KPME_ORDER_SWITCH(g.p, CALL)
-#undef CALL
 }
 
 hipError_t launch_gather_direct(int prec, const GridGeom& g, int64_t n, const void* pos,

@@ -111,8 +111,6 @@ struct Bins {
 
 // All launches are asynchronous on `st`; they return the launch status.
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t st);
-hipError_t launch_spread_atomic(int prec, const GridGeom& g, int64_t n, const void* pos,
-                                const void* q, void* grid, hipStream_t st);
 hipError_t launch_gather_direct(int prec, const GridGeom& g, int64_t n, const void* pos,
                                 const void* q, const void* grid, void* pot, void* force,
                                 hipStream_t st);
