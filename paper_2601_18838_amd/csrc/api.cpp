@@ -599,7 +599,7 @@ kpme_status kpme_plan_create(kpme_plan_t* plan, const double box[3], const int g
       for (int sh = 0; sh < 8; ++sh)
         for (int x = 0; x < pl->blen; ++x) {
           const int idx = ((K2P - x - sh) % K2 + K2) % K2;
-          put(base + static_cast<size_t>(sh) * pl->blen + (sh ? kX3ShiftB : 0) + x, sB * cb[idx]);
+          put(base + static_cast<size_t>(sh) * pl->blen + x3_shift_b(sh) + x, sB * cb[idx]);
         }
       const size_t abase = base + 8 * static_cast<size_t>(pl->blen) + 8;
       for (int sh = 0; sh < 4; ++sh)

@@ -421,12 +421,12 @@ __attribute__((amdgpu_waves_per_eu(RT >= 8 ? 1 : 2))) void stage2_x3(
   static_assert((2 * NKC) % CT == 0, "column tiles must divide K2P / 16");
   constexpr int K1P = RT * 16, K2P = NKC * 32;
   constexpr int WPS = 2 * NKC / CT;             // waves per stream
-  constexpr int blen = 2 * K2P + 8, alen = 2 * K1P + 16;  // x3_blen, x3_alen
+  constexpr int blen = 2 * K2P + 8 + (K2P % 64 == 0 ? 64 : 0), alen = 2 * K1P + 16;  // x3_blen, x3_alen
   constexpr int plane = 8 * blen + 8 + 4 * alen + 8;  // x3_plane: halves per plane
   constexpr int tsz = 2 * plane;                // halves per term (hi plane, lo plane)
   constexpr int STHR = 64 * WPS;                // threads per stream
   constexpr int PF = (tsz / 8 + STHR - 1) / STHR;  // 16-byte chunks per stream thread
-  constexpr int YSTR = K2P + 8;
+  constexpr int YSTR = K2P;                     // rows swizzled by x3_yswz
   extern __shared__ __attribute__((aligned(16))) char smem[];
   H* Ysh = reinterpret_cast<H*>(smem);
   H* Ysl = Ysh + K1P * YSTR;
@@ -455,10 +455,15 @@ __attribute__((amdgpu_waves_per_eu(RT >= 8 ? 1 : 2))) void stage2_x3(
   // uB = 8 q - col0 - m + K2P; the kc, j part is a multiple of 8, hence a
   // constant offset from offB.  Likewise the A half-fragment at K offset 16 d
   // (d = 2 c - i, then 2 c - i + 1) starts at uA + 16 d, uA = 4 q - m + K1P,
-  // in copy (uA & 3).  Copies s >= 1 start kX3ShiftB / kX3ShiftA halves late.
+  // in copy (uA & 3).  Copy s starts x3_shift_b(s) (B) or kX3ShiftA (A, s >= 1)
+  // halves late.  The Y fragment of row m + 16 i and K chunk (kc, q) is chunk
+  // (4 kc + q) ^ x3_yswz(NKC, m) of its row (the swizzle of rows m + 16 i is
+  // that of row m).
   const int uB = 8 * q - col0 - m + K2P, uA = 4 * q - m + K1P;
   const int sB = uB & 7, sA = uA & 3;
-  const int offB = sB * blen + (sB ? kX3ShiftB : 0) + (uB & ~7) - 16;
+  const int offB = sB * blen + x3_shift_b(sB) + (uB & ~7) - 16;
+  const int ysw = x3_yswz(NKC, m);
+  auto ycol = [&](int kc) { return 8 * ((4 * kc + q) ^ ysw); };
   const int offA = 8 * blen + 8 + sA * alen + (sA ? kX3ShiftA : 0) + (uA & ~3) - 16 * (RT - 1);
   // prologue: this stream's first term's vectors into its buffer 0
   if (s0 < s1) {
@@ -481,9 +486,9 @@ __attribute__((amdgpu_waves_per_eu(RT >= 8 ? 1 : 2))) void stage2_x3(
       constexpr int cpr = K2P / 8;
       for (int e = tid; e < K1P * cpr; e += nthr) {
         const int r = e / cpr, c8 = e % cpr;
-        *reinterpret_cast<v8*>(&Ysh[r * YSTR + 8 * c8]) =
+        *reinterpret_cast<v8*>(&Ysh[r * YSTR + 8 * (c8 ^ x3_yswz(NKC, r))]) =
             *reinterpret_cast<const v8*>(&yh[static_cast<long>(r) * K2P + 8 * c8]);
-        *reinterpret_cast<v8*>(&Ysl[r * YSTR + 8 * c8]) =
+        *reinterpret_cast<v8*>(&Ysl[r * YSTR + 8 * (c8 ^ x3_yswz(NKC, r))]) =
             *reinterpret_cast<const v8*>(&yl[static_cast<long>(r) * K2P + 8 * c8]);
       }
       cur = g;
@@ -518,8 +523,8 @@ __attribute__((amdgpu_waves_per_eu(RT >= 8 ? 1 : 2))) void stage2_x3(
       bh[j] = *reinterpret_cast<const v8*>(&Bvh[16 * (1 - j)]);
       bl[j] = *reinterpret_cast<const v8*>(&Bvl[16 * (1 - j)]);
     }
-    v8 ah = *reinterpret_cast<const v8*>(&Ysh[m * YSTR + 8 * q]);
-    v8 al = *reinterpret_cast<const v8*>(&Ysl[m * YSTR + 8 * q]);
+    v8 ah = *reinterpret_cast<const v8*>(&Ysh[m * YSTR + ycol(0)]);
+    v8 al = *reinterpret_cast<const v8*>(&Ysl[m * YSTR + ycol(0)]);
 #pragma unroll
     for (int kc = 0; kc < NKC; ++kc) {
 #pragma unroll
@@ -527,11 +532,11 @@ __attribute__((amdgpu_waves_per_eu(RT >= 8 ? 1 : 2))) void stage2_x3(
         v8 nh = ah, nl = al, nbh[CT], nbl[CT];
         const bool next_kc = (i + 1 == RT) && (kc + 1 < NKC);
         if (i + 1 < RT) {
-          const int yo = (m + 16 * (i + 1)) * YSTR + 32 * kc + 8 * q;
+          const int yo = (m + 16 * (i + 1)) * YSTR + ycol(kc);
           nh = *reinterpret_cast<const v8*>(&Ysh[yo]);
           nl = *reinterpret_cast<const v8*>(&Ysl[yo]);
         } else if (next_kc) {
-          const int yo = m * YSTR + 32 * (kc + 1) + 8 * q;
+          const int yo = m * YSTR + ycol(kc + 1);
           nh = *reinterpret_cast<const v8*>(&Ysh[yo]);
           nl = *reinterpret_cast<const v8*>(&Ysl[yo]);
 #pragma unroll
@@ -897,7 +902,7 @@ hipError_t launch_s2_x3(const SkpArgs& a, hipStream_t st) {
   constexpr int K1P = RT * 16, K2P = NKC * 32;
   constexpr int CT = x3_ct(K1P, K2P), NS = x3_streams(K1P, K2P);
   const size_t tsz = 2 * static_cast<size_t>(x3_plane(K1P, K2P));
-  const size_t lds = sizeof(H) * (2 * static_cast<size_t>(K1P) * (K2P + 8) + 2 * NS * tsz);
+  const size_t lds = sizeof(H) * (2 * static_cast<size_t>(K1P) * K2P + 2 * NS * tsz);
   hipError_t e = set_lds(stage2_x3<H, RT, NKC, CT, NS>, lds);
   if (e != hipSuccess) return e;
   const int threads = 64 * (K2P / (16 * CT)) * NS;
@@ -957,7 +962,7 @@ size_t stage2_lds_bytes(int prec, int K1P, int K2P) {
   if (prec == PREC_BF16X3 || prec == PREC_FP16X3) {
     // Y slab (two planes) + two buffers of circulant vectors per stream
     const size_t tsz = 2 * static_cast<size_t>(x3_plane(K1P, K2P));
-    return 2 * (2 * static_cast<size_t>(K1P) * (K2P + 8) + 2 * x3_streams(K1P, K2P) * tsz);
+    return 2 * (2 * static_cast<size_t>(K1P) * K2P + 2 * x3_streams(K1P, K2P) * tsz);
   }
   if (prec == PREC_FP32) return sizeof(float) * static_cast<size_t>(K1P) * (K2P + 1);
   return sizeof(double) * static_cast<size_t>(K1P) * (K2P + 1);
