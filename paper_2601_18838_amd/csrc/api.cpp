@@ -135,7 +135,7 @@ struct kpme_plan_s {
   size_t esize() const { return prec == PREC_FP64 ? 8 : 4; }
   GridGeom geom() const {
     GridGeom g;
-    for (int j = 0; j < 3; ++j) { g.K[j] = K[j]; g.L[j] = box[j]; }
+    for (int j = 0; j < 3; ++j) { g.K[j] = K[j]; g.L[j] = box[j]; g.invL[j] = 1.0 / box[j]; }
     g.p = p;
     return g;
   }

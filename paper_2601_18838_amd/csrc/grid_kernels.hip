@@ -35,11 +35,12 @@ __device__ __forceinline__ void bspline(T f, T* w, T* dw) {
   }
 }
 
-// Scaled coordinate of one axis, computed in double: u = K (x / L mod 1);
-// returns the fractional part and sets the base grid index floor(u) mod K.
+// Scaled coordinate of one axis, computed in double: u = K (x / L mod 1),
+// with x / L taken as x times the host-computed 1 / L; returns the fractional
+// part and sets the base grid index floor(u) mod K.
 template <typename T>
-__device__ __forceinline__ T scaled(T x, double L, int K, int& base) {
-  double s = static_cast<double>(x) / L;
+__device__ __forceinline__ T scaled(T x, double invL, int K, int& base) {
+  double s = static_cast<double>(x) * invL;
   s -= floor(s);
   const double u = s * K;
   const double fl = floor(u);
@@ -122,7 +123,7 @@ __global__ __launch_bounds__(256) void gather_direct(long n, const T* __restrict
   int base[3];
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
-    const T f = scaled(pos[3 * i + j], g.L[j], g.K[j], base[j]);
+    const T f = scaled(pos[3 * i + j], g.invL[j], g.K[j], base[j]);
     bspline<T, P>(f, w[j], dw[j]);
   }
   const int K1 = g.K[0], K2 = g.K[1], K3 = g.K[2];
@@ -160,9 +161,9 @@ __global__ __launch_bounds__(256) void gather_direct(long n, const T* __restrict
   if (pot) pot[i] = phi;
   if (force) {
     const T qi = q[i];
-    force[3 * i + 0] = -qi * g0 * static_cast<T>(K1 / g.L[0]);
-    force[3 * i + 1] = -qi * g1 * static_cast<T>(K2 / g.L[1]);
-    force[3 * i + 2] = -qi * g2 * static_cast<T>(K3 / g.L[2]);
+    force[3 * i + 0] = -qi * g0 * static_cast<T>(K1 * g.invL[0]);
+    force[3 * i + 1] = -qi * g1 * static_cast<T>(K2 * g.invL[1]);
+    force[3 * i + 2] = -qi * g2 * static_cast<T>(K3 * g.invL[2]);
   }
 }
 
@@ -177,7 +178,7 @@ __device__ __forceinline__ int brick_of_particle(const T* __restrict__ pos, long
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
     int base;
-    (void)scaled(pos[3 * i + j], g.L[j], g.K[j], base);
+    (void)scaled(pos[3 * i + j], g.invL[j], g.K[j], base);
     bid = bid * bg.nb[j] + base / bg.edge[j];
   }
   return bid;
@@ -386,14 +387,24 @@ __global__ __launch_bounds__(256) void bin_scatter(long n, const T* __restrict__
 // Owner-computes spread: one workgroup per grid brick.  It visits the
 // particles binned in the home bricks whose stencils reach it (per-axis
 // lists nbr[axis][brick] = {count, b0, b1, ...}, at most 4^3 combinations,
-// flattened into one index range so that every thread stays busy), adds the
-// stencil points that fall inside its brick into an LDS tile with LDS
-// atomics, and stores the tile: every grid value is written exactly once,
-// with no global atomics.  It also writes the tile's FP64 sum and largest
-// magnitude (part2[brick] = {sum, max}) for the correction and the FP16X3
-// grid scale.  The tile accumulates in FP64 for every precision (the LDS FP64
-// add is also the faster one on gfx950).
-template <typename T, int P>
+// flattened into one candidate range), adds the stencil points that fall
+// inside its brick into an LDS tile with LDS atomics, and stores the tile:
+// every grid value is written exactly once, with no global atomics.  It also
+// writes the tile's FP64 sum and largest magnitude (part2[brick] = {sum, max})
+// for the correction and the FP16X3 grid scale.  The tile accumulates in FP64
+// for every precision (the LDS FP64 add is also the faster one on gfx950).
+//
+// Most candidates from neighbouring home bricks do not reach the brick (for
+// 8-point bricks and P = 4, about a third of them do), and a wave pays for
+// the stencil loop of its busiest lane, so a first pass compacts the
+// candidates that reach the brick into an LDS list: wave w examines the
+// 64-candidate runs w, w + 4, ... of the pass and appends the hits in order to
+// its own segment (ballot prefix, deterministic).  The stencil pass then runs
+// over the concatenated segments.  E8: every brick edge is 8 (compile-time tile
+// strides).
+constexpr int kSpreadCand = 1024;  // candidates examined per pass, 256 per wave
+
+template <typename T, int P, bool E8>
 __global__ __launch_bounds__(256) void spread_brick(const T* __restrict__ sorted,
                                                     const int* __restrict__ offset,
                                                     const int* __restrict__ nbr,
@@ -401,11 +412,14 @@ __global__ __launch_bounds__(256) void spread_brick(const T* __restrict__ sorted
                                                     double* __restrict__ part2,
                                                     int* __restrict__ count, GridGeom g,
                                                     BinGeom bg) {
+  static_assert(P <= 4, "owner-computes spread is for spline orders up to 4");
   extern __shared__ __attribute__((aligned(16))) char smem[];
   double* tile = reinterpret_cast<double*>(smem);
   __shared__ int hstart[64], hpre[65];
+  __shared__ int list[kSpreadCand], wcnt[4];
   __shared__ double red[32];
-  const int E0 = bg.edge[0], E1 = bg.edge[1], E2 = bg.edge[2];
+  const int E0 = E8 ? 8 : bg.edge[0], E1 = E8 ? 8 : bg.edge[1], E2 = E8 ? 8 : bg.edge[2];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   // neighbouring bricks (which read overlapping particle lists) share an XCD
   const int brick = xcd_order(blockIdx.x, gridDim.x);
   if (threadIdx.x == 0) count[brick] = 0;  // the scatter has read it: ready for the next binning
@@ -414,11 +428,11 @@ __global__ __launch_bounds__(256) void spread_brick(const T* __restrict__ sorted
   own[1] = rest % bg.nb[1];
   own[0] = rest / bg.nb[1];
   int lo[3], ext[3];
+  lo[0] = own[0] * E0;
+  lo[1] = own[1] * E1;
+  lo[2] = own[2] * E2;
 #pragma unroll
-  for (int j = 0; j < 3; ++j) {
-    lo[j] = own[j] * bg.edge[j];
-    ext[j] = min(bg.edge[j], g.K[j] - lo[j]);
-  }
+  for (int j = 0; j < 3; ++j) ext[j] = min(j == 0 ? E0 : j == 1 ? E1 : E2, g.K[j] - lo[j]);
   const int ntile = E0 * E1 * E2;
   for (int e = threadIdx.x; e < ntile; e += blockDim.x) tile[e] = 0.0;
   const int* n0 = nbr + kNbrRec * (0 * bg.nbmax + own[0]);
@@ -450,40 +464,82 @@ __global__ __launch_bounds__(256) void spread_brick(const T* __restrict__ sorted
   }
   __syncthreads();
   const int total = hpre[nh];
-  for (int v = threadIdx.x; v < total; v += blockDim.x) {
-    int c = 0;
-    while (hpre[c + 1] <= v) ++c;
-    const long i = hstart[c] + (v - hpre[c]);
-    T w[3][P], dw[P];
-    int d[3][P];
+  for (int c0 = 0; c0 < total; c0 += kSpreadCand) {
+    // pass 1: compact the candidates whose stencil reaches this brick
+    int nw = 0;
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      int base;
-      const T f = scaled(sorted[4 * i + j], g.L[j], g.K[j], base);
-      bspline<T, P>(f, w[j], dw);
+    for (int k = 0; k < kSpreadCand / 256; ++k) {
+      const int v = c0 + 64 * (4 * k + wave) + lane;
+      bool hit = false;
+      int i = 0;
+      if (v < total) {
+        int c = 0;
+        while (hpre[c + 1] <= v) ++c;
+        i = hstart[c] + (v - hpre[c]);
+        hit = true;
 #pragma unroll
-      for (int t = 0; t < P; ++t) {
-        int k = base - t;
-        if (k < 0) k += g.K[j];
-        const int dd = k - lo[j];
-        d[j][t] = (dd >= 0 && dd < ext[j]) ? dd : -1;
+        for (int j = 0; j < 3; ++j) {
+          int base;
+          (void)scaled(sorted[4L * i + j], g.invL[j], g.K[j], base);
+          bool any = false;
+#pragma unroll
+          for (int t = 0; t < P; ++t) {
+            int kk = base - t;
+            if (kk < 0) kk += g.K[j];
+            const int dd = kk - lo[j];
+            any = any || (dd >= 0 && dd < ext[j]);
+          }
+          hit = hit && any;
+        }
+      }
+      const unsigned long long m = __ballot(hit);
+      const int below = __builtin_amdgcn_mbcnt_hi(static_cast<unsigned>(m >> 32),
+                                                  __builtin_amdgcn_mbcnt_lo(static_cast<unsigned>(m), 0));
+      if (hit) list[(kSpreadCand / 4) * wave + nw + below] = i;
+      nw += __popcll(m);
+    }
+    if (lane == 0) wcnt[wave] = nw;
+    __syncthreads();
+    // pass 2: the stencils of the listed particles, segments in wave order
+    const int s1 = wcnt[0], s2 = s1 + wcnt[1], s3 = s2 + wcnt[2], nl = s3 + wcnt[3];
+    for (int u = threadIdx.x; u < nl; u += blockDim.x) {
+      const int w = (u >= s1) + (u >= s2) + (u >= s3);
+      const int segbase = w == 0 ? 0 : w == 1 ? s1 : w == 2 ? s2 : s3;
+      const long i = list[(kSpreadCand / 4) * w + u - segbase];
+      T w3[3][P], dw[P];
+      int d[3][P];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        int base;
+        const T f = scaled(sorted[4 * i + j], g.invL[j], g.K[j], base);
+        bspline<T, P>(f, w3[j], dw);
+#pragma unroll
+        for (int t = 0; t < P; ++t) {
+          int k = base - t;
+          if (k < 0) k += g.K[j];
+          const int dd = k - lo[j];
+          d[j][t] = (dd >= 0 && dd < ext[j]) ? dd : -1;
+        }
+      }
+      const double qi = static_cast<double>(sorted[4 * i + 3]);
+      double wz[P];
+#pragma unroll
+      for (int cc = 0; cc < P; ++cc) wz[cc] = static_cast<double>(w3[2][cc]);
+      for (int a = 0; a < P; ++a) {
+        if (d[0][a] < 0) continue;
+        const double wa = qi * static_cast<double>(w3[0][a]);
+        for (int b = 0; b < P; ++b) {
+          if (d[1][b] < 0) continue;
+          const double wab = wa * static_cast<double>(w3[1][b]);
+          double* row = tile + (d[0][a] * E1 + d[1][b]) * E2;
+#pragma unroll
+          for (int cc = 0; cc < P; ++cc)
+            if (d[2][cc] >= 0) atomicAdd(&row[d[2][cc]], wab * wz[cc]);
+        }
       }
     }
-    const T qi = sorted[4 * i + 3];
-    for (int a = 0; a < P; ++a) {
-      if (d[0][a] < 0) continue;
-      const T wa = qi * w[0][a];
-      for (int b = 0; b < P; ++b) {
-        if (d[1][b] < 0) continue;
-        const T wab = wa * w[1][b];
-        double* row = tile + (d[0][a] * E1 + d[1][b]) * E2;
-#pragma unroll
-        for (int cc = 0; cc < P; ++cc)
-          if (d[2][cc] >= 0) atomicAdd(&row[d[2][cc]], static_cast<double>(wab * w[2][cc]));
-      }
-    }
+    __syncthreads();  // the list is rewritten by the next pass; the tile is read below
   }
-  __syncthreads();
   double s = 0.0, m = 0.0;
   for (int e = threadIdx.x; e < ntile; e += blockDim.x) {
     const int c = e % E2, b = (e / E2) % E1, a = e / (E1 * E2);
@@ -538,7 +594,7 @@ __global__ __launch_bounds__(64) void spread_home(const T* __restrict__ sorted,
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
       int base;
-      const T f = scaled(sorted[4L * i + j], g.L[j], g.K[j], base);
+      const T f = scaled(sorted[4L * i + j], g.invL[j], g.K[j], base);
       bspline<T, P>(f, w[j], dw);
       // the particle was binned by the same floor, so base lies in this
       // brick; the clamp only keeps a corrupted input inside the tile
@@ -661,7 +717,7 @@ __global__ __launch_bounds__(256) void gather_sorted(long n, const T* __restrict
     int base[3];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      const T f = scaled(sorted[4 * s + j], g.L[j], g.K[j], base[j]);
+      const T f = scaled(sorted[4 * s + j], g.invL[j], g.K[j], base[j]);
       bspline<T, P>(f, w[j], dw[j]);
     }
     const int K1 = g.K[0], K2 = g.K[1], K3 = g.K[2];
@@ -713,9 +769,9 @@ __global__ __launch_bounds__(256) void gather_sorted(long n, const T* __restrict
     const T qi = sorted[4 * s + 3];
     if (pot) pot[i] = phi;
     if (force) {
-      force[3 * i + 0] = -qi * g0 * static_cast<T>(K1 / g.L[0]);
-      force[3 * i + 1] = -qi * g1 * static_cast<T>(K2 / g.L[1]);
-      force[3 * i + 2] = -qi * g2 * static_cast<T>(K3 / g.L[2]);
+      force[3 * i + 0] = -qi * g0 * static_cast<T>(K1 * g.invL[0]);
+      force[3 * i + 1] = -qi * g1 * static_cast<T>(K2 * g.invL[1]);
+      force[3 * i + 2] = -qi * g2 * static_cast<T>(K3 * g.invL[2]);
     }
   }
 }
@@ -745,7 +801,7 @@ __global__ __launch_bounds__(256) void gather_sorted_planes(long n, const T* __r
     int base[3];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      const T f = scaled(sorted[4 * s + j], g.L[j], g.K[j], base[j]);
+      const T f = scaled(sorted[4 * s + j], g.invL[j], g.K[j], base[j]);
       bspline<T, P>(f, w[j], dw[j]);
     }
     qi = sorted[4 * s + 3];
@@ -800,9 +856,9 @@ __global__ __launch_bounds__(256) void gather_sorted_planes(long n, const T* __r
     const long i = perm[s];
     if (pot) pot[i] = phi;
     if (force) {
-      force[3 * i + 0] = -qi * g0 * static_cast<T>(g.K[0] / g.L[0]);
-      force[3 * i + 1] = -qi * g1 * static_cast<T>(g.K[1] / g.L[1]);
-      force[3 * i + 2] = -qi * g2 * static_cast<T>(g.K[2] / g.L[2]);
+      force[3 * i + 0] = -qi * g0 * static_cast<T>(g.K[0] * g.invL[0]);
+      force[3 * i + 1] = -qi * g1 * static_cast<T>(g.K[1] * g.invL[1]);
+      force[3 * i + 2] = -qi * g2 * static_cast<T>(g.K[2] * g.invL[2]);
     }
   }
 }
@@ -857,7 +913,7 @@ __global__ __launch_bounds__(256) void gather_brick(const T* __restrict__ sorted
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
       int base;
-      const T f = scaled(sorted[4L * s + j], g.L[j], g.K[j], base);
+      const T f = scaled(sorted[4L * s + j], g.invL[j], g.K[j], base);
       bspline<T, P>(f, w[j], dw[j]);
       // binned by the same floor: base lies in this brick (the clamp only
       // keeps a corrupted input inside the tile)
@@ -900,9 +956,9 @@ __global__ __launch_bounds__(256) void gather_brick(const T* __restrict__ sorted
     const T qi = sorted[4L * s + 3];
     if (pot) pot[i] = phi;
     if (force) {
-      force[3 * i + 0] = -qi * g0 * static_cast<T>(K1 / g.L[0]);
-      force[3 * i + 1] = -qi * g1 * static_cast<T>(K2 / g.L[1]);
-      force[3 * i + 2] = -qi * g2 * static_cast<T>(K3 / g.L[2]);
+      force[3 * i + 0] = -qi * g0 * static_cast<T>(K1 * g.invL[0]);
+      force[3 * i + 1] = -qi * g1 * static_cast<T>(K2 * g.invL[1]);
+      force[3 * i + 2] = -qi * g2 * static_cast<T>(K3 * g.invL[2]);
     }
   }
 }
@@ -938,7 +994,7 @@ __global__ __launch_bounds__(256) void gather_backward(
   int base[3];
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
-    const T f = scaled(sorted[4 * s + j], g.L[j], g.K[j], base[j]);
+    const T f = scaled(sorted[4 * s + j], g.invL[j], g.K[j], base[j]);
     bspline<T, P>(f, w[j], dw[j]);
   }
   const int K1 = g.K[0], K2 = g.K[1], K3 = g.K[2];
@@ -1000,7 +1056,7 @@ __global__ __launch_bounds__(256) void gather_backward(
     const T cf = ge * qi + gp;
 #pragma unroll
     for (int j = 0; j < 3; ++j)
-      grad_pos[3 * i + j] = (cf * vf[1 + j] + qi * vs[1 + j]) * static_cast<T>(g.K[j] / g.L[j]);
+      grad_pos[3 * i + j] = (cf * vf[1 + j] + qi * vs[1 + j]) * static_cast<T>(g.K[j] * g.invL[j]);
   }
   if (grad_q) {
     const double pi = 3.141592653589793238462643383279502884;
@@ -1169,10 +1225,15 @@ template <typename T, int P>
 hipError_t spread_brick_p(const GridGeom& g, const Bins& b, const void* src, void* grid,
                           double* part2, hipStream_t st) {
   const T* srt = static_cast<const T*>(src ? src : b.sorted);
-  if (P <= 4) {
+  if constexpr (P <= 4) {
     const size_t lds = sizeof(double) * b.geom.edge[0] * b.geom.edge[1] * b.geom.edge[2];
-    hipLaunchKernelGGL((spread_brick<T, P>), dim3(b.geom.nbricks), dim3(256), lds, st, srt,
-                       b.offset, b.nbr, static_cast<T*>(grid), part2, b.count, g, b.geom);
+    const bool e8 = b.geom.edge[0] == 8 && b.geom.edge[1] == 8 && b.geom.edge[2] == 8;
+    if (e8)
+      hipLaunchKernelGGL((spread_brick<T, P, true>), dim3(b.geom.nbricks), dim3(256), lds, st,
+                         srt, b.offset, b.nbr, static_cast<T*>(grid), part2, b.count, g, b.geom);
+    else
+      hipLaunchKernelGGL((spread_brick<T, P, false>), dim3(b.geom.nbricks), dim3(256), lds, st,
+                         srt, b.offset, b.nbr, static_cast<T*>(grid), part2, b.count, g, b.geom);
     return hipGetLastError();
   }
   const int ntile = (b.geom.edge[0] + P - 1) * (b.geom.edge[1] + P - 1) * (b.geom.edge[2] + P - 1);

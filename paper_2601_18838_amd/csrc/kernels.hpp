@@ -99,6 +99,7 @@ size_t stage2_lds_bytes(int prec, int K1P, int K2P);
 struct GridGeom {
   int K[3];
   double L[3];
+  double invL[3];  // 1 / L
   int p;
 };
 
