@@ -1042,8 +1042,8 @@ kpme_status kpme_evaluate(kpme_plan_t plan, int64_t n, const void* pos, const vo
   hipStream_t st = static_cast<hipStream_t>(stream);
   if ((s = do_spread(plan, n, pos, q, plan->Qg, st)) != KPME_SUCCESS) return s;
   // energies from the grid: finalize leaves the sums of Q * Phi, the scatter
-  // those of q and q^2; the gather's first workgroup (or, without a gather, a
-  // one-workgroup kernel) combines them
+  // those of q and q^2; one extra workgroup of the gather (or, without a
+  // gather, a one-workgroup kernel) combines them
   if ((s = do_skp(plan, plan->Qg, plan->Phig, st, true, nullptr, nullptr,
                   energy4 ? plan->epart : nullptr)) != KPME_SUCCESS)
     return s;

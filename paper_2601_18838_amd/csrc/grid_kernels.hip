@@ -699,8 +699,7 @@ __global__ __launch_bounds__(512) void spread_combine(const T* __restrict__ tile
 
 // Gather in binned order (neighbouring threads read neighbouring grid
 // values); results are written back to the caller's order through perm.
-// Each workgroup also writes its FP64 partial sums (q pot, q, q^2) to
-// (The first workgroup also runs the evaluation's energy job.)
+// With an energy job, one extra last workgroup runs it.
 template <typename T, int P>
 __global__ __launch_bounds__(256) void gather_sorted(long n, const T* __restrict__ sorted,
                                                      const int* __restrict__ perm,
@@ -708,9 +707,14 @@ __global__ __launch_bounds__(256) void gather_sorted(long n, const T* __restrict
                                                      T* __restrict__ pot,
                                                      T* __restrict__ force,
                                                      EnergyJob ej, GridGeom g) {
-  if (ej.e4 && blockIdx.x == 0) run_energy_job(ej);
+  // with an energy job, one extra last workgroup runs it beside the gather
+  const int nwork = gridDim.x - (ej.e4 ? 1 : 0);
+  if (static_cast<int>(blockIdx.x) == nwork) {
+    run_energy_job(ej);
+    return;
+  }
   // neighbouring particle blocks (neighbouring bricks) share an XCD's L2
-  const int blk = xcd_order(blockIdx.x, gridDim.x);
+  const int blk = xcd_order(blockIdx.x, nwork);
   const long s = blk * static_cast<long>(blockDim.x) + threadIdx.x;
   if (s < n) {
     T w[3][P], dw[3][P];
@@ -789,13 +793,20 @@ __global__ __launch_bounds__(256) void gather_sorted_planes(long n, const T* __r
                                                             T* __restrict__ force,
                                                             EnergyJob ej, GridGeom g) {
   static_assert(P == 4, "one lane per plane, four lanes per particle");
-  if (ej.e4 && blockIdx.x == 0) run_energy_job(ej);
-  const int blk = xcd_order(blockIdx.x, gridDim.x);
+  // with an energy job, one extra last workgroup runs it beside the gather
+  const int nwork = gridDim.x - (ej.e4 ? 1 : 0);
+  if (static_cast<int>(blockIdx.x) == nwork) {
+    run_energy_job(ej);
+    return;
+  }
+  const int blk = xcd_order(blockIdx.x, nwork);
   const long s = (blk * static_cast<long>(blockDim.x) + threadIdx.x) / P;
   const int a = threadIdx.x % P;
   T phi = 0, g0 = 0, g1 = 0, g2 = 0;
   const bool live = s < n;
   T qi = 0;
+  // the destination index is loaded first; its latency hides behind the stencil
+  const long dst = live && a == 0 ? perm[s] : 0;
   if (live) {
     T w[3][P], dw[3][P];
     int base[3];
@@ -853,7 +864,7 @@ __global__ __launch_bounds__(256) void gather_sorted_planes(long n, const T* __r
     g2 += __shfl_xor(g2, o, 64);
   }
   if (live && a == 0) {
-    const long i = perm[s];
+    const long i = dst;
     if (pot) pot[i] = phi;
     if (force) {
       force[3 * i + 0] = -qi * g0 * static_cast<T>(g.K[0] * g.invL[0]);
@@ -868,8 +879,8 @@ __global__ __launch_bounds__(256) void gather_sorted_planes(long n, const T* __r
 // and the P - 1 planes below it on each axis, H_j = edge_j + P - 1 points,
 // wrapped periodically -- then interpolates those particles from LDS (every
 // stencil point is inside the tile: no masking).  Results go back to the
-// caller's order through perm; each workgroup writes its FP64 partial sums
-// (The first workgroup also runs the evaluation's energy job.)
+// caller's order through perm.  With an energy job, one extra last
+// workgroup runs it.
 template <typename T, int P>
 __global__ __launch_bounds__(256) void gather_brick(const T* __restrict__ sorted,
                                                     const int* __restrict__ offset,
@@ -880,8 +891,13 @@ __global__ __launch_bounds__(256) void gather_brick(const T* __restrict__ sorted
                                                     BinGeom bg) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   T* tile = reinterpret_cast<T*>(smem);
-  if (ej.e4 && blockIdx.x == 0) run_energy_job(ej);
-  const int brick = xcd_order(blockIdx.x, gridDim.x);
+  // with an energy job, one extra last workgroup runs it beside the gather
+  const int nwork = gridDim.x - (ej.e4 ? 1 : 0);
+  if (static_cast<int>(blockIdx.x) == nwork) {
+    run_energy_job(ej);
+    return;
+  }
+  const int brick = xcd_order(blockIdx.x, nwork);
   int own[3], rest = brick;
   own[2] = rest % bg.nb[2]; rest /= bg.nb[2];
   own[1] = rest % bg.nb[1];
@@ -1255,18 +1271,19 @@ hipError_t gather_brick_p(const GridGeom& g, const Bins& b, int64_t n, const voi
                           void* pot, void* force, const EnergyJob& ej, hipStream_t st) {
   if (sizeof(T) == 4 && P > 4) {
     const int ntile = (b.geom.edge[0] + P - 1) * (b.geom.edge[1] + P - 1) * (b.geom.edge[2] + P - 1);
-    hipLaunchKernelGGL((gather_brick<T, P>), dim3(b.geom.nbricks), dim3(128), sizeof(T) * ntile,
+    hipLaunchKernelGGL((gather_brick<T, P>), dim3(b.geom.nbricks + (ej.e4 ? 1 : 0)), dim3(128),
+                       sizeof(T) * ntile,
                        st, static_cast<const T*>(b.sorted), b.offset, b.perm,
                        static_cast<const T*>(grid), static_cast<T*>(pot), static_cast<T*>(force),
                        ej, g, b.geom);
   } else if (P == 4) {
-    const unsigned blocks = static_cast<unsigned>((n + 63) / 64);
+    const unsigned blocks = static_cast<unsigned>((n + 63) / 64) + (ej.e4 ? 1 : 0);
     hipLaunchKernelGGL((gather_sorted_planes<T, 4>), dim3(blocks), dim3(256), 0, st,
                        static_cast<long>(n), static_cast<const T*>(b.sorted), b.perm,
                        static_cast<const T*>(grid), static_cast<T*>(pot), static_cast<T*>(force),
                        ej, g);
   } else {
-    const unsigned blocks = static_cast<unsigned>((n + 255) / 256);
+    const unsigned blocks = static_cast<unsigned>((n + 255) / 256) + (ej.e4 ? 1 : 0);
     hipLaunchKernelGGL((gather_sorted<T, P>), dim3(blocks), dim3(256), 0, st,
                        static_cast<long>(n), static_cast<const T*>(b.sorted), b.perm,
                        static_cast<const T*>(grid), static_cast<T*>(pot), static_cast<T*>(force),

@@ -157,7 +157,7 @@ int finalize_blocks(int K1, int K2, int K3);
 // binned (x, y, z, charge) records to spread (NULL: the plan's own bins).
 hipError_t launch_spread_binned(int prec, const GridGeom& g, const Bins& b, void* grid,
                                 double* part2, hipStream_t st, const void* src = nullptr);
-// ej.e4 != NULL: the gather's first workgroup also runs the energy job.
+// ej.e4 != NULL: one extra workgroup of the gather runs the energy job.
 hipError_t launch_gather_binned(int prec, const GridGeom& g, const Bins& b, int64_t n,
                                 const void* grid, void* pot, void* force, const EnergyJob& ej,
                                 hipStream_t st);

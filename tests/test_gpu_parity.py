@@ -185,10 +185,13 @@ def test_empty_and_capacity_edges(prec):
 @pytest.mark.parametrize("case", ["small_pm1", "ragged_noncubic"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16x3"])
 def test_energy_paths_agree(prec, case):
-    """E_rec comes from the grid (1/2 sum_k Q Phi, combined inside the gather);
+    """E_rec comes from the grid (1/2 sum_k Q Phi, combined beside the gather);
     an energy-only call combines the same partials in its own kernel, and the
     particle-side sum 1/2 sum_i q_i pot_i of the returned potentials must
-    agree (partition of unity): to rounding, 1e-12 (FP64) or 1e-6 relative."""
+    agree (partition of unity): to rounding, 1e-12 (FP64) or 1e-6 relative.
+    The two calls are separate evaluations: binning assigns the order of the
+    particles inside a brick with atomics, so the spread's FP64 sums may be
+    added in another order and the energies agree to rounding, not bitwise."""
     print(f"[parity] energy paths {case} {prec}", flush=True)
     box, grid, p, beta, rank, pos, q = make(case)
     kpme = kp()
@@ -197,9 +200,10 @@ def test_energy_paths_agree(prec, case):
     e_full, pot, _ = pl.evaluate(P, Qc)
     e_only, none_pot, none_f = pl.evaluate(P, Qc, potentials=False, forces=False)
     assert none_pot is None and none_f is None
-    assert np.array_equal(host(e_full), host(e_only))
-    e_part = 0.5 * float((host(Qc) * host(pot)).sum())
     tol = 1e-12 if prec == "fp64" else 1e-6
+    ef, eo = host(e_full), host(e_only)
+    assert np.all(np.abs(ef - eo) <= tol * np.abs(ef).max())
+    e_part = 0.5 * float((host(Qc) * host(pot)).sum())
     assert abs(host(e_full)[0] - e_part) <= tol * abs(e_part)
 
 
