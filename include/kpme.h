@@ -231,7 +231,9 @@ kpme_status kpme_batch_evaluate(kpme_batch_t batch, const int64_t* n,
  * pairs per stage between two reads; later stages go unrecorded).
  * kpme_plan_profile_read waits for the recorded events and returns, per
  * stage, the summed elapsed milliseconds and the number of recorded launches
- * (host arrays of KPME_NUM_STAGES), then starts a new accumulation.
+ * (host arrays of KPME_NUM_STAGES), then starts a new accumulation.  A stage
+ * that launches nothing in a call (the grid sum when the split stage 1
+ * reduces the spread's partials itself) records nothing.
  * Enabling creates the events (host-side, no device memory); disabling
  * synchronizes the device and destroys them. */
 #define KPME_NUM_STAGES 7

@@ -195,8 +195,10 @@ struct StageTimer {
   int stage;
   hipStream_t st;
   bool active;
-  StageTimer(kpme_plan_s* p, int s, hipStream_t stream) : pl(p), stage(s), st(stream) {
-    active = pl->prof_on && pl->prof_used[stage] < kProfCap;
+  // on = false: the region launches nothing and records no interval
+  StageTimer(kpme_plan_s* p, int s, hipStream_t stream, bool on = true)
+      : pl(p), stage(s), st(stream) {
+    active = on && pl->prof_on && pl->prof_used[stage] < kProfCap;
     if (active) (void)hipEventRecord(pl->prof_ev[stage][0][pl->prof_used[stage]], st);
   }
   ~StageTimer() {
@@ -862,7 +864,7 @@ kpme_status do_skp(kpme_plan_t plan, const void* in, void* out, hipStream_t st,
   a.sum_np = s1_reduces ? np : 0;
   hipError_t e = hipSuccess;
   {
-    StageTimer tm(plan, KPME_STAGE_GRID_SUM, st);
+    StageTimer tm(plan, KPME_STAGE_GRID_SUM, st, !(s1_reduces && sum_ready));
     if (s1_reduces)
       e = sum_ready ? hipSuccess : launch_sum_partials(a, st);
     else

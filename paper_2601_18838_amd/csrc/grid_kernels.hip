@@ -179,7 +179,8 @@ __device__ __forceinline__ int brick_of_particle(const T* __restrict__ pos, long
   for (int j = 0; j < 3; ++j) {
     int base;
     (void)scaled(pos[3 * i + j], g.invL[j], g.K[j], base);
-    bid = bid * bg.nb[j] + base / bg.edge[j];
+    // edges are 8 unless the axis is shorter (a uniform branch)
+    bid = bid * bg.nb[j] + (bg.edge[j] == 8 ? base >> 3 : base / bg.edge[j]);
   }
   return bid;
 }
