@@ -77,6 +77,12 @@ CASES = {
     # order-6 stencils on 6- to 9-point axes: a brick tile (brick + 5 planes)
     # is longer than the axis, so one grid point has several tile images
     "wide_stencil": ((6.0, 7.0, 9.0), (6, 7, 9), 6, 0.9, 40, 300, "pm1", 14),
+    # order 4 on 8-point bricks with 3000 candidates per owner brick: the
+    # owner spread compacts them in several passes of 1024
+    "dense_p4": ((16.0, 16.0, 16.0), (16, 16, 16), 4, 0.4, 8, 3000, "pm1", 15),
+    # order 4 with a 6-point axis: one brick spans it (edge 6) and stencils
+    # wrap inside that brick
+    "short_axis_p4": ((6.0, 20.0, 24.0), (6, 20, 24), 4, 0.5, 12, 800, "pm1", 16),
 }
 
 
