@@ -185,7 +185,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the reciprocal path is a single-device "
-              "library in this build; multi-GPU sharding is a design note, not a run.",
+              "library; multi-GPU sharding is a design note, not a run.",
               file=sys.stderr)
         sys.exit(2)
     import torch
