@@ -188,7 +188,8 @@ __device__ __forceinline__ int brick_of_particle(const T* __restrict__ pos, long
 // Histogram with a per-workgroup LDS copy (up to kLdsHist bricks): each
 // workgroup ranks its particles inside the bricks in LDS, then reserves one
 // range per brick with a single global atomic.  count[] must be zero on entry.
-constexpr int kBinPer = 4;        // particles per thread
+constexpr int kBinPer = 4;        // particles per thread of the scatter
+constexpr int kCountPer = 4;      // particles per thread of the LDS-histogram count
 constexpr int kLdsHist = 8192;    // bricks handled with an LDS histogram
 
 template <typename T>
@@ -201,10 +202,10 @@ __global__ __launch_bounds__(256) void bin_count_lds(long n, const T* __restrict
   const int nb = bg.nbricks;
   for (int b = threadIdx.x; b < nb; b += blockDim.x) hist[b] = 0;
   __syncthreads();
-  const long base = static_cast<long>(blockIdx.x) * blockDim.x * kBinPer;
-  int bid[kBinPer], loc[kBinPer];
+  const long base = static_cast<long>(blockIdx.x) * blockDim.x * kCountPer;
+  int bid[kCountPer], loc[kCountPer];
 #pragma unroll
-  for (int k = 0; k < kBinPer; ++k) {
+  for (int k = 0; k < kCountPer; ++k) {
     const long i = base + static_cast<long>(k) * blockDim.x + threadIdx.x;
     bid[k] = -1;
     if (i < n) {
@@ -234,7 +235,7 @@ __global__ __launch_bounds__(256) void bin_count_lds(long n, const T* __restrict
   }
   __syncthreads();
 #pragma unroll
-  for (int k = 0; k < kBinPer; ++k) {
+  for (int k = 0; k < kCountPer; ++k) {
     const long i = base + static_cast<long>(k) * blockDim.x + threadIdx.x;
     if (bid[k] >= 0) {
       brick_of[i] = bid[k];
@@ -1199,7 +1200,7 @@ template <typename T>
 hipError_t bin_t(const GridGeom& g, const Bins& b, int64_t n, const void* pos, hipStream_t st) {
   if (n > 0) {
     if (b.geom.nbricks <= kLdsHist) {
-      const long per = 256L * kBinPer;
+      const long per = 256L * kCountPer;
       const unsigned blocks = static_cast<unsigned>((n + per - 1) / per);
       hipLaunchKernelGGL((bin_count_lds<T>), dim3(blocks), dim3(256), 0, st,
                          static_cast<long>(n), static_cast<const T*>(pos), g, b.geom,
