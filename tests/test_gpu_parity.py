@@ -242,3 +242,26 @@ def test_water_100k_mixed_paths_against_fp64():
         assert rel_e < tol_e, prec
         assert relrms(pot, ref["phi"]) < tol_f, prec
         assert relrms(frc, ref["F"]) < tol_f, prec
+
+
+@pytest.mark.parametrize("prec,grid_sum", [("fp16x3", 0), ("fp64", 3)])
+def test_stage_profiler_records_launching_stages(prec, grid_sum):
+    """The native stage timers record one interval per call for every stage
+    that launches work: the grid sum records none where the split stage 1
+    reduces the spread's per-brick partials itself (FP16X3, 8 bricks) and one
+    per call otherwise (FP64 launches the sum); the energy is combined inside
+    the gather, so the energy stage records nothing either."""
+    print(f"[profile] stage timers {prec}", flush=True)
+    box, grid, p, beta, rank, pos, q = make("small_pm1")
+    pl = kp().Plan(box, grid, p, beta, rank=rank, precision=prec, max_particles=len(q))
+    P, Qc = dev(pos, prec), dev(q, prec)
+    pl.profile(True)
+    pl.profile_read()
+    for _ in range(3):
+        pl.evaluate(P, Qc)
+    st = pl.profile_read()
+    pl.profile(False)
+    assert st["grid_sum"][1] == grid_sum
+    assert st["energy"][1] == 0
+    for name in ("spread", "skp_stage1", "skp_stage2", "skp_finalize", "gather"):
+        assert st[name][1] == 3 and st[name][0] > 0, name
