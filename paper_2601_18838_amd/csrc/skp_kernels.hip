@@ -515,30 +515,33 @@ __attribute__((amdgpu_waves_per_eu(RT >= 8 ? 1 : 2))) void stage2_x3(
     for (int i = 0; i < RT; ++i)
 #pragma unroll
       for (int j = 0; j < CT; ++j) acc1[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    // (kc, i) steps; each loads the next step's Y fragment, and the last i of
-    // a kc also the next kc's B fragments
-    v8 bh[CT], bl[CT];
+    // (kc, i) steps s = RT kc + i; each loads the Y fragment of step s + 2,
+    // and the next-to-last i of a kc also the next kc's B fragments
+    constexpr int NSTEP = NKC * RT;
+    auto yfrag = [&](int st1, v8& h, v8& l) {
+      const int yo = (m + 16 * (st1 % RT)) * YSTR + ycol(st1 / RT);
+      h = *reinterpret_cast<const v8*>(&Ysh[yo]);
+      l = *reinterpret_cast<const v8*>(&Ysl[yo]);
+    };
+    v8 bh[CT], bl[CT], nbh[CT], nbl[CT];
 #pragma unroll
     for (int j = 0; j < CT; ++j) {
       bh[j] = *reinterpret_cast<const v8*>(&Bvh[16 * (1 - j)]);
       bl[j] = *reinterpret_cast<const v8*>(&Bvl[16 * (1 - j)]);
     }
-    v8 ah = *reinterpret_cast<const v8*>(&Ysh[m * YSTR + ycol(0)]);
-    v8 al = *reinterpret_cast<const v8*>(&Ysl[m * YSTR + ycol(0)]);
+    v8 ah, al, a1h, a1l;
+    yfrag(0, ah, al);
+    a1h = ah;
+    a1l = al;
+    if (NSTEP > 1) yfrag(1, a1h, a1l);
 #pragma unroll
     for (int kc = 0; kc < NKC; ++kc) {
 #pragma unroll
       for (int i = 0; i < RT; ++i) {
-        v8 nh = ah, nl = al, nbh[CT], nbl[CT];
-        const bool next_kc = (i + 1 == RT) && (kc + 1 < NKC);
-        if (i + 1 < RT) {
-          const int yo = (m + 16 * (i + 1)) * YSTR + ycol(kc);
-          nh = *reinterpret_cast<const v8*>(&Ysh[yo]);
-          nl = *reinterpret_cast<const v8*>(&Ysl[yo]);
-        } else if (next_kc) {
-          const int yo = m * YSTR + ycol(kc + 1);
-          nh = *reinterpret_cast<const v8*>(&Ysh[yo]);
-          nl = *reinterpret_cast<const v8*>(&Ysl[yo]);
+        const int st1 = kc * RT + i;
+        v8 a2h = a1h, a2l = a1l;
+        if (st1 + 2 < NSTEP) yfrag(st1 + 2, a2h, a2l);
+        if (i + 2 == RT && kc + 1 < NKC) {
 #pragma unroll
           for (int j = 0; j < CT; ++j) {
             nbh[j] = *reinterpret_cast<const v8*>(&Bvh[32 * (kc + 1) + 16 * (1 - j)]);
@@ -551,9 +554,11 @@ __attribute__((amdgpu_waves_per_eu(RT >= 8 ? 1 : 2))) void stage2_x3(
         for (int j = 0; j < CT; ++j) acc1[i][j] = mfma_h(ah, bl[j], acc1[i][j]);
 #pragma unroll
         for (int j = 0; j < CT; ++j) acc1[i][j] = mfma_h(al, bh[j], acc1[i][j]);
-        ah = nh;
-        al = nl;
-        if (next_kc) {
+        ah = a1h;
+        al = a1l;
+        a1h = a2h;
+        a1l = a2l;
+        if (i + 1 == RT && kc + 1 < NKC) {
 #pragma unroll
           for (int j = 0; j < CT; ++j) {
             bh[j] = nbh[j];
