@@ -404,6 +404,7 @@ __global__ __launch_bounds__(256) void bin_scatter(long n, const T* __restrict__
 // its own segment (ballot prefix, deterministic).  The stencil pass then runs
 // over the concatenated segments.  E8: every brick edge is 8 (compile-time tile
 // strides).
+constexpr int kHomeThreads = 256;  // threads per brick of the home-computes spread
 constexpr int kSpreadCand = 1024;  // candidates examined per pass, 256 per wave
 
 template <typename T, int P, bool E8>
@@ -560,7 +561,8 @@ __global__ __launch_bounds__(256) void spread_brick(const T* __restrict__ sorted
   }
 }
 
-// Home-computes spread, pass 1: one wave per grid brick adds the stencils of
+// Home-computes spread, pass 1: one workgroup (kHomeThreads threads, one
+// particle per thread at a time) per grid brick adds the stencils of
 // the particles binned in that brick into an LDS tile covering the brick and
 // the P - 1 planes below it on each axis, H_j = edge_j + P - 1 points, where
 // every stencil point of those particles falls (no masking, each particle
@@ -568,7 +570,7 @@ __global__ __launch_bounds__(256) void spread_brick(const T* __restrict__ sorted
 // to tiles[brick].  Local tile coordinate of grid point k_j:
 // k_j - lo_j + P - 1 (unwrapped).
 template <typename T, int P>
-__global__ __launch_bounds__(64) void spread_home(const T* __restrict__ sorted,
+__global__ __launch_bounds__(256) void spread_home(const T* __restrict__ sorted,
                                                   const int* __restrict__ offset,
                                                   T* __restrict__ tiles,
                                                   int* __restrict__ count, GridGeom g, BinGeom bg) {
@@ -1255,7 +1257,7 @@ hipError_t spread_brick_p(const GridGeom& g, const Bins& b, const void* src, voi
     return hipGetLastError();
   }
   const int ntile = (b.geom.edge[0] + P - 1) * (b.geom.edge[1] + P - 1) * (b.geom.edge[2] + P - 1);
-  hipLaunchKernelGGL((spread_home<T, P>), dim3(b.geom.nbricks), dim3(64),
+  hipLaunchKernelGGL((spread_home<T, P>), dim3(b.geom.nbricks), dim3(kHomeThreads),
                      sizeof(double) * ntile, st, srt, b.offset, static_cast<T*>(b.tiles), b.count,
                      g, b.geom);
   hipLaunchKernelGGL((spread_combine<T, P>), dim3(b.geom.nbricks), dim3(512), 0, st,
