@@ -405,6 +405,7 @@ __global__ __launch_bounds__(256) void bin_scatter(long n, const T* __restrict__
 // over the concatenated segments.  E8: every brick edge is 8 (compile-time tile
 // strides).
 constexpr int kHomeThreads = 256;  // threads per brick of the home-computes spread
+static_assert(kHomeThreads % 64 == 0 && kHomeThreads <= 256, "spread_home's launch bound");
 constexpr int kSpreadCand = 1024;  // candidates examined per pass, 256 per wave
 
 template <typename T, int P, bool E8>
