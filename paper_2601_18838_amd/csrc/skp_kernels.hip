@@ -780,30 +780,13 @@ __global__ __launch_bounds__(256) void finalize(const A* __restrict__ part, int 
   const long pstride = static_cast<long>(K3) * K1 * K2;
   const bool vec = sizeof(A) == 4 && (K2 & 3) == 0 && (K3 & 3) == 0 && k2b + 32 <= K2 &&
                    k3b + 32 <= K3;
-  // the parts are loaded kFinChunk at a time, all in flight together, and
-  // added in part order (the same sums as one load after another)
-  constexpr int kFinChunk = 8;
-  float4 qv = make_float4(0.f, 0.f, 0.f, 0.f);
   if (vec) {
     const int r = t >> 3, c4 = (t & 7) * 4;  // k3 row, k2 column group
     const long base = (static_cast<long>(k3b + r) * K1 + k1) * K2 + k2b + c4;
     float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-    for (int p0 = 0; p0 < nparts; p0 += kFinChunk) {
-      float4 w[kFinChunk];
-#pragma unroll
-      for (int u = 0; u < kFinChunk; ++u)
-        if (p0 + u < nparts)
-          w[u] = *reinterpret_cast<const float4*>(&part[(p0 + u) * pstride + base]);
-      if (p0 == 0 && epart) {
-        // the energy's Q values of this thread's output, in flight with the parts
-        const long at = (static_cast<long>(k1) * K2 + k2b + r) * K3 + k3b + c4;
-        qv = *reinterpret_cast<const float4*>(&Q[at]);
-      }
-#pragma unroll
-      for (int u = 0; u < kFinChunk; ++u)
-        if (p0 + u < nparts) {
-          v.x += w[u].x; v.y += w[u].y; v.z += w[u].z; v.w += w[u].w;
-        }
+    for (int p = 0; p < nparts; ++p) {
+      const float4 w = *reinterpret_cast<const float4*>(&part[p * pstride + base]);
+      v.x += w.x; v.y += w.y; v.z += w.z; v.w += w.w;
     }
     tile[r][c4] = v.x;
     tile[r][c4 + 1] = v.y;
@@ -815,15 +798,7 @@ __global__ __launch_bounds__(256) void finalize(const A* __restrict__ part, int 
       A v = 0;
       if (k3 < K3 && k2 < K2) {
         const long base = (static_cast<long>(k3) * K1 + k1) * K2 + k2;
-        for (int p0 = 0; p0 < nparts; p0 += kFinChunk) {
-          A w[kFinChunk];
-#pragma unroll
-          for (int u = 0; u < kFinChunk; ++u)
-            if (p0 + u < nparts) w[u] = part[(p0 + u) * pstride + base];
-#pragma unroll
-          for (int u = 0; u < kFinChunk; ++u)
-            if (p0 + u < nparts) v += w[u];
-        }
+        for (int p = 0; p < nparts; ++p) v += part[p * pstride + base];
       }
       tile[j][t & 31] = v;
     }
@@ -842,6 +817,7 @@ __global__ __launch_bounds__(256) void finalize(const A* __restrict__ part, int 
     const long at = (static_cast<long>(k1) * K2 + k2b + r) * K3 + k3b + c4;
     *reinterpret_cast<float4*>(&Phi[at]) = o;
     if (epart) {
+      const float4 qv = *reinterpret_cast<const float4*>(&Q[at]);
       e = static_cast<double>(qv.x) * o.x + static_cast<double>(qv.y) * o.y +
           static_cast<double>(qv.z) * o.z + static_cast<double>(qv.w) * o.w;
     }
