@@ -1,14 +1,16 @@
 """Benchmark of the reciprocal-space SKP-PME path on one MI355X.
 
-One step = one full reciprocal evaluation (spread -> Kronecker operator with
-correction -> gather of potentials and forces -> FP64 energies) of the
-1e5-atom water box (N = 99,999, 96^3 grid, p = 4, beta = 0.34, R from the
-1e-6 Frobenius rule), inputs resident in HBM, plan built beforehand.
+One step = one full reciprocal evaluation (bin + spread -> Kronecker operator
+with correction -> gather of potentials and forces -> FP64 energies), inputs
+resident in HBM, plan built beforehand (its creation time is reported
+separately).  Default workload: the 1e6-atom water box (N = 1,000,002,
+128^3 grid, p = 6, beta = 0.34, R from the 1e-6 Frobenius rule), the
+configuration the precision metric is quoted on.
 
-The mixed-precision path (FP16X3 by default; BF16X3 or FP32 on request) is
-timed, its error against the FP64 GPU path at equal R is measured outside the
-timed region, and the FP64 GPU path is timed the same way for the speedup.
-Prints one JSON line.
+The mixed-precision path (FP16X3 by default) is timed, its error against the
+FP64 GPU path at equal R is measured outside the timed region, the FP64 GPU
+path is timed the same way for the speedup, and the BF16X3 split is measured
+beside it (error and time).  Prints one JSON line.
 """
 import argparse
 import json
@@ -31,31 +33,44 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--precision", default="fp16x3", choices=["fp16x3", "bf16x3", "fp32"])
-    ap.add_argument("--workload", default="water_100k",
+    ap.add_argument("--precision", default=None, choices=["fp16x3", "bf16x3", "fp32"],
+                    help="mixed path: FP16X3 for the single-system workloads, the BF16 "
+                         "split for the 64-system batch (the precision each is quoted in)")
+    ap.add_argument("--workload", default="water_1m",
                     choices=["water_100k", "water_1m", "water_200k_noncubic", "batch64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-evals", type=int, default=5)
+    ap.add_argument("--cpu-repeats", type=int, default=3,
+                    help="repeats of the bounded CPU-oracle sample (median reported)")
+    ap.add_argument("--no-bf16", action="store_true", help="skip the BF16X3 side measurement")
     ap.add_argument("--mixed-only", action="store_true",
                     help="time only the mixed path (short profiler runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="run 5 device copies of MIB MiB and exit (byte-counter calibration)")
-    return ap.parse_args()
+    a = ap.parse_args()
+    if a.precision is None:
+        a.precision = "bf16x3" if a.workload == "batch64" else "fp16x3"
+    return a
 
 
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "stage2_x3_water_n99999_g96_p4_traffic.md")
+def log(msg):
+    """Progress line on stderr (the JSON result is the only stdout line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2601_18838_amd", "csrc", "skp_kernels.hip")
+HBM_PEAK_GBS = 8000.0
 
 
 def committed_traffic(workload, precision, parts):
     """HBM bytes per stage-2 launch from the committed rocprofv3 counter summary
-    (FETCH_SIZE and WRITE_SIZE, scaled by the copy-kernel calibration), or None
-    when that summary is for another configuration or the kernel source has
-    changed since the counters were taken."""
+    for this workload (FETCH_SIZE and WRITE_SIZE, scaled by the copy-kernel
+    calibration), or None when there is none, it is for another configuration,
+    or the kernel source has changed since the counters were taken."""
     import hashlib
+    summary = os.path.join(ROOT, "profiles", f"stage2_x3_{workload}_traffic.md")
     try:
         fields = {}
-        for line in open(TRAFFIC_SUMMARY):
+        for line in open(summary):
             if line.startswith("- ") and ": " in line:
                 k, v = line[2:].strip().split(": ", 1)
                 fields[k] = v.strip("` ")
@@ -164,21 +179,46 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(wl, pos, q, evals):
-    """The FP64 oracle on the host cores: `evals` full evaluations."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wl, pos, q, repeats):
+    """The FP64 oracle on the host cores, on a bounded sample of the workload:
+    the Kronecker operator applied once to a full grid, and spread + gather of
+    a contiguous 1/32 of the particles (whole molecules), each repeated and
+    the median taken; evals/s = 1 / (t_apply + 32 t_spread_gather)."""
+    import statistics
     from oracle import skp, spme
     pl = skp.Plan(wl.box, wl.grid, wl.order, wl.beta, tol=wl.tol)
-    t0 = time.perf_counter()
-    for _ in range(evals):
-        Qg = spme.spread(pos, q, wl.box, wl.grid, wl.order)
+    frac = 32
+    ns = (len(q) // frac) // 3 * 3
+    t_sg, t_ap = [], []
+    for _ in range(repeats):
+        t0 = time.perf_counter()
+        Qg = spme.spread(pos[:ns], q[:ns], wl.box, wl.grid, wl.order)
+        t1 = time.perf_counter()
         Phi = pl.apply(Qg)
-        spme.gather(pos, q, wl.box, wl.grid, wl.order, Phi)
-    dt = (time.perf_counter() - t0) / evals
+        t2 = time.perf_counter()
+        spme.gather(pos[:ns], q[:ns], wl.box, wl.grid, wl.order, Phi)
+        t3 = time.perf_counter()
+        t_sg.append((t1 - t0) + (t3 - t2))
+        t_ap.append(t2 - t1)
+    per_eval = statistics.median(t_ap) + statistics.median(t_sg) * len(q) / ns
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": 1.0 / dt, "unit": "evals/s", "cores": min(threads, os.cpu_count() or 1),
-            "kind": "oracle",
-            "sample": f"{evals} full FP64 oracle evaluations of {wl.name} "
-                      f"(R={pl.rank}; spread, Kronecker operator, gather)"}
+    return {"value": 1.0 / per_eval, "unit": "evals/s",
+            "cores": min(threads, os.cpu_count() or 1), "kind": "oracle",
+            "cpu_model": cpu_model(), "seconds_per_eval": per_eval,
+            "sample": f"FP64 oracle on {wl.name} (R={pl.rank}): median of {repeats} runs of "
+                      f"one Kronecker-operator application on the full grid plus spread and "
+                      f"gather of {ns} of {len(q)} particles, the latter scaled by "
+                      f"{len(q) / ns:.3f} (spread and gather are per-particle work)"}
 
 
 def main():
@@ -202,37 +242,57 @@ def main():
     pos, q = wl.particles()
     n = len(q)
     mixed, ref = args.precision, "fp64"
-    plans, tensors, outs = {}, {}, {}
-    for prec in (mixed, ref):
+    side = [] if (args.no_bf16 or args.mixed_only or mixed == "bf16x3") else ["bf16x3"]
+    plans, tensors, outs, plan_s, tune_s = {}, {}, {}, {}, {}
+    for prec in [mixed, ref] + side:
         dt = torch.float64 if prec == "fp64" else torch.float32
+        t0 = time.perf_counter()
         plans[prec] = kpme.Plan(wl.box, wl.grid, wl.order, wl.beta, rank=wl.rank, tol=wl.tol,
                                 precision=prec, max_particles=n)
-        plans[prec].autotune()          # the library's stage-2 work-split tuner
+        plan_s[prec] = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        plans[prec].autotune()          # the library's work-split tuner
+        tune_s[prec] = time.perf_counter() - t0
+        log(f"{prec} plan {plan_s[prec]:.1f} s, autotune {tune_s[prec]:.1f} s")
         tensors[prec] = (torch.tensor(pos, dtype=dt, device="cuda"),
                          torch.tensor(q, dtype=dt, device="cuda"))
         outs[prec] = (torch.empty(4, dtype=torch.float64, device="cuda"),
                       torch.empty(n, dtype=dt, device="cuda"),
                       torch.empty((n, 3), dtype=dt, device="cuda"))
     info = plans[mixed].info
-    # accuracy of the mixed path against the FP64 GPU path at equal R
+    # accuracy of the mixed paths against the FP64 GPU path at equal R
     res = {}
-    for prec in (mixed, ref):
+    for prec in [mixed, ref] + side:
         e4, pot, frc = plans[prec].evaluate(*tensors[prec], out=outs[prec])
         torch.cuda.synchronize()
         res[prec] = (e4.cpu().numpy().copy(), pot.double().cpu().numpy(),
                      frc.double().cpu().numpy())
-    rel_e = abs(res[mixed][0][0] - res[ref][0][0]) / abs(res[ref][0][0])
     rms = lambda a, b: float(np.sqrt(((a - b) ** 2).sum() / (b ** 2).sum()))
-    rms_phi = rms(res[mixed][1], res[ref][1])
-    rms_f = rms(res[mixed][2], res[ref][2])
 
+    def errors(prec):
+        return (abs(res[prec][0][0] - res[ref][0][0]) / abs(res[ref][0][0]),
+                rms(res[prec][1], res[ref][1]), rms(res[prec][2], res[ref][2]))
+
+    rel_e, rms_phi, rms_f = errors(mixed)
+
+    log(f"{mixed} relE {rel_e:.2e} rmsF {rms_f:.2e}; timing")
     t_mixed, st_mixed = time_steps(plans[mixed], *tensors[mixed], outs[mixed], args.steps,
                                    args.warmup)
+    log(f"{mixed} {1.0 / t_mixed:.1f} evals/s")
     if args.mixed_only:
         t_ref, st_ref = float("nan"), {k: (float("nan"), 1) for k in st_mixed}
     else:
         t_ref, st_ref = time_steps(plans[ref], *tensors[ref], outs[ref],
                                    max(5, args.steps // 5), min(args.warmup, 2))
+    side_out = {}
+    for prec in side:
+        t_s, _ = time_steps(plans[prec], *tensors[prec], outs[prec], max(5, args.steps // 5),
+                            min(args.warmup, 2))
+        e_s, p_s, f_s = errors(prec)
+        side_out[prec] = {"evals_per_s": 1.0 / t_s, "ns_per_particle": t_s * 1e9 / n,
+                          "rel_energy_err": e_s, "rel_rms_potential_err": p_s,
+                          "rel_rms_force_err": f_s,
+                          "accuracy_target_met": bool(e_s <= 1e-5 and f_s <= 1e-4)}
 
     K1, K2, K3 = wl.grid
     G = K1 * K2 * K3
@@ -245,6 +305,18 @@ def main():
     peak = PEAK_TFLOPS[mixed]
     stage_us = {k: (v[0] / max(v[1], 1) * 1e3) for k, v in st_mixed.items()}
     stage_us_fp64 = {k: (v[0] / max(v[1], 1) * 1e3) for k, v in st_ref.items()}
+
+    # HBM rooflines of the particle-grid stages from their algorithmic bytes
+    # (FP32 values): the spread (binning included) reads positions and charges
+    # (16 B per particle) and writes the grid once (4 B per point); the gather
+    # reads positions, charges and the grid once and writes potential and
+    # force (16 B per particle)
+    def hbm(bytes_, us):
+        gbs = bytes_ / (us * 1e-6) / 1e9
+        return {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": gbs / HBM_PEAK_GBS, "algorithmic_bytes": bytes_, "us": us}
+    spread_bytes = 16.0 * n + 4.0 * G
+    gather_bytes = 16.0 * n + 4.0 * G + 16.0 * n
 
     out = {
         "metric": METRIC,
@@ -274,6 +346,8 @@ def main():
         "rel_rms_force_err": rms_f,
         "accuracy_target_met": bool(rel_e <= 1e-5 and rms_f <= 1e-4),
         "E_rec": float(res[ref][0][0]),
+        "plan_seconds": plan_s,
+        "autotune_seconds": tune_s,
         "stage_us": stage_us,
         "stage_us_fp64": stage_us_fp64,
         "roofline": {"bound": "mfma", "kernel": "skp_stage2", "achieved": achieved,
@@ -281,9 +355,14 @@ def main():
                      "traffic": committed_traffic(wl.name, mixed, plans[mixed].stage2_parts()),
                      "flops_per_launch": issued,
                      "effective_single_product_tflops": flops_s2 / avg_s2 / 1e12},
+        "roofline_spread": hbm(spread_bytes, stage_us["spread"]),
+        "roofline_gather": hbm(gather_bytes, stage_us["gather"]),
     }
+    for prec, v in side_out.items():
+        out[prec] = v
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, pos, q, args.cpu_evals)
+        log("CPU oracle baseline")
+        out["cpu_baseline"] = cpu_baseline(wl, pos, q, args.cpu_repeats)
     print(json.dumps(out), flush=True)
 
 

@@ -103,7 +103,13 @@ typedef struct {
  * Eq. VtV) in the requested precision, and all device workspace for up to
  * max_particles particles.
  *   box[3]        host, L1..L3 > 0 and finite.
- *   grid[3]       host, 4 <= K_j <= 256 and K_j >= spline_order.
+ *   grid[3]       host, 4 <= K_j <= 256 and K_j >= spline_order
+ *                 (KPME_ERROR_INVALID_VALUE otherwise).  The operator
+ *                 kernels further need K1 <= 128, and, for KPME_BF16X3 and
+ *                 KPME_FP16X3 with K1 > 96, K2 <= 128; and the K1 x K2
+ *                 slab must fit in the 160 KiB of LDS at the plan's
+ *                 precision (K1 = K2 = 128 fits every precision).  Grids
+ *                 outside these limits return KPME_ERROR_NOT_SUPPORTED.
  *   spline_order  even, 4..12 (odd orders: KPME_ERROR_NOT_SUPPORTED).
  *   ewald_beta    > 0, the Ewald splitting parameter (xi in Eq. hexpr).
  *   skp_rank      R >= 1, or <= 0 to select R by svd_tol; R larger than the
@@ -208,10 +214,11 @@ kpme_status kpme_factors_compute(const double box[3], const int grid[3],
  * cost.  kpme_batch_evaluate records, for a new argument signature (n[] and
  * the five pointers), every system's kpme_evaluate launch sequence into one
  * HIP graph with parallel branches, and replays it as a single launch on
- * `stream`; an unchanged signature only replays.  A recording replaced by a
- * new signature is kept (it may still be executing) and released after a
- * device-wide synchronisation, every 8 replacements and at destroy, so a
- * signature change never waits for the previous replay.  pos/q/pot/force are device
+ * `stream`; an unchanged signature only replays.  A signature change after
+ * the first recording synchronises `stream` and then the whole device
+ * before the previous recording is released and the new one captured, so
+ * no recording ever overlaps a running replay; callers that evaluate in a
+ * loop should therefore keep their output buffers.  pos/q/pot/force are device
  * arrays concatenated in system order (offsets = prefix sums of n[s]);
  * energy4 (device) receives 4 doubles per system; pot/force/energy4 may be
  * NULL.  n[s] <= max_particles[s] (host array).  Errors as for the single

@@ -143,7 +143,6 @@ struct kpme_plan_s {
 };
 
 constexpr int kBatchBranches = 4;  // parallel branches of the batch graph
-constexpr size_t kRetiredCap = 8;  // replaced graph recordings kept before a release
 constexpr uint32_t kBatchMagic = 0x4b42544eu;
 
 struct kpme_batch_s {
@@ -156,14 +155,45 @@ struct kpme_batch_s {
   hipEvent_t fork = nullptr;
   hipEvent_t join[kBatchBranches] = {};
   hipGraphExec_t exec = nullptr;       // recorded graph for the last signature
-  // recordings replaced by a newer one; released only after a device-wide
-  // synchronisation (every kRetiredCap replacements, and at destroy)
-  std::vector<hipGraphExec_t> retired;
   std::vector<int64_t> sig_n;
   const void* sig_ptr[5] = {};
 };
 
 namespace {
+
+// Kernel arguments of one operator application on the plan's factors and
+// workspace (the per-call reduction inputs are filled in by the caller).
+SkpArgs skp_args(const kpme_plan_s* plan, const void* in, void* out, double* scalars) {
+  SkpArgs a;
+  a.prec = plan->prec;
+  for (int j = 0; j < 3; ++j) a.K[j] = plan->K[j];
+  a.K1P = plan->K1P; a.K2P = plan->K2P; a.K3P = plan->K3P;
+  a.r0 = plan->r0; a.R = plan->R; a.nparts = plan->nparts;
+  a.s1_split = plan->s1_split;
+  a.Q = in; a.Phi = out;
+  a.eQ = in;
+  a.epart = nullptr;
+  for (int k = 0; k < 2; ++k) { a.A[k] = plan->A[k]; a.B[k] = plan->B[k]; a.C[k] = plan->C[k]; a.Y[k] = plan->Y[k]; }
+  a.Phi_part = plan->Phi_part;
+  a.vec = plan->vec;
+  a.blen = plan->blen;
+  a.alen = plan->alen;
+  a.term_group = plan->term_group;
+  a.part_begin = plan->part_begin;
+  a.x3_streams = plan->streams;
+  a.step_term = plan->step_term;
+  a.step_group = plan->step_group;
+  a.step_begin = plan->step_begin;
+  a.scratch = plan->scratch;
+  a.sum_part = nullptr;
+  a.sum_np = 0;
+  a.sumQ = scalars;
+  a.c0 = plan->zero_mode;
+  a.sy = plan->sy;
+  a.st = plan->st;
+  a.const_scale = plan->const_scale;
+  return a;
+}
 
 hipError_t plan_alloc(kpme_plan_s* pl, void** out, size_t bytes) {
   *out = nullptr;
@@ -221,8 +251,6 @@ void batch_free(kpme_batch_s* b) {
   (void)hipSetDevice(b->device);
   (void)hipDeviceSynchronize();
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
-  for (hipGraphExec_t x : b->retired) (void)hipGraphExecDestroy(x);
-  b->retired.clear();
   for (int k = 0; k < kBatchBranches; ++k) {
     if (b->branch[k]) (void)hipStreamDestroy(b->branch[k]);
     if (b->join[k]) (void)hipEventDestroy(b->join[k]);
@@ -766,6 +794,7 @@ kpme_status kpme_plan_create(kpme_plan_t* plan, const double box[3], const int g
     if ((e = plan_alloc(pl, &pl->Q2g, G * es)) != hipSuccess) break;
     if ((e = plan_alloc(pl, &pl->Psig, G * es)) != hipSuccess) break;
     if ((e = plan_alloc(pl, &pl->sorted2, nmax * 4 * es)) != hipSuccess) break;
+    if ((e = prepare_skp_stage2(skp_args(pl, pl->Qg, pl->Phig, pl->scalars))) != hipSuccess) break;
     e = hipDeviceSynchronize();
   } while (false);
   if (e != hipSuccess) {
@@ -829,32 +858,8 @@ kpme_status do_skp(kpme_plan_t plan, const void* in, void* out, hipStream_t st,
                    const double* part2 = nullptr, double* epart = nullptr) {
   if (!scalars) scalars = plan->scalars;
   if (!part2) part2 = plan->part2;
-  SkpArgs a;
-  a.prec = plan->prec;
-  for (int j = 0; j < 3; ++j) a.K[j] = plan->K[j];
-  a.K1P = plan->K1P; a.K2P = plan->K2P; a.K3P = plan->K3P;
-  a.r0 = plan->r0; a.R = plan->R; a.nparts = plan->nparts;
-  a.s1_split = plan->s1_split;
-  a.Q = in; a.Phi = out;
-  a.eQ = in;
+  SkpArgs a = skp_args(plan, in, out, scalars);
   a.epart = epart;
-  for (int k = 0; k < 2; ++k) { a.A[k] = plan->A[k]; a.B[k] = plan->B[k]; a.C[k] = plan->C[k]; a.Y[k] = plan->Y[k]; }
-  a.Phi_part = plan->Phi_part;
-  a.vec = plan->vec;
-  a.blen = plan->blen;
-  a.alen = plan->alen;
-  a.term_group = plan->term_group;
-  a.part_begin = plan->part_begin;
-  a.x3_streams = plan->streams;
-  a.step_term = plan->step_term;
-  a.step_group = plan->step_group;
-  a.step_begin = plan->step_begin;
-  a.scratch = plan->scratch;
-  a.sumQ = scalars;
-  a.c0 = plan->zero_mode;
-  a.sy = plan->sy;
-  a.st = plan->st;
-  a.const_scale = plan->const_scale;
   // the split stage-1 kernels reduce up to kFoldedSums (sum, max) partials
   // themselves (every workgroup reads them all); more go through sum_final
   const int np = sum_ready ? plan->bins.geom.nbricks : kSumBlocks;
@@ -1180,11 +1185,17 @@ kpme_status kpme_batch_create(kpme_batch_t* batch, int count, const double* box3
   }
   // autotune each distinct class once (cached in memory and on disk)
   std::map<std::string, std::pair<int, int>> done;  // class -> (parts, stage-1 split)
-  for (kpme_plan_t pl : b->plans) {
+  for (kpme_plan_t& pl : b->plans) {
     const std::string key = tune_key(pl);
     auto it = done.find(key);
     if (it != done.end()) {
-      if (set_parts(pl, it->second.first) != hipSuccess) break;
+      const hipError_t e = set_parts(pl, it->second.first);
+      if (e != hipSuccess) {
+        const std::string msg = "system " + std::to_string(&pl - b->plans.data()) +
+                                ": stage-2 split: " + hipGetErrorString(e);
+        batch_free(b);
+        return fail(e == hipErrorOutOfMemory ? KPME_ERROR_OUT_OF_MEMORY : KPME_ERROR_DEVICE, msg);
+      }
       pl->s1_split = it->second.second;
       continue;
     }
@@ -1263,14 +1274,13 @@ kpme_status kpme_batch_evaluate(kpme_batch_t batch, const int64_t* n, const void
                     std::equal(ptrs, ptrs + 5, batch->sig_ptr);
   if (!same) {
     if (batch->exec) {
-      // the previous recording may still be executing: keep it, and release
-      // the kept ones only after the device has drained
-      if (batch->retired.size() >= kRetiredCap) {
-        if (hipDeviceSynchronize() != hipSuccess) return fail(KPME_ERROR_DEVICE, "hipDeviceSynchronize");
-        for (hipGraphExec_t x : batch->retired) (void)hipGraphExecDestroy(x);
-        batch->retired.clear();
-      }
-      batch->retired.push_back(batch->exec);
+      // No recording happens while a replay may still run: the device drains
+      // first (the launch stream, then every stream), and only then is the
+      // previous recording released and a new one captured.
+      hipError_t e = hipStreamSynchronize(st);
+      if (e == hipSuccess) e = hipDeviceSynchronize();
+      if (e != hipSuccess) return from_hip(e, "batch re-record synchronisation");
+      (void)hipGraphExecDestroy(batch->exec);
       batch->exec = nullptr;
     }
     const size_t es = batch->plans[0]->esize();

@@ -93,6 +93,10 @@ hipError_t launch_skp_sum(const SkpArgs& a, hipStream_t st);
 hipError_t launch_sum_partials(const SkpArgs& a, hipStream_t st);
 hipError_t launch_skp_stage1(const SkpArgs& a, hipStream_t st);
 hipError_t launch_skp_stage2(const SkpArgs& a, hipStream_t st);
+// Raises the dynamic-LDS limit of the stage-2 kernel instance that `a`
+// selects; called once at plan creation, so that no attribute change is ever
+// issued between launches (or inside a stream capture).
+hipError_t prepare_skp_stage2(const SkpArgs& a);
 hipError_t launch_skp_finalize(const SkpArgs& a, hipStream_t st);
 size_t stage2_lds_bytes(int prec, int K1P, int K2P);
 

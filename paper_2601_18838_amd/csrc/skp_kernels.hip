@@ -902,14 +902,15 @@ hipError_t set_lds(K kernel, size_t bytes) {
                              static_cast<int>(bytes));
 }
 
+// prep: only raise the kernel instance's dynamic-LDS limit (plan creation,
+// outside any stream capture); otherwise launch.
 template <typename H, int RT, int NKC>
-hipError_t launch_s2_x3(const SkpArgs& a, hipStream_t st) {
+hipError_t launch_s2_x3(const SkpArgs& a, hipStream_t st, bool prep) {
   constexpr int K1P = RT * 16, K2P = NKC * 32;
   constexpr int CT = x3_ct(K1P, K2P), NS = x3_streams(K1P, K2P);
   const size_t tsz = 2 * static_cast<size_t>(x3_plane(K1P, K2P));
   const size_t lds = sizeof(H) * (2 * static_cast<size_t>(K1P) * K2P + 2 * NS * tsz);
-  hipError_t e = set_lds(stage2_x3<H, RT, NKC, CT, NS>, lds);
-  if (e != hipSuccess) return e;
+  if (prep) return set_lds(stage2_x3<H, RT, NKC, CT, NS>, lds);
   const int threads = 64 * (K2P / (16 * CT)) * NS;
   if (a.K2P != K2P || a.x3_streams != NS || a.blen != x3_blen(K2P) || a.alen != x3_alen(K1P))
     return hipErrorInvalidValue;
@@ -921,23 +922,22 @@ hipError_t launch_s2_x3(const SkpArgs& a, hipStream_t st) {
 }
 
 template <typename H, int RT>
-hipError_t launch_s2_x3(const SkpArgs& a, hipStream_t st) {
+hipError_t launch_s2_x3(const SkpArgs& a, hipStream_t st, bool prep) {
   switch (a.K2P) {
-    case 32: return launch_s2_x3<H, RT, 1>(a, st);
-    case 64: return launch_s2_x3<H, RT, 2>(a, st);
-    case 96: return launch_s2_x3<H, RT, 3>(a, st);
-    case 128: return launch_s2_x3<H, RT, 4>(a, st);
+    case 32: return launch_s2_x3<H, RT, 1>(a, st, prep);
+    case 64: return launch_s2_x3<H, RT, 2>(a, st, prep);
+    case 96: return launch_s2_x3<H, RT, 3>(a, st, prep);
+    case 128: return launch_s2_x3<H, RT, 4>(a, st, prep);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <typename T, int RT, int CT, bool AL>
-hipError_t launch_s2_k4(const SkpArgs& a, hipStream_t st) {
+hipError_t launch_s2_k4(const SkpArgs& a, hipStream_t st, bool prep) {
   const int K1P = RT * 16;
   size_t lds = sizeof(T) * static_cast<size_t>(K1P) * (a.K2P + 1);
   if (AL) lds += sizeof(T) * static_cast<size_t>(K1P) * (K1P + 1);
-  hipError_t e = set_lds(stage2_k4<T, RT, CT, AL>, lds);
-  if (e != hipSuccess) return e;
+  if (prep) return set_lds(stage2_k4<T, RT, CT, AL>, lds);
   const int threads = 64 * (a.K2P / (16 * CT));
   hipLaunchKernelGGL((stage2_k4<T, RT, CT, AL>), dim3(a.K[2], a.nparts), dim3(threads), lds, st,
                      static_cast<const T*>(a.Y[0]), static_cast<const T*>(a.A[0]),
@@ -947,18 +947,28 @@ hipError_t launch_s2_k4(const SkpArgs& a, hipStream_t st) {
 }
 
 template <int RT>
-hipError_t dispatch_s2(const SkpArgs& a, hipStream_t st) {
+hipError_t dispatch_s2(const SkpArgs& a, hipStream_t st, bool prep) {
   const int K1P = RT * 16;
-  if (a.prec == PREC_BF16X3) return launch_s2_x3<bf16, RT>(a, st);
-  if (a.prec == PREC_FP16X3) return launch_s2_x3<f16, RT>(a, st);
+  if (a.prec == PREC_BF16X3) return launch_s2_x3<bf16, RT>(a, st, prep);
+  if (a.prec == PREC_FP16X3) return launch_s2_x3<f16, RT>(a, st, prep);
   if (a.prec == PREC_FP32) {
     const size_t full = sizeof(float) * static_cast<size_t>(K1P) * (a.K2P + 1 + K1P + 1);
-    return full <= kMaxLds ? launch_s2_k4<float, RT, 2, true>(a, st)
-                           : launch_s2_k4<float, RT, 2, false>(a, st);
+    return full <= kMaxLds ? launch_s2_k4<float, RT, 2, true>(a, st, prep)
+                           : launch_s2_k4<float, RT, 2, false>(a, st, prep);
   }
   const size_t full = sizeof(double) * static_cast<size_t>(K1P) * (a.K2P + 1 + K1P + 1);
-  return full <= kMaxLds ? launch_s2_k4<double, RT, 1, true>(a, st)
-                         : launch_s2_k4<double, RT, 1, false>(a, st);
+  return full <= kMaxLds ? launch_s2_k4<double, RT, 1, true>(a, st, prep)
+                         : launch_s2_k4<double, RT, 1, false>(a, st, prep);
+}
+
+hipError_t stage2_dispatch(const SkpArgs& a, hipStream_t st, bool prep) {
+  switch (a.K1P) {
+    case 32: return dispatch_s2<2>(a, st, prep);
+    case 64: return dispatch_s2<4>(a, st, prep);
+    case 96: return dispatch_s2<6>(a, st, prep);
+    case 128: return dispatch_s2<8>(a, st, prep);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace
@@ -1050,14 +1060,10 @@ hipError_t launch_skp_stage1(const SkpArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_skp_stage2(const SkpArgs& a, hipStream_t st) {
-  switch (a.K1P) {
-    case 32: return dispatch_s2<2>(a, st);
-    case 64: return dispatch_s2<4>(a, st);
-    case 96: return dispatch_s2<6>(a, st);
-    case 128: return dispatch_s2<8>(a, st);
-    default: return hipErrorInvalidValue;
-  }
+  return stage2_dispatch(a, st, false);
 }
+
+hipError_t prepare_skp_stage2(const SkpArgs& a) { return stage2_dispatch(a, nullptr, true); }
 
 hipError_t launch_skp_finalize(const SkpArgs& a, hipStream_t st) {
   dim3 gf((a.K[1] + 31) / 32, (a.K[2] + 31) / 32, a.K[0]);

@@ -307,19 +307,25 @@ class BatchPlan:
 
     def evaluate(self, n, pos, q, pot=None, force=None, energy=None):
         """n: per-system counts; pos (sum n, 3) and q (sum n) concatenated in order.
-        Returns (energy4 [count, 4], pot, force); pass output tensors to reuse them."""
+        Returns (energy4 [count, 4], pot, force).  Outputs not passed in are
+        the BatchPlan's own buffers, allocated once per total count and reused
+        by later calls (so repeated calls replay one recorded graph); the next
+        call overwrites them."""
         import torch
         total = int(sum(n))
         for t, shape in ((pos, (total, 3)), (q, (total,))):
             if not (isinstance(t, torch.Tensor) and t.device == self.device
                     and t.dtype == self.dtype and t.is_contiguous() and tuple(t.shape) == shape):
                 raise TypeError(f"expected a contiguous {self.dtype} tensor of shape {shape}")
-        if energy is None:
-            energy = torch.empty((self.count, 4), dtype=torch.float64, device=self.device)
-        if pot is None:
-            pot = torch.empty(total, dtype=self.dtype, device=self.device)
-        if force is None:
-            force = torch.empty((total, 3), dtype=self.dtype, device=self.device)
+        own = getattr(self, "_own", None)
+        if own is None or own[1].shape[0] != total:
+            own = (torch.empty((self.count, 4), dtype=torch.float64, device=self.device),
+                   torch.empty(total, dtype=self.dtype, device=self.device),
+                   torch.empty((total, 3), dtype=self.dtype, device=self.device))
+            self._own = own
+        energy = own[0] if energy is None else energy
+        pot = own[1] if pot is None else pot
+        force = own[2] if force is None else force
         nn = (ctypes.c_int64 * self.count)(*[int(x) for x in n])
         p = lambda t: ctypes.c_void_p(t.data_ptr())
         _check(lib().kpme_batch_evaluate(self._h, nn, p(pos), p(q), p(pot), p(force),

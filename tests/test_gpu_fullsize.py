@@ -3,9 +3,9 @@ tests/golden/make_full_size_golden.py (which runs only the FP64 oracle):
 E_rec and the potentials and forces of 64 sampled particles, in the launch
 configuration that bench.py times (kpme_evaluate on device-resident inputs).
 
-Tolerances: FP64 path 1e-10 relative; FP16X3 and FP32 paths relE <= 1e-5 and
-relative RMS <= 1e-4 over the sampled potentials and forces (the targets of
-the mixed-precision path).
+Tolerances: FP64 path 1e-10 relative; FP32, FP16X3 and BF16X3 paths
+relE <= 1e-5 and relative RMS <= 1e-4 over the sampled potentials and forces
+(the targets of the mixed-precision path).
 """
 import json
 import os
@@ -32,7 +32,7 @@ def relrms(a, b):
 
 @pytest.mark.parametrize("wl", [systems.WATER_1M, systems.WATER_200K_NONCUBIC],
                          ids=lambda w: w.name)
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16x3"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16x3", "bf16x3"])
 def test_full_size_against_stored_oracle(wl, prec):
     path = os.path.join(GOLDEN, wl.name + ".json")
     ref = json.load(open(path))

@@ -10,10 +10,10 @@ relative RMS, as named):
   against FP64 at equal R (measured ~1e-7 and ~2e-6 on the 1e5-atom water
   box); grid values within 1e-5 of the largest value.
 * BF16X3 path: hi + lo keeps 16 significand bits, so each operand carries a
-  relative error up to 2^-16; on small systems it meets the same targets, on
-  the 1e5-atom water box (a strongly cancelling energy) it reaches relE
-  1.2e-5 and RMS force 9.5e-5 (reproduced by a CPU emulation of the split
-  arithmetic), so there it is held to relE <= 3e-5 and RMS force <= 2e-4.
+  relative error up to 2^-16; it is held to the same targets (relE <= 1e-5,
+  RMS force <= 1e-4).  On the 1e5-atom water box (a strongly cancelling
+  energy) it measured relE 1.2e-5, so that case is an expected failure: the
+  BF16 split does not qualify there, and the FP16 split is the mixed path.
 The oracle runs at the same R, grid, order and beta, so truncation error is
 excluded and only precision error is measured.
 """
@@ -83,6 +83,11 @@ CASES = {
     # order 4 with a 6-point axis: one brick spans it (edge 6) and stencils
     # wrap inside that brick
     "short_axis_p4": ((6.0, 20.0, 24.0), (6, 20, 24), 4, 0.5, 12, 800, "pm1", 16),
+    # K2 and K3 padded to 128 (K1P = 64): the 128-row stage-1 tile and the
+    # 128-column stage-2 instances
+    "k2p_k3p_128": ((40.0, 100.0, 120.0), (40, 100, 120), 4, 0.34, 24, 3000, "pm1", 17),
+    # K3 = 160 (K3P > 128): the one-wave stage 1 that loops over K chunks
+    "k3p_160": ((24.0, 40.0, 160.0), (24, 40, 160), 6, 0.34, 20, 2001, "water", 18),
 }
 
 
@@ -213,35 +218,45 @@ def test_energy_paths_agree(prec, case):
     assert abs(host(e_full)[0] - e_part) <= tol * abs(e_part)
 
 
-def test_water_100k_mixed_paths_against_fp64():
-    """The 1e5-atom water box (96^3, p=4, R from the 1e-6 rule): the mixed
-    paths against the FP64 GPU path and the oracle at equal R."""
+_WATER_REF = {}
+
+
+def water_100k_reference():
+    """The oracle's evaluation of the 1e5-atom water box at R = 73 (cached)."""
     wl = systems.WATER_100K
-    print(f"[parity] {wl.name}", flush=True)
-    pos, q = wl.particles()
-    kpme = kp()
-    res = {}
-    for prec in ("fp64", "fp32", "bf16x3", "fp16x3"):
-        pl = kpme.Plan(wl.box, wl.grid, wl.order, wl.beta, rank=0, tol=wl.tol,
-                       precision=prec, max_particles=len(q))
-        e4, pot, frc = pl.evaluate(dev(pos, prec), dev(q, prec))
-        res[prec] = (host(e4), host(pot), host(frc), pl.info)
-    assert res["fp64"][3]["rank"] == 73
-    orc = oracle_plan(wl.box, wl.grid, wl.order, wl.beta, tol=wl.tol)
-    assert orc.rank == 73
-    ref = orc.evaluate(pos, q)
-    e64 = res["fp64"][0][0]
-    assert abs(e64 - ref["E_rec"]) < 1e-10 * abs(ref["E_rec"])
-    assert relrms(res["fp64"][2], ref["F"]) < 1e-10
-    bound = {"fp32": (1e-5, 1e-4), "fp16x3": (1e-5, 1e-4), "bf16x3": (3e-5, 2e-4)}
-    for prec, (tol_e, tol_f) in bound.items():
-        e, pot, frc, _ = res[prec]
-        rel_e = abs(e[0] - ref["E_rec"]) / abs(ref["E_rec"])
-        print(f"  {prec}: relE={rel_e:.3e} rmsPhi={relrms(pot, ref['phi']):.3e} "
-              f"rmsF={relrms(frc, ref['F']):.3e}", flush=True)
-        assert rel_e < tol_e, prec
-        assert relrms(pot, ref["phi"]) < tol_f, prec
-        assert relrms(frc, ref["F"]) < tol_f, prec
+    if not _WATER_REF:
+        pos, q = wl.particles()
+        orc = oracle_plan(wl.box, wl.grid, wl.order, wl.beta, tol=wl.tol)
+        assert orc.rank == 73
+        _WATER_REF.update(pos=pos, q=q, ref=orc.evaluate(pos, q))
+    return _WATER_REF
+
+
+@pytest.mark.parametrize("prec", [
+    "fp64", "fp32", "fp16x3",
+    pytest.param("bf16x3", marks=pytest.mark.xfail(
+        reason="BF16 hi+lo keeps 16 significand bits: relE 1.2e-5 measured on this "
+               "cancelling water box, above the 1e-5 bar", strict=False))])
+def test_water_100k_mixed_paths_against_fp64(prec):
+    """The 1e5-atom water box (96^3, p=4, R from the 1e-6 rule): every path
+    against the oracle at equal R -- FP64 to 1e-10, the others to the
+    mixed-precision targets relE <= 1e-5 and relative RMS <= 1e-4."""
+    wl = systems.WATER_100K
+    print(f"[parity] {wl.name} {prec}", flush=True)
+    w = water_100k_reference()
+    pos, q, ref = w["pos"], w["q"], w["ref"]
+    pl = kp().Plan(wl.box, wl.grid, wl.order, wl.beta, rank=0, tol=wl.tol,
+                   precision=prec, max_particles=len(q))
+    assert pl.info["rank"] == 73
+    e4, pot, frc = pl.evaluate(dev(pos, prec), dev(q, prec))
+    e, pot, frc = host(e4), host(pot), host(frc)
+    rel_e = abs(e[0] - ref["E_rec"]) / abs(ref["E_rec"])
+    print(f"  {prec}: relE={rel_e:.3e} rmsPhi={relrms(pot, ref['phi']):.3e} "
+          f"rmsF={relrms(frc, ref['F']):.3e}", flush=True)
+    tol_e, tol_f = (1e-10, 1e-10) if prec == "fp64" else (1e-5, 1e-4)
+    assert rel_e < tol_e
+    assert relrms(pot, ref["phi"]) < tol_f
+    assert relrms(frc, ref["F"]) < tol_f
 
 
 @pytest.mark.parametrize("prec,grid_sum", [("fp16x3", 0), ("fp64", 3)])
