@@ -21,8 +21,9 @@ definitions it follows:
   Eq. formfinale), the three mode products per term (Sec. 3.2-3.3, Alg. 1 and
   Alg. 2) and the constant correction (Sec. 4.1 Eq. termbonsum, Alg. 4).
 
-The sinc-quadrature SKP of the kernel (Sec. 2.1.2) is not part of the hot
-path built here and has no oracle module.
+* ``quadrature`` -- the second SKP construction: the sinc quadrature of 1/x
+  (Sec. 2.1.2, Eqs. one_over_r_int and quaddecompalpham), one Kronecker term
+  per node, with the brute-force choice of the lifting factor h.
 
 Parity status of each function is stated in its module header; every function
 here is pinned by a test in ``tests/test_oracle_*.py`` against values the
