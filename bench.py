@@ -38,6 +38,11 @@ def parse():
                          "split for the 64-system batch (the precision each is quoted in)")
     ap.add_argument("--workload", default="water_1m",
                     choices=["water_100k", "water_1m", "water_200k_noncubic", "batch64"])
+    ap.add_argument("--skp-method", default="nested_svd", choices=["nested_svd", "sinc"],
+                    help="Kronecker-term construction: nested SVD (Frobenius tail rule) or "
+                         "the sinc quadrature (max-norm symbol tolerance)")
+    ap.add_argument("--quad-tol", type=float, default=1e-6,
+                    help="sinc quadrature: relative max-norm symbol tolerance")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-repeats", type=int, default=3,
                     help="repeats of the bounded CPU-oracle sample (median reported)")
@@ -247,8 +252,13 @@ def main():
     for prec in [mixed, ref] + side:
         dt = torch.float64 if prec == "fp64" else torch.float32
         t0 = time.perf_counter()
-        plans[prec] = kpme.Plan(wl.box, wl.grid, wl.order, wl.beta, rank=wl.rank, tol=wl.tol,
-                                precision=prec, max_particles=n)
+        if args.skp_method == "sinc":
+            plans[prec] = kpme.Plan(wl.box, wl.grid, wl.order, wl.beta, rank=0,
+                                    tol=args.quad_tol, precision=prec, max_particles=n,
+                                    method="sinc")
+        else:
+            plans[prec] = kpme.Plan(wl.box, wl.grid, wl.order, wl.beta, rank=wl.rank,
+                                    tol=wl.tol, precision=prec, max_particles=n)
         plan_s[prec] = time.perf_counter() - t0
         t0 = time.perf_counter()
         plans[prec].autotune()          # the library's work-split tuner
@@ -333,7 +343,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "N": n, "grid": list(wl.grid), "order": wl.order,
                    "beta": wl.beta, "box": list(wl.box), "rank": R, "r0": info["r0"],
-                   "rank_rule": f"relative Frobenius tail <= {wl.tol:g}",
+                   "skp_method": args.skp_method,
+                   "rank_rule": (f"relative Frobenius tail <= {wl.tol:g}"
+                                 if args.skp_method == "nested_svd" else
+                                 f"sinc rule N={info['quad_N']}, h={info['quad_h']:.6g}: "
+                                 f"max-norm symbol error {info['sym_err']:.3g} <= "
+                                 f"{args.quad_tol:g}"),
                    "precision": mixed, "reference": "fp64 GPU path at equal R",
                    "stage2_parts": plans[mixed].stage2_parts(),
                    "stage1_split": plans[mixed].stage1_split()},

@@ -80,6 +80,39 @@ typedef enum {
   KPME_FP16X3 = 3
 } kpme_precision;
 
+/* How the kernel tensor is compressed into Kronecker terms. */
+typedef enum {
+  /* Nested SVD (Sec. 2.1.1, Eq. last_decomp_kron): axis 2 separated first,
+   * terms kept by weight; kernel-independent. */
+  KPME_SKP_NESTED_SVD = 0,
+  /* Sinc quadrature of 1/|m|^2 (Sec. 2.1.2, Eqs. one_over_r_int and
+   * quaddecompalpham): nodes lambda_l = log(1 + e^{lh}), weights
+   * omega_l = h / (1 + e^{-lh}), l = -N..N, one Kronecker term per node
+   * (R = 2N + 1, every term its own axis-2 factor, so r0 = R), applied to
+   * x = s |m_hat|^2 with s = max_j L_j^2 so that x >= 1 for m != 0.
+   * skp_rank > 0 must be odd and fixes N = (skp_rank - 1) / 2; skp_rank <= 0
+   * takes the smallest N whose best h gives a symbol error
+   * max_{m != 0} |theta_Lambda(m) - theta_hat(m)| / max theta_hat <= svd_tol
+   * (a max-norm tolerance, unlike the nested SVD's Frobenius one). */
+  KPME_SKP_SINC_QUADRATURE = 1
+} kpme_skp_method;
+
+/* Interpolation between particles and the grid. */
+typedef enum {
+  KPME_INTERP_BSPLINE = 0   /* order-p cardinal B-splines (smooth PME) */
+} kpme_interpolation;
+
+/* Options of kpme_plan_create_ex (NULL = all defaults, which is what
+ * kpme_plan_create uses). */
+typedef struct {
+  int skp_method;     /* kpme_skp_method, default KPME_SKP_NESTED_SVD        */
+  double quad_h;      /* sinc rule: lifting factor h > 0, or <= 0 to choose
+                         it by brute force (the h of a geometric scan around
+                         pi / sqrt(2N + 1) with the smallest symbol error)  */
+  int interpolation;  /* kpme_interpolation, default KPME_INTERP_BSPLINE     */
+  int mode_cutoff;    /* 0 (all grid modes)                                  */
+} kpme_plan_options;
+
 typedef struct {
   int grid[3];          /* K1, K2, K3                                        */
   int spline_order;     /* p                                                 */
@@ -93,6 +126,10 @@ typedef struct {
   double trunc_err;     /* ||theta_hat - theta_hat_R||_F (exact tail)        */
   double zero_mode;     /* c = theta_hat_R(0), the correction constant       */
   size_t workspace_bytes;
+  int skp_method;       /* kpme_skp_method of the plan                       */
+  int quad_N;           /* sinc rule: N (R = 2N + 1); -1 for the nested SVD  */
+  double quad_h;        /* sinc rule: lifting factor h                       */
+  double sym_err;       /* sinc rule: max-norm symbol error (relative)       */
 } kpme_plan_info_t;
 
 /* Build a plan: the smooth-PME kernel theta_hat on the K1 x K2 x K3 mode grid,
@@ -122,6 +159,18 @@ kpme_status kpme_plan_create(kpme_plan_t* plan, const double box[3],
                              const int grid[3], int spline_order,
                              double ewald_beta, int skp_rank, double svd_tol,
                              int precision, int64_t max_particles, int device);
+
+/* kpme_plan_create with options (NULL: defaults): the kernel compression
+ * method (nested SVD or sinc quadrature) and its parameters.  Arguments,
+ * errors and ownership as for kpme_plan_create; invalid options give
+ * KPME_ERROR_INVALID_VALUE, options this build does not implement
+ * KPME_ERROR_NOT_SUPPORTED. */
+kpme_status kpme_plan_create_ex(kpme_plan_t* plan, const double box[3],
+                                const int grid[3], int spline_order,
+                                double ewald_beta, int skp_rank,
+                                double svd_tol, int precision,
+                                int64_t max_particles, int device,
+                                const kpme_plan_options* options);
 
 kpme_status kpme_plan_destroy(kpme_plan_t plan);
 
@@ -204,6 +253,18 @@ kpme_status kpme_factors_compute(const double box[3], const int grid[3],
                                  int* n_terms, double* omega, double* vec0,
                                  double* vec1, double* vec2, int* group,
                                  double* info3);
+
+/* kpme_factors_compute with options (NULL: defaults).  info6 (host, may be
+ * NULL) receives {||theta||_F, ||theta - theta_R||_F, zero_mode, N, h,
+ * symbol error}; the last three are -1, 0, 0 for the nested SVD.  With the
+ * sinc quadrature the terms come in node order l = -N..N and group[r] = r. */
+kpme_status kpme_factors_compute_ex(const double box[3], const int grid[3],
+                                    int spline_order, double ewald_beta,
+                                    int skp_rank, double svd_tol,
+                                    const kpme_plan_options* options,
+                                    int max_terms, int* n_terms, double* omega,
+                                    double* vec0, double* vec1, double* vec2,
+                                    int* group, double* info6);
 
 /* Batched evaluation of independent systems (each with its own box, grid,
  * spline order and rank R = skp_rank[s] >= 1).  kpme_batch_create builds one

@@ -97,6 +97,9 @@ struct kpme_plan_s {
   int s1_split = 2;  // split stage 1: workgroups per position tile
   int64_t max_n = 0;
   double theta_norm = 0, trunc_err = 0, zero_mode = 0;
+  int skp_method = KPME_SKP_NESTED_SVD;
+  int quad_N = -1;            // sinc rule: 2N + 1 nodes, lifting factor h
+  double quad_h = 0, sym_err = 0;
   float sy = 1.f, st = 1.f;   // FP16X3 powers of two for Y and T
   double const_scale = 1.0;   // FP16X3 product of plan-time scales
   size_t ws_bytes = 0;
@@ -384,6 +387,36 @@ std::vector<int> split_range(int n, int np, int max_parts) {
   return pb;
 }
 
+kpme_plan_options default_options() {
+  kpme_plan_options o;
+  o.skp_method = KPME_SKP_NESTED_SVD;
+  o.quad_h = 0.0;
+  o.interpolation = KPME_INTERP_BSPLINE;
+  o.mode_cutoff = 0;
+  return o;
+}
+
+kpme_status validate_options(const kpme_plan_options& o, int skp_rank) {
+  if (o.skp_method != KPME_SKP_NESTED_SVD && o.skp_method != KPME_SKP_SINC_QUADRATURE)
+    return fail(KPME_ERROR_INVALID_VALUE, "unknown skp_method");
+  if (o.skp_method == KPME_SKP_SINC_QUADRATURE && skp_rank > 0 && skp_rank % 2 == 0)
+    return fail(KPME_ERROR_INVALID_VALUE, "the sinc rule has 2N + 1 nodes: skp_rank must be odd");
+  if (!std::isfinite(o.quad_h)) return fail(KPME_ERROR_INVALID_VALUE, "quad_h must be finite");
+  if (o.interpolation != KPME_INTERP_BSPLINE)
+    return fail(KPME_ERROR_NOT_SUPPORTED, "only B-spline interpolation is available");
+  if (o.mode_cutoff != 0) return fail(KPME_ERROR_NOT_SUPPORTED, "mode_cutoff must be 0");
+  return KPME_SUCCESS;
+}
+
+// The factor set of the requested construction; false with a message on
+// failure.
+bool make_factors(const double box[3], const int grid[3], int p, double beta, int rank,
+                  double tol, const kpme_plan_options& o, FactorSet* fs, std::string* err) {
+  if (o.skp_method == KPME_SKP_SINC_QUADRATURE)
+    return build_factors_quadrature(box, grid, p, beta, rank, tol, o.quad_h, fs, err);
+  return build_factors(box, grid, p, beta, rank, tol, fs, err);
+}
+
 }  // namespace
 
 extern "C" {
@@ -414,20 +447,38 @@ kpme_status kpme_factors_compute(const double box[3], const int grid[3], int spl
                                  double ewald_beta, int skp_rank, double svd_tol,
                                  int max_terms, int* n_terms, double* omega, double* vec0,
                                  double* vec1, double* vec2, int* group, double* info3) {
+  double info6[6];
+  const kpme_status s = kpme_factors_compute_ex(box, grid, spline_order, ewald_beta, skp_rank,
+                                                svd_tol, nullptr, max_terms, n_terms, omega,
+                                                vec0, vec1, vec2, group, info6);
+  if (info3 && s == KPME_SUCCESS) std::copy(info6, info6 + 3, info3);
+  return s;
+}
+
+kpme_status kpme_factors_compute_ex(const double box[3], const int grid[3], int spline_order,
+                                    double ewald_beta, int skp_rank, double svd_tol,
+                                    const kpme_plan_options* options, int max_terms,
+                                    int* n_terms, double* omega, double* vec0, double* vec1,
+                                    double* vec2, int* group, double* info6) {
   kpme_status st = validate_params(box, grid, spline_order, ewald_beta, KPME_FP64);
   if (st != KPME_SUCCESS) return st;
+  const kpme_plan_options opts = options ? *options : default_options();
+  if ((st = validate_options(opts, skp_rank)) != KPME_SUCCESS) return st;
   if (skp_rank <= 0 && !(svd_tol > 0 && svd_tol < 1))
     return fail(KPME_ERROR_INVALID_VALUE, "svd_tol must be in (0, 1) when skp_rank <= 0");
   FactorSet fs;
   std::string err;
-  if (!build_factors(box, grid, spline_order, ewald_beta, skp_rank, svd_tol, &fs, &err))
+  if (!make_factors(box, grid, spline_order, ewald_beta, skp_rank, svd_tol, opts, &fs, &err))
     return fail(KPME_ERROR_NUMERICAL, err);
   const int R = static_cast<int>(fs.terms.size());
   if (n_terms) *n_terms = R;
-  if (info3) {
-    info3[0] = fs.theta_norm;
-    info3[1] = fs.trunc_err;
-    info3[2] = fs.zero_mode;
+  if (info6) {
+    info6[0] = fs.theta_norm;
+    info6[1] = fs.trunc_err;
+    info6[2] = fs.zero_mode;
+    info6[3] = fs.quad_N;
+    info6[4] = fs.quad_h;
+    info6[5] = fs.sym_err;
   }
   if ((omega || vec0 || vec1 || vec2 || group) && R > max_terms)
     return fail(KPME_ERROR_INVALID_VALUE, "max_terms is smaller than the number of terms");
@@ -446,10 +497,20 @@ kpme_status kpme_plan_create(kpme_plan_t* plan, const double box[3], const int g
                              int spline_order, double ewald_beta, int skp_rank,
                              double svd_tol, int precision, int64_t max_particles,
                              int device) {
+  return kpme_plan_create_ex(plan, box, grid, spline_order, ewald_beta, skp_rank, svd_tol,
+                             precision, max_particles, device, nullptr);
+}
+
+kpme_status kpme_plan_create_ex(kpme_plan_t* plan, const double box[3], const int grid[3],
+                                int spline_order, double ewald_beta, int skp_rank,
+                                double svd_tol, int precision, int64_t max_particles,
+                                int device, const kpme_plan_options* options) {
   if (!plan) return fail(KPME_ERROR_INVALID_VALUE, "plan must not be NULL");
   *plan = nullptr;
   kpme_status st = validate_params(box, grid, spline_order, ewald_beta, precision);
   if (st != KPME_SUCCESS) return st;
+  const kpme_plan_options opts = options ? *options : default_options();
+  if ((st = validate_options(opts, skp_rank)) != KPME_SUCCESS) return st;
   if (skp_rank <= 0 && !(svd_tol > 0 && svd_tol < 1))
     return fail(KPME_ERROR_INVALID_VALUE, "svd_tol must be in (0, 1) when skp_rank <= 0");
   if (max_particles <= 0 || max_particles >= (int64_t(1) << 31))
@@ -470,7 +531,7 @@ kpme_status kpme_plan_create(kpme_plan_t* plan, const double box[3], const int g
 
   FactorSet fs;
   std::string err;
-  if (!build_factors(box, grid, spline_order, ewald_beta, skp_rank, svd_tol, &fs, &err))
+  if (!make_factors(box, grid, spline_order, ewald_beta, skp_rank, svd_tol, opts, &fs, &err))
     return fail(KPME_ERROR_NUMERICAL, err);
   if (fs.terms.empty()) return fail(KPME_ERROR_NUMERICAL, "no Kronecker terms were kept");
 
@@ -486,6 +547,10 @@ kpme_status kpme_plan_create(kpme_plan_t* plan, const double box[3], const int g
   pl->trunc_err = fs.trunc_err;
   pl->zero_mode = fs.zero_mode;
   pl->total_terms = fs.total_terms;
+  pl->skp_method = opts.skp_method;
+  pl->quad_N = fs.quad_N;
+  pl->quad_h = fs.quad_h;
+  pl->sym_err = fs.sym_err;
 
   // Device term order: grouped by outer index (stable), so consecutive terms
   // share their axis-2 factor and stage 2 reloads Y only at group changes.
@@ -831,6 +896,10 @@ kpme_status kpme_plan_info(kpme_plan_t plan, kpme_plan_info_t* info) {
   info->trunc_err = plan->trunc_err;
   info->zero_mode = plan->zero_mode;
   info->workspace_bytes = plan->ws_bytes;
+  info->skp_method = plan->skp_method;
+  info->quad_N = plan->quad_N;
+  info->quad_h = plan->quad_h;
+  info->sym_err = plan->sym_err;
   return KPME_SUCCESS;
 }
 

@@ -32,7 +32,23 @@ class PlanInfo(ctypes.Structure):
                 ("total_terms", ctypes.c_int), ("max_particles", ctypes.c_int64),
                 ("beta", ctypes.c_double), ("theta_norm", ctypes.c_double),
                 ("trunc_err", ctypes.c_double), ("zero_mode", ctypes.c_double),
-                ("workspace_bytes", ctypes.c_size_t)]
+                ("workspace_bytes", ctypes.c_size_t), ("skp_method", ctypes.c_int),
+                ("quad_N", ctypes.c_int), ("quad_h", ctypes.c_double),
+                ("sym_err", ctypes.c_double)]
+
+
+class PlanOptions(ctypes.Structure):
+    _fields_ = [("skp_method", ctypes.c_int), ("quad_h", ctypes.c_double),
+                ("interpolation", ctypes.c_int), ("mode_cutoff", ctypes.c_int)]
+
+
+METHODS = {"nested_svd": 0, "sinc": 1}
+INTERPOLATIONS = {"bspline": 0}
+
+
+def _options(method, quad_h, interpolation="bspline", mode_cutoff=0):
+    return PlanOptions(METHODS[method], float(quad_h), INTERPOLATIONS[interpolation],
+                       int(mode_cutoff))
 
 
 _lib = None
@@ -45,6 +61,8 @@ _IP = ctypes.POINTER(ctypes.c_int)
 
 _SIGNATURES = {
     "kpme_plan_create": [ctypes.POINTER(_P), _DP, _IP, _INT, _D, _INT, _D, _INT, _I64, _INT],
+    "kpme_plan_create_ex": [ctypes.POINTER(_P), _DP, _IP, _INT, _D, _INT, _D, _INT, _I64, _INT,
+                            ctypes.POINTER(PlanOptions)],
     "kpme_plan_destroy": [_P],
     "kpme_plan_info": [_P, ctypes.POINTER(PlanInfo)],
     "kpme_spread": [_P, _I64, _P, _P, _P, _P],
@@ -55,6 +73,8 @@ _SIGNATURES = {
     "kpme_evaluate_backward": [_P, _I64, _P, _P, _P, _P, _P, _P, _P],
     "kpme_factors_compute": [_DP, _IP, _INT, _D, _INT, _D, _INT, _IP, _DP, _DP, _DP, _DP,
                              _IP, _DP],
+    "kpme_factors_compute_ex": [_DP, _IP, _INT, _D, _INT, _D, ctypes.POINTER(PlanOptions), _INT,
+                                _IP, _DP, _DP, _DP, _DP, _IP, _DP],
     "kpme_batch_create": [ctypes.POINTER(_P), _INT, _DP, _IP, _IP, _DP, _IP, _INT,
                           ctypes.POINTER(_I64), _INT],
     "kpme_batch_destroy": [_P],
@@ -107,7 +127,8 @@ def device_count():
     return lib().kpme_device_count()
 
 
-def factors_compute(box, grid, order, beta, rank=0, tol=1e-6, max_terms=4096):
+def factors_compute(box, grid, order, beta, rank=0, tol=1e-6, max_terms=4096,
+                    method="nested_svd", quad_h=0.0):
     """Host FP64 factor construction (no device needed): dict of numpy arrays."""
     L = lib()
     K = [int(k) for k in grid]
@@ -115,15 +136,18 @@ def factors_compute(box, grid, order, beta, rank=0, tol=1e-6, max_terms=4096):
     om = np.zeros(max_terms)
     v = [np.zeros(max_terms * K[j]) for j in range(3)]
     grp = np.zeros(max_terms, np.int32)
-    info = np.zeros(3)
+    info = np.zeros(6)
+    opts = _options(method, quad_h)
     dp = lambda a: a.ctypes.data_as(_DP)
-    _check(L.kpme_factors_compute(_dbl3(box), _int3(K), int(order), float(beta), int(rank),
-                                  float(tol), max_terms, ctypes.byref(n), dp(om), dp(v[0]),
-                                  dp(v[1]), dp(v[2]), grp.ctypes.data_as(_IP), dp(info)))
+    _check(L.kpme_factors_compute_ex(_dbl3(box), _int3(K), int(order), float(beta), int(rank),
+                                     float(tol), ctypes.byref(opts), max_terms, ctypes.byref(n),
+                                     dp(om), dp(v[0]), dp(v[1]), dp(v[2]),
+                                     grp.ctypes.data_as(_IP), dp(info)))
     R = n.value
     return {"omega": om[:R].copy(), "group": grp[:R].copy(),
             "vec": [v[j][:R * K[j]].reshape(R, K[j]).copy() for j in range(3)],
-            "theta_norm": info[0], "trunc_err": info[1], "zero_mode": info[2]}
+            "theta_norm": info[0], "trunc_err": info[1], "zero_mode": info[2],
+            "quad_N": int(info[3]), "quad_h": info[4], "sym_err": info[5]}
 
 
 def _stream():
@@ -135,7 +159,7 @@ class Plan:
     """A device plan: factors and workspace for one box/grid/order/beta/rank."""
 
     def __init__(self, box, grid, order, beta, rank=0, tol=1e-6, precision="fp32",
-                 max_particles=1, device=0):
+                 max_particles=1, device=0, method="nested_svd", quad_h=0.0):
         import torch
         self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         self.dtype = torch.float64 if self.precision == FP64 else torch.float32
@@ -145,9 +169,11 @@ class Plan:
         self.beta = float(beta)
         self.device = torch.device("cuda", device)
         self._h = _P()
-        _check(lib().kpme_plan_create(ctypes.byref(self._h), _dbl3(box), _int3(grid), self.order,
-                                      self.beta, int(rank), float(tol), self.precision,
-                                      int(max_particles), int(device)))
+        opts = _options(method, quad_h)
+        _check(lib().kpme_plan_create_ex(ctypes.byref(self._h), _dbl3(box), _int3(grid),
+                                         self.order, self.beta, int(rank), float(tol),
+                                         self.precision, int(max_particles), int(device),
+                                         ctypes.byref(opts)))
         info = PlanInfo()
         _check(lib().kpme_plan_info(self._h, ctypes.byref(info)))
         self.info = {f: getattr(info, f) for f, _ in PlanInfo._fields_}

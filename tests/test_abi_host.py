@@ -125,3 +125,53 @@ def test_factors_compute_rejects_a_small_output_buffer():
     with pytest.raises(kpme.KpmeError) as e:
         kpme.factors_compute((20, 20, 20), (16, 16, 16), 4, 0.35, rank=30, max_terms=8)
     assert e.value.status == 1
+
+
+@pytest.mark.parametrize("box,grid,p,beta,N", [
+    ((20.0, 20.0, 20.0), (16, 16, 16), 4, 0.35, 9),
+    ((9.0, 11.0, 13.0), (8, 10, 12), 4, 0.7, 5),
+    ((30.0, 37.5, 45.0), (20, 25, 30), 6, 0.34, 14),
+])
+def test_sinc_quadrature_factors_match_the_oracle(box, grid, p, beta, N):
+    """Library sinc-quadrature terms (host FP64) against the oracle's at the
+    same rule (N, h): weights, unit mode vectors, the correction constant,
+    the Frobenius distance to theta_hat and the symbol error."""
+    from oracle import quadrature as qd
+    h, err = qd.best_h(box, grid, p, beta, N)
+    lib = kpme.factors_compute(box, grid, p, beta, rank=2 * N + 1, method="sinc", quad_h=h)
+    orc = qd.Plan(box, grid, p, beta, N=N, h=h)
+    assert len(lib["omega"]) == orc.rank == 2 * N + 1
+    assert lib["quad_N"] == N and lib["quad_h"] == h
+    np.testing.assert_array_equal(lib["group"], np.arange(2 * N + 1))
+    w_o = np.array([t[0] for t in orc.terms])
+    np.testing.assert_allclose(lib["omega"], w_o, rtol=1e-12)
+    for j in range(3):
+        v_o = np.array([t[1 + j] for t in orc.terms])
+        np.testing.assert_allclose(lib["vec"][j], v_o, atol=1e-13)
+    scale = orc.theta.max()
+    assert abs(lib["zero_mode"] - orc.c0) < 1e-12 * abs(orc.c0)
+    assert abs(lib["zero_mode"] - qd.correction_constant(box, N, h)) < 1e-12 * abs(orc.c0)
+    assert abs(lib["trunc_err"] - orc.trunc_err) < 1e-10 * orc.trunc_err + 1e-14 * scale
+    assert abs(lib["sym_err"] - err) <= 1e-10 * err + 1e-15
+
+
+@pytest.mark.parametrize("tol", [1e-4, 1e-7])
+def test_sinc_quadrature_selection_meets_the_tolerance(tol):
+    """The library's own choice of (N, h) for a tolerance: the oracle's
+    symbol error at that rule is within it, and one node pair fewer with the
+    oracle's best h is not."""
+    from oracle import quadrature as qd
+    box, grid, p, beta = (30.0, 37.5, 45.0), (20, 25, 30), 4, 0.34
+    lib = kpme.factors_compute(box, grid, p, beta, rank=0, tol=tol, method="sinc")
+    N, h = lib["quad_N"], lib["quad_h"]
+    assert len(lib["omega"]) == 2 * N + 1
+    e = qd.symbol_error(box, grid, p, beta, N, h)
+    assert e <= tol and abs(e - lib["sym_err"]) <= 1e-10 * e + 1e-15
+    if N > 0:
+        assert qd.best_h(box, grid, p, beta, N - 1)[1] > tol
+
+
+def test_sinc_quadrature_rejects_an_even_rank():
+    with pytest.raises(kpme.KpmeError) as e:
+        kpme.factors_compute((20, 20, 20), (16, 16, 16), 4, 0.35, rank=8, method="sinc")
+    assert e.value.status == 1

@@ -84,6 +84,7 @@ def test_batch64_against_stored_oracle():
     ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
                                       "batch64_pm1.json")))["systems"]
     batch = systems.batch_systems(count=64)
+    failures = []
     for prec in ("fp16x3", "bf16x3"):
         print(f"[batch] 64 systems {prec} vs stored oracle", flush=True)
         bp, pos, q, n = build(batch, prec)
@@ -91,22 +92,22 @@ def test_batch64_against_stored_oracle():
         e4 = e4.cpu().numpy()
         pot = pot.double().cpu().numpy()
         f = f.double().cpu().numpy()
-        off, worst_e, worst_p, worst_f = 0, 0.0, 0.0, 0.0
+        off, worst, bad = 0, [0.0, 0.0, 0.0], []
         for k, (wl, _, _) in enumerate(batch):
             r = ref[k]
             assert r["n"] == wl.n and r["rank"] == wl.rank
             idx = off + np.asarray(r["sample_index"])
-            rel_e = abs(e4[k, 0] - r["E_rec"]) / abs(r["E_rec"])
-            rp = relrms(pot[idx], np.asarray(r["phi"]))
-            rf = relrms(f[idx], np.asarray(r["F"]))
-            worst_e, worst_p, worst_f = max(worst_e, rel_e), max(worst_p, rp), max(worst_f, rf)
-            assert rel_e < 1e-5, (prec, k, rel_e)
-            assert rp < 1e-4, (prec, k, rp)
-            assert rf < 1e-4, (prec, k, rf)
+            errs = (abs(e4[k, 0] - r["E_rec"]) / abs(r["E_rec"]),
+                    relrms(pot[idx], np.asarray(r["phi"])), relrms(f[idx], np.asarray(r["F"])))
+            worst = [max(a, b) for a, b in zip(worst, errs)]
+            if errs[0] >= 1e-5 or errs[1] >= 1e-4 or errs[2] >= 1e-4:
+                bad.append((k, wl.grid, wl.order, wl.rank, ["%.2e" % x for x in errs]))
             off += wl.n
-        print(f"  {prec}: worst relE={worst_e:.2e} rmsPhi={worst_p:.2e} rmsF={worst_f:.2e}",
-              flush=True)
+        print(f"  {prec}: worst relE={worst[0]:.2e} rmsPhi={worst[1]:.2e} "
+              f"rmsF={worst[2]:.2e}; systems off the bar: {bad}", flush=True)
+        failures.extend((prec, b) for b in bad)
         del bp
+    assert not failures, failures
 
 
 def test_small_fp64_batch_against_oracle():
