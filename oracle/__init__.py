@@ -21,6 +21,9 @@ definitions it follows:
   Eq. formfinale), the three mode products per term (Sec. 3.2-3.3, Alg. 1 and
   Alg. 2) and the constant correction (Sec. 4.1 Eq. termbonsum, Alg. 4).
 
+* ``lagrange`` -- the paper's own discretisation (Sec. 2.2, Sec. 4.1): per-cell
+  equispaced Lagrange interpolation and the mode-truncated kernel alpha_M,
+  with the direct alpha_M mode sum it approximates.
 * ``quadrature`` -- the second SKP construction: the sinc quadrature of 1/x
   (Sec. 2.1.2, Eqs. one_over_r_int and quaddecompalpham), one Kronecker term
   per node, with the brute-force choice of the lifting factor h.
