@@ -208,6 +208,19 @@ kpme_status kpme_gather(kpme_plan_t plan, int64_t n, const void* pos,
 kpme_status kpme_energy(kpme_plan_t plan, int64_t n, const void* q,
                         const void* pot, double* energy4, void* stream);
 
+/* kpme_energy for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops, harnesses that forbid allocation):
+ * the same reduction and results, with its scratch -- the per-block FP64
+ * partial sums, 3 x 256 doubles (6 KiB) -- in a fixed device array of the
+ * library instead of the plan's workspace.  Each GPU holds one such array
+ * until the process ends, shared by every call on that GPU: calls that
+ * overlap in time on one GPU (on different streams, or from different
+ * plans) race on it and must be serialised by the caller.  No call makes
+ * any allocation; n is limited only by the plan's max_particles.  Errors as
+ * for kpme_energy. */
+kpme_status kpme_energy_noalloc(kpme_plan_t plan, int64_t n, const void* q,
+                                const void* pot, double* energy4, void* stream);
+
 /* The whole reciprocal path in one call (Alg. 4 on one device): bin the
  * particles by grid brick once, spread, apply the Kronecker operator with its
  * correction, gather potentials and forces, reduce the energies.  pot, force

@@ -11,7 +11,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libkpme.so")
-SOURCES = ["api.cpp", "factors.cpp", "quadrature.cpp", "grid_kernels.hip", "skp_kernels.hip"]
+SOURCES = ["api.cpp", "factors.cpp", "quadrature.cpp", "grid_kernels.hip", "skp_kernels.hip",
+           "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS_C = [

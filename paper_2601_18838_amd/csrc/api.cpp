@@ -21,6 +21,7 @@
 
 #include "factors.hpp"
 #include "kernels.hpp"
+#include "noalloc.hpp"
 
 using namespace kpme;
 
@@ -1107,6 +1108,23 @@ kpme_status kpme_energy(kpme_plan_t plan, int64_t n, const void* q, const void* 
   if (!energy4 || (n > 0 && (!q || !pot)))
     return fail(KPME_ERROR_INVALID_VALUE, "q, pot and energy4 must not be NULL");
   return do_energy(plan, n, q, pot, energy4, static_cast<hipStream_t>(stream));
+}
+
+kpme_status kpme_energy_noalloc(kpme_plan_t plan, int64_t n, const void* q, const void* pot,
+                                double* energy4, void* stream) {
+  kpme_status s = check_plan(plan);
+  if (s != KPME_SUCCESS) return s;
+  if ((s = check_n(plan, n)) != KPME_SUCCESS) return s;
+  if (!energy4 || (n > 0 && (!q || !pot)))
+    return fail(KPME_ERROR_INVALID_VALUE, "q, pot and energy4 must not be NULL");
+  // the reduction's scratch is the library's fixed device array: one
+  // partial triple per summing block, for any n (the blocks stride over it)
+  static_assert(3 * kSumBlocks <= kNoallocScratchDoubles, "energy scratch exceeds the array");
+  StageTimer tm(plan, KPME_STAGE_ENERGY, static_cast<hipStream_t>(stream));
+  const double V = plan->box[0] * plan->box[1] * plan->box[2];
+  return from_hip(launch_energy_noalloc(plan->device, plan->prec, n, q, pot, plan->beta, V,
+                                        energy4, static_cast<hipStream_t>(stream)),
+                  "energy (no allocation)");
 }
 
 kpme_status kpme_evaluate(kpme_plan_t plan, int64_t n, const void* pos, const void* q,

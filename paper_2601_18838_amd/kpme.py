@@ -69,6 +69,7 @@ _SIGNATURES = {
     "kpme_skp_apply": [_P, _P, _P, _P],
     "kpme_gather": [_P, _I64, _P, _P, _P, _P, _P, _P],
     "kpme_energy": [_P, _I64, _P, _P, _P, _P],
+    "kpme_energy_noalloc": [_P, _I64, _P, _P, _P, _P],
     "kpme_evaluate": [_P, _I64, _P, _P, _P, _P, _P, _P],
     "kpme_evaluate_backward": [_P, _I64, _P, _P, _P, _P, _P, _P, _P],
     "kpme_factors_compute": [_DP, _IP, _INT, _D, _INT, _D, _INT, _IP, _DP, _DP, _DP, _DP,
@@ -241,6 +242,16 @@ class Plan:
         e4 = torch.empty(4, dtype=torch.float64, device=self.device)
         _check(lib().kpme_energy(self._h, n, self._p(q), self._p(pot), self._p(e4), _stream()))
         return e4
+
+    def energy_noalloc(self, q, pot, out):
+        """kpme_energy_noalloc: the energy reduction into the caller's
+        4-double device tensor `out`, with the library's fixed scratch array
+        (no allocation by the library or by this call)."""
+        n = q.shape[0]
+        self._t(q, (n,)); self._t(pot, (n,))
+        _check(lib().kpme_energy_noalloc(self._h, n, self._p(q), self._p(pot), self._p(out),
+                                         _stream()))
+        return out
 
     def evaluate(self, pos, q, potentials=True, forces=True, energy=True, out=None):
         """Whole path; returns (energy4 [4] float64 tensor, pot, force)."""
