@@ -24,6 +24,9 @@ definitions it follows:
 * ``lagrange`` -- the paper's own discretisation (Sec. 2.2, Sec. 4.1): per-cell
   equispaced Lagrange interpolation and the mode-truncated kernel alpha_M,
   with the direct alpha_M mode sum it approximates.
+* ``rect``     -- the rectangular real cos/sin form of the per-axis factors
+  (Sec. 2.3 Eq. kronw, Sec. 2.4 Eq. VtV): A = V^T S V, two thin products per
+  mode product.
 * ``quadrature`` -- the second SKP construction: the sinc quadrature of 1/x
   (Sec. 2.1.2, Eqs. one_over_r_int and quaddecompalpham), one Kronecker term
   per node, with the brute-force choice of the lifting factor h.
