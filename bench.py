@@ -37,7 +37,11 @@ def parse():
                     help="mixed path: FP16X3 for the single-system workloads, the BF16 "
                          "split for the 64-system batch (the precision each is quoted in)")
     ap.add_argument("--workload", default="water_1m",
-                    choices=["water_100k", "water_1m", "water_200k_noncubic", "batch64"])
+                    choices=["water_100k", "water_1m", "water_200k_noncubic", "lagrange_m10",
+                             "batch64"])
+    ap.add_argument("--skp-form", default="circulant", choices=["circulant", "rect"],
+                    help="operator form: circulant factors on the matrix cores, or the "
+                         "rectangular real cos/sin factors (FP64/FP32)")
     ap.add_argument("--skp-method", default="nested_svd", choices=["nested_svd", "sinc"],
                     help="Kronecker-term construction: nested SVD (Frobenius tail rule) or "
                          "the sinc quadrature (max-norm symbol tolerance)")
@@ -201,17 +205,26 @@ def cpu_baseline(wl, pos, q, repeats):
     the median taken; evals/s = 1 / (t_apply + 32 t_spread_gather)."""
     import statistics
     from oracle import skp, spme
-    pl = skp.Plan(wl.box, wl.grid, wl.order, wl.beta, tol=wl.tol)
+    if wl.extra.get("interpolation") == "lagrange":
+        from oracle import lagrange as lg
+        cells = (wl.extra["cells"],) * 3
+        pl = lg.Plan(wl.box, cells, wl.order, wl.extra["mode_cutoff"], wl.beta, tol=wl.tol)
+        sp = lambda p_, q_: lg.spread(p_, q_, wl.box, cells, wl.order)
+        ga = lambda p_, q_, g_: lg.gather(p_, q_, wl.box, cells, wl.order, g_)
+    else:
+        pl = skp.Plan(wl.box, wl.grid, wl.order, wl.beta, tol=wl.tol)
+        sp = lambda p_, q_: spme.spread(p_, q_, wl.box, wl.grid, wl.order)
+        ga = lambda p_, q_, g_: spme.gather(p_, q_, wl.box, wl.grid, wl.order, g_)
     frac = 32
     ns = (len(q) // frac) // 3 * 3
     t_sg, t_ap = [], []
     for _ in range(repeats):
         t0 = time.perf_counter()
-        Qg = spme.spread(pos[:ns], q[:ns], wl.box, wl.grid, wl.order)
+        Qg = sp(pos[:ns], q[:ns])
         t1 = time.perf_counter()
         Phi = pl.apply(Qg)
         t2 = time.perf_counter()
-        spme.gather(pos[:ns], q[:ns], wl.box, wl.grid, wl.order, Phi)
+        ga(pos[:ns], q[:ns], Phi)
         t3 = time.perf_counter()
         t_sg.append((t1 - t0) + (t3 - t2))
         t_ap.append(t2 - t1)
@@ -243,11 +256,15 @@ def main():
         return
 
     wl = {"water_100k": systems.WATER_100K, "water_1m": systems.WATER_1M,
-          "water_200k_noncubic": systems.WATER_200K_NONCUBIC}[args.workload]
+          "water_200k_noncubic": systems.WATER_200K_NONCUBIC,
+          "lagrange_m10": systems.LAGRANGE_M10}[args.workload]
+    interp = dict(interpolation=wl.extra.get("interpolation", "bspline"),
+                  mode_cutoff=wl.extra.get("mode_cutoff", 0), form=args.skp_form)
     pos, q = wl.particles()
     n = len(q)
     mixed, ref = args.precision, "fp64"
-    side = [] if (args.no_bf16 or args.mixed_only or mixed == "bf16x3") else ["bf16x3"]
+    side = [] if (args.no_bf16 or args.mixed_only or mixed == "bf16x3"
+                  or args.skp_form == "rect") else ["bf16x3"]
     plans, tensors, outs, plan_s, tune_s = {}, {}, {}, {}, {}
     for prec in [mixed, ref] + side:
         dt = torch.float64 if prec == "fp64" else torch.float32
@@ -255,10 +272,10 @@ def main():
         if args.skp_method == "sinc":
             plans[prec] = kpme.Plan(wl.box, wl.grid, wl.order, wl.beta, rank=0,
                                     tol=args.quad_tol, precision=prec, max_particles=n,
-                                    method="sinc")
+                                    method="sinc", **interp)
         else:
             plans[prec] = kpme.Plan(wl.box, wl.grid, wl.order, wl.beta, rank=wl.rank,
-                                    tol=wl.tol, precision=prec, max_particles=n)
+                                    tol=wl.tol, precision=prec, max_particles=n, **interp)
         plan_s[prec] = time.perf_counter() - t0
         t0 = time.perf_counter()
         plans[prec].autotune()          # the library's work-split tuner
@@ -343,7 +360,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "N": n, "grid": list(wl.grid), "order": wl.order,
                    "beta": wl.beta, "box": list(wl.box), "rank": R, "r0": info["r0"],
-                   "skp_method": args.skp_method,
+                   "skp_method": args.skp_method, "skp_form": args.skp_form,
+                   "interpolation": interp["interpolation"],
+                   "mode_cutoff": interp["mode_cutoff"],
                    "rank_rule": (f"relative Frobenius tail <= {wl.tol:g}"
                                  if args.skp_method == "nested_svd" else
                                  f"sinc rule N={info['quad_N']}, h={info['quad_h']:.6g}: "

@@ -8,8 +8,10 @@
  *     phi = S* ( sum_r  A_r (x) B_r (x) C_r ) S q  -  c 1 1^T q
  *
  * with S the order-p cardinal B-spline spread onto a periodic K1 x K2 x K3
- * grid (the B-spline option of Sec. 2.2), the Kronecker terms from the nested
- * SVD of the smooth-PME kernel (Sec. 2.1.1) expanded into real circulant
+ * grid (the B-spline option of Sec. 2.2; or, by plan option, the paper's
+ * per-cell Lagrange interpolation), the Kronecker terms from the nested
+ * SVD of the smooth-PME kernel (Sec. 2.1.1; or its sinc quadrature,
+ * Sec. 2.1.2) expanded into real circulant
  * per-axis factors (Sec. 2.3-2.4), applied as three mode products per term
  * (Sec. 3.2-3.3, Alg. 1 and Alg. 2), and c the constant correction
  * (Sec. 4.1, Eq. termbonsum; Alg. 4).
@@ -99,8 +101,37 @@ typedef enum {
 
 /* Interpolation between particles and the grid. */
 typedef enum {
-  KPME_INTERP_BSPLINE = 0   /* order-p cardinal B-splines (smooth PME) */
+  /* order-p cardinal B-splines on the periodic grid (smooth PME); the kernel
+   * is theta_hat with the B-spline moduli over every DFT mode */
+  KPME_INTERP_BSPLINE = 0,
+  /* the paper's own scheme (Sec. 2.2, Eqs. interp1d and interpnd; Sec. 4.1):
+   * K_j / (L - 1) cells per axis, on each an equispaced product grid of
+   * L = spline_order nodes per axis with the end points shared by
+   * neighbouring cells (so the nodes form the periodic K_j-point grid), each
+   * particle interpolated by the Lagrange basis of its cell; the kernel is
+   * the mode-truncated alpha_M, exp(-pi^2 |m_hat|^2 / beta^2) /
+   * (pi V |m_hat|^2) for 0 < |m'_j| <= mode_cutoff on every axis, zero
+   * elsewhere (no B-spline moduli).  Needs K_j a multiple of L - 1 and
+   * 1 <= mode_cutoff with 2 mode_cutoff + 1 <= K_j (no aliasing);
+   * L even, 4..12. */
+  KPME_INTERP_LAGRANGE = 1
 } kpme_interpolation;
+
+/* Form in which the Kronecker terms are applied. */
+typedef enum {
+  /* real symmetric circulant K_j x K_j factors, three mode products per term
+   * on the matrix cores, terms grouped by their axis-2 factor (every
+   * precision) */
+  KPME_FORM_CIRCULANT = 0,
+  /* the rectangular real cos/sin factors of Sec. 2.3-2.4 (Eqs. kronw, VtV):
+   * each factor is F^T diag(d_r) F with F the min(2M + 1, K) x K real
+   * Fourier rows (M the mode cutoff, or K / 2), so every term shares F and
+   * the operator is three thin products into the real mode basis, one
+   * scaling by D = sum_r omega_r d_r1 (x) d_r2 (x) d_r3, and three thin
+   * products back (plain GEMMs, rocBLAS).  KPME_FP64 and KPME_FP32 only
+   * (KPME_ERROR_NOT_SUPPORTED otherwise). */
+  KPME_FORM_RECT = 1
+} kpme_skp_form;
 
 /* Options of kpme_plan_create_ex (NULL = all defaults, which is what
  * kpme_plan_create uses). */
@@ -110,7 +141,8 @@ typedef struct {
                          it by brute force (the h of a geometric scan around
                          pi / sqrt(2N + 1) with the smallest symbol error)  */
   int interpolation;  /* kpme_interpolation, default KPME_INTERP_BSPLINE     */
-  int mode_cutoff;    /* 0 (all grid modes)                                  */
+  int mode_cutoff;    /* Lagrange: M, the largest |m_j| kept; B-spline: 0    */
+  int skp_form;       /* kpme_skp_form, default KPME_FORM_CIRCULANT          */
 } kpme_plan_options;
 
 typedef struct {
@@ -130,6 +162,9 @@ typedef struct {
   int quad_N;           /* sinc rule: N (R = 2N + 1); -1 for the nested SVD  */
   double quad_h;        /* sinc rule: lifting factor h                       */
   double sym_err;       /* sinc rule: max-norm symbol error (relative)       */
+  int interpolation;    /* kpme_interpolation of the plan                    */
+  int mode_cutoff;      /* Lagrange: M; B-spline: 0                          */
+  int skp_form;         /* kpme_skp_form of the plan                         */
 } kpme_plan_info_t;
 
 /* Build a plan: the smooth-PME kernel theta_hat on the K1 x K2 x K3 mode grid,

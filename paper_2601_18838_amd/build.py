@@ -12,7 +12,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libkpme.so")
 SOURCES = ["api.cpp", "factors.cpp", "quadrature.cpp", "grid_kernels.hip", "skp_kernels.hip",
-           "noalloc.hip"]
+           "noalloc.hip", "rect.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS_C = [
@@ -53,7 +53,8 @@ def build(verbose=False):
             print("\n".join(msgs))
     tmp = LIB + ".tmp"
     rc, msgs = _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC",
-                     *[o for _, o in jobs], "-o", tmp], verbose)
+                     *[o for _, o in jobs], "-o", tmp, "-L/opt/rocm/lib", "-lrocblas",
+                     "-Wl,-rpath,/opt/rocm/lib"], verbose)
     if rc != 0:
         sys.stderr.write("\n".join(msgs) + "\n")
         raise RuntimeError("hipcc link failed")

@@ -22,6 +22,7 @@
 #include "factors.hpp"
 #include "kernels.hpp"
 #include "noalloc.hpp"
+#include "rect.hpp"
 
 using namespace kpme;
 
@@ -99,6 +100,14 @@ struct kpme_plan_s {
   int64_t max_n = 0;
   double theta_norm = 0, trunc_err = 0, zero_mode = 0;
   int skp_method = KPME_SKP_NESTED_SVD;
+  int interp = KPME_INTERP_BSPLINE, mode_cutoff = 0;
+  // rectangular-factor form of the operator (FP64 / FP32)
+  bool rect = false;
+  int rn[3] = {0, 0, 0};
+  void* rF[3] = {nullptr, nullptr, nullptr};
+  void* rFt[3] = {nullptr, nullptr, nullptr};
+  void* rD = nullptr;
+  void* blas = nullptr;       // rocBLAS handle of the rectangular form
   int quad_N = -1;            // sinc rule: 2N + 1 nodes, lifting factor h
   double quad_h = 0, sym_err = 0;
   float sy = 1.f, st = 1.f;   // FP16X3 powers of two for Y and T
@@ -141,6 +150,7 @@ struct kpme_plan_s {
     GridGeom g;
     for (int j = 0; j < 3; ++j) { g.K[j] = K[j]; g.L[j] = box[j]; g.invL[j] = 1.0 / box[j]; }
     g.p = p;
+    g.cell = interp == KPME_INTERP_LAGRANGE ? p - 1 : 0;
     return g;
   }
   long grid_size() const { return static_cast<long>(K[0]) * K[1] * K[2]; }
@@ -245,6 +255,8 @@ struct StageTimer {
 
 void plan_free(kpme_plan_s* pl) {
   prof_release(pl);
+  rect_destroy_handle(pl->blas);
+  pl->blas = nullptr;
   for (void* p : pl->allocations) (void)hipFree(p);
   pl->allocations.clear();
   pl->magic = 0;
@@ -394,19 +406,43 @@ kpme_plan_options default_options() {
   o.quad_h = 0.0;
   o.interpolation = KPME_INTERP_BSPLINE;
   o.mode_cutoff = 0;
+  o.skp_form = KPME_FORM_CIRCULANT;
   return o;
 }
 
-kpme_status validate_options(const kpme_plan_options& o, int skp_rank) {
+// grid and p are validated before (validate_params).
+kpme_status validate_options(const kpme_plan_options& o, int skp_rank, const int grid[3],
+                             int p) {
   if (o.skp_method != KPME_SKP_NESTED_SVD && o.skp_method != KPME_SKP_SINC_QUADRATURE)
     return fail(KPME_ERROR_INVALID_VALUE, "unknown skp_method");
   if (o.skp_method == KPME_SKP_SINC_QUADRATURE && skp_rank > 0 && skp_rank % 2 == 0)
     return fail(KPME_ERROR_INVALID_VALUE, "the sinc rule has 2N + 1 nodes: skp_rank must be odd");
   if (!std::isfinite(o.quad_h)) return fail(KPME_ERROR_INVALID_VALUE, "quad_h must be finite");
-  if (o.interpolation != KPME_INTERP_BSPLINE)
-    return fail(KPME_ERROR_NOT_SUPPORTED, "only B-spline interpolation is available");
-  if (o.mode_cutoff != 0) return fail(KPME_ERROR_NOT_SUPPORTED, "mode_cutoff must be 0");
+  if (o.skp_form != KPME_FORM_CIRCULANT && o.skp_form != KPME_FORM_RECT)
+    return fail(KPME_ERROR_INVALID_VALUE, "unknown skp_form");
+  if (o.interpolation == KPME_INTERP_BSPLINE) {
+    if (o.mode_cutoff != 0)
+      return fail(KPME_ERROR_INVALID_VALUE, "mode_cutoff applies to Lagrange interpolation only");
+    return KPME_SUCCESS;
+  }
+  if (o.interpolation != KPME_INTERP_LAGRANGE)
+    return fail(KPME_ERROR_INVALID_VALUE, "unknown interpolation");
+  for (int j = 0; j < 3; ++j) {
+    if (grid[j] % (p - 1) != 0)
+      return fail(KPME_ERROR_INVALID_VALUE,
+                  "Lagrange interpolation: every K_j must be a multiple of L - 1 (whole cells)");
+    if (o.mode_cutoff < 1 || 2 * o.mode_cutoff + 1 > grid[j])
+      return fail(KPME_ERROR_INVALID_VALUE,
+                  "Lagrange interpolation: need 1 <= mode_cutoff and 2 mode_cutoff + 1 <= K_j");
+  }
   return KPME_SUCCESS;
+}
+
+KernelSpec kernel_spec(const kpme_plan_options& o) {
+  KernelSpec ks;
+  ks.lagrange = o.interpolation == KPME_INTERP_LAGRANGE;
+  ks.cutoff = ks.lagrange ? o.mode_cutoff : 0;
+  return ks;
 }
 
 // The factor set of the requested construction; false with a message on
@@ -414,8 +450,9 @@ kpme_status validate_options(const kpme_plan_options& o, int skp_rank) {
 bool make_factors(const double box[3], const int grid[3], int p, double beta, int rank,
                   double tol, const kpme_plan_options& o, FactorSet* fs, std::string* err) {
   if (o.skp_method == KPME_SKP_SINC_QUADRATURE)
-    return build_factors_quadrature(box, grid, p, beta, rank, tol, o.quad_h, fs, err);
-  return build_factors(box, grid, p, beta, rank, tol, fs, err);
+    return build_factors_quadrature(box, grid, p, beta, rank, tol, o.quad_h, kernel_spec(o),
+                                    fs, err);
+  return build_factors(box, grid, p, beta, rank, tol, kernel_spec(o), fs, err);
 }
 
 }  // namespace
@@ -464,7 +501,7 @@ kpme_status kpme_factors_compute_ex(const double box[3], const int grid[3], int 
   kpme_status st = validate_params(box, grid, spline_order, ewald_beta, KPME_FP64);
   if (st != KPME_SUCCESS) return st;
   const kpme_plan_options opts = options ? *options : default_options();
-  if ((st = validate_options(opts, skp_rank)) != KPME_SUCCESS) return st;
+  if ((st = validate_options(opts, skp_rank, grid, spline_order)) != KPME_SUCCESS) return st;
   if (skp_rank <= 0 && !(svd_tol > 0 && svd_tol < 1))
     return fail(KPME_ERROR_INVALID_VALUE, "svd_tol must be in (0, 1) when skp_rank <= 0");
   FactorSet fs;
@@ -511,7 +548,9 @@ kpme_status kpme_plan_create_ex(kpme_plan_t* plan, const double box[3], const in
   kpme_status st = validate_params(box, grid, spline_order, ewald_beta, precision);
   if (st != KPME_SUCCESS) return st;
   const kpme_plan_options opts = options ? *options : default_options();
-  if ((st = validate_options(opts, skp_rank)) != KPME_SUCCESS) return st;
+  if ((st = validate_options(opts, skp_rank, grid, spline_order)) != KPME_SUCCESS) return st;
+  if (opts.skp_form == KPME_FORM_RECT && precision != KPME_FP64 && precision != KPME_FP32)
+    return fail(KPME_ERROR_NOT_SUPPORTED, "the rectangular-factor form runs in FP64 or FP32");
   if (skp_rank <= 0 && !(svd_tol > 0 && svd_tol < 1))
     return fail(KPME_ERROR_INVALID_VALUE, "svd_tol must be in (0, 1) when skp_rank <= 0");
   if (max_particles <= 0 || max_particles >= (int64_t(1) << 31))
@@ -549,6 +588,8 @@ kpme_status kpme_plan_create_ex(kpme_plan_t* plan, const double box[3], const in
   pl->zero_mode = fs.zero_mode;
   pl->total_terms = fs.total_terms;
   pl->skp_method = opts.skp_method;
+  pl->interp = opts.interpolation;
+  pl->mode_cutoff = opts.mode_cutoff;
   pl->quad_N = fs.quad_N;
   pl->quad_h = fs.quad_h;
   pl->sym_err = fs.sym_err;
@@ -861,6 +902,48 @@ kpme_status kpme_plan_create_ex(kpme_plan_t* plan, const double box[3], const in
     if ((e = plan_alloc(pl, &pl->Psig, G * es)) != hipSuccess) break;
     if ((e = plan_alloc(pl, &pl->sorted2, nmax * 4 * es)) != hipSuccess) break;
     if ((e = prepare_skp_stage2(skp_args(pl, pl->Qg, pl->Phig, pl->scalars))) != hipSuccess) break;
+    if (opts.skp_form == KPME_FORM_RECT) {
+      // rows of the real Fourier basis per axis (up to the mode cutoff) and
+      // the diagonal D = sum_r omega_r d_r1 (x) d_r2 (x) d_r3 in that basis
+      pl->rect = true;
+      std::vector<double> Fh[3];
+      std::vector<int> modes[3];
+      for (int j = 0; j < 3; ++j) {
+        const int M = opts.interpolation == KPME_INTERP_LAGRANGE ? opts.mode_cutoff : grid[j] / 2;
+        Fh[j] = rect_rows(grid[j], M, &modes[j]);
+        pl->rn[j] = static_cast<int>(modes[j].size());
+      }
+      const int n1 = pl->rn[0], n2 = pl->rn[1], n3 = pl->rn[2];
+      std::vector<double> D(static_cast<size_t>(n1) * n2 * n3, 0.0);
+      for (const Term& t : fs.terms) {
+        const std::vector<double> d1 = rect_weights(t.v[0], modes[0]);
+        const std::vector<double> d2 = rect_weights(t.v[1], modes[1]);
+        const std::vector<double> d3 = rect_weights(t.v[2], modes[2]);
+        for (int a = 0; a < n1; ++a)
+          for (int b = 0; b < n2; ++b) {
+            const double w = t.omega * d1[a] * d2[b];
+            double* row = &D[(static_cast<size_t>(a) * n2 + b) * n3];
+            for (int c = 0; c < n3; ++c) row[c] += w * d3[c];
+          }
+      }
+      auto put = [&](const std::vector<double>& h, void** dst) -> hipError_t {
+        hipError_t er = plan_alloc(pl, dst, h.size() * es);
+        if (er != hipSuccess) return er;
+        if (precision == KPME_FP64) return hipMemcpy(*dst, h.data(), h.size() * 8, hipMemcpyHostToDevice);
+        std::vector<float> f(h.begin(), h.end());
+        return hipMemcpy(*dst, f.data(), f.size() * 4, hipMemcpyHostToDevice);
+      };
+      for (int j = 0; j < 3 && e == hipSuccess; ++j) {
+        std::vector<double> Ft(Fh[j].size());
+        const int n = pl->rn[j], K = grid[j];
+        for (int r = 0; r < n; ++r)
+          for (int g = 0; g < K; ++g) Ft[static_cast<size_t>(g) * n + r] = Fh[j][static_cast<size_t>(r) * K + g];
+        if ((e = put(Fh[j], &pl->rF[j])) == hipSuccess) e = put(Ft, &pl->rFt[j]);
+      }
+      if (e != hipSuccess) break;
+      if ((e = put(D, &pl->rD)) != hipSuccess) break;
+      if ((e = rect_create_handle(&pl->blas)) != hipSuccess) break;
+    }
     e = hipDeviceSynchronize();
   } while (false);
   if (e != hipSuccess) {
@@ -898,6 +981,9 @@ kpme_status kpme_plan_info(kpme_plan_t plan, kpme_plan_info_t* info) {
   info->zero_mode = plan->zero_mode;
   info->workspace_bytes = plan->ws_bytes;
   info->skp_method = plan->skp_method;
+  info->interpolation = plan->interp;
+  info->skp_form = plan->rect ? KPME_FORM_RECT : KPME_FORM_CIRCULANT;
+  info->mode_cutoff = plan->mode_cutoff;
   info->quad_N = plan->quad_N;
   info->quad_h = plan->quad_h;
   info->sym_err = plan->sym_err;
@@ -945,6 +1031,34 @@ kpme_status do_skp(kpme_plan_t plan, const void* in, void* out, hipStream_t st,
     else
       e = sum_ready ? launch_sum_final(part2, plan->bins.geom.nbricks, scalars, st)
                     : launch_skp_sum(a, st);
+  }
+  if (e == hipSuccess && plan->rect) {
+    RectArgs ra;
+    ra.fp64 = plan->prec == PREC_FP64;
+    for (int j = 0; j < 3; ++j) {
+      ra.K[j] = plan->K[j];
+      ra.n[j] = plan->rn[j];
+      ra.F[j] = plan->rF[j];
+      ra.Ft[j] = plan->rFt[j];
+    }
+    ra.D = plan->rD;
+    ra.Q = in;
+    ra.Phi = out;
+    ra.wa = plan->Y[0];
+    ra.wb = plan->Phi_part;
+    ra.handle = plan->blas;
+    ra.sumQ = scalars;
+    ra.c0 = plan->zero_mode;
+    ra.epart = epart;
+    {
+      StageTimer tm(plan, KPME_STAGE_SKP2, st);
+      e = launch_rect_apply(ra, st);
+    }
+    if (e == hipSuccess) {
+      StageTimer tm(plan, KPME_STAGE_FINALIZE, st);
+      e = launch_rect_finalize(ra, st);
+    }
+    return from_hip(e, "skp_apply (rectangular factors)");
   }
   if (e == hipSuccess) {
     StageTimer tm(plan, KPME_STAGE_SKP1, st);

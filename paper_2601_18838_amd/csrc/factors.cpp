@@ -159,14 +159,16 @@ std::vector<double> circulant_column(const std::vector<double>& a) {
 }
 
 bool build_factors(const double box[3], const int K[3], int p, double beta, int rank,
-                   double tol, FactorSet* out, std::string* err) {
+                   double tol, const KernelSpec& ks, FactorSet* out, std::string* err) {
   const double V = box[0] * box[1] * box[2];
   int H[3];
   std::vector<double> w[3], bm[3], mh2[3];
   for (int j = 0; j < 3; ++j) {
     H[j] = K[j] / 2 + 1;
     w[j].resize(H[j]);
-    bm[j] = bspline_moduli(K[j], p);
+    const std::vector<double> bfull = ks.lagrange ? std::vector<double>() : bspline_moduli(K[j], p);
+    bm[j].resize(H[j]);
+    for (int h = 0; h < H[j]; ++h) bm[j][h] = ks.axis_factor(bfull, h);
     mh2[j].resize(H[j]);
     for (int h = 0; h < H[j]; ++h) {
       const bool single = (h == 0) || (K[j] % 2 == 0 && h == K[j] / 2);

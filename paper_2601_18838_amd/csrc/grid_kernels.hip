@@ -38,6 +38,13 @@ __device__ __forceinline__ void bspline(T f, T* w, T* dw) {
 // Scaled coordinate of one axis, computed in double: u = K (x / L mod 1),
 // with x / L taken as x times the host-computed 1 / L; returns the fractional
 // part and sets the base grid index floor(u) mod K.
+//
+// The compiler may fuse x * invL with the subtraction of its floor into one
+// FMA, which subtracts from the exact product: for x on the box face
+// (x = L) the exact product can lie just below the rounded 1.0, so s comes
+// out as a tiny negative number, u slightly below 0, floor(u) = -1 and the
+// fraction ~1.  That is the same stencil as base 0 with fraction 0, and is
+// kept as such by wrapping the base into [0, K) from either side.
 template <typename T>
 __device__ __forceinline__ T scaled(T x, double invL, int K, int& base) {
   double s = static_cast<double>(x) * invL;
@@ -46,11 +53,97 @@ __device__ __forceinline__ T scaled(T x, double invL, int K, int& base) {
   const double fl = floor(u);
   int b = static_cast<int>(fl);
   if (b >= K) b -= K;
+  if (b < 0) b += K;
   // a non-finite coordinate must not index outside the grid (its NaN weights
   // still propagate into the results)
   if (!(b >= 0 && b < K)) b = 0;
   base = b;
   return static_cast<T>(u - fl);
+}
+
+// Scaled coordinate and stencil base of one axis for either interpolation
+// rule (GridGeom::cell), computed in double:
+//   B-spline (cell == 0): u = K (x / L mod 1), base = floor(u) mod K, and the
+//     returned fractional part f in [0, 1) gives the weights M_p(f + t);
+//   Lagrange (cell = p - 1): the particle's cell c = floor(u / cell) has the
+//     nodes c cell + s, s = 0..p-1 (end points shared with the neighbouring
+//     cells); base = (c + 1) cell mod K, its last node, and the returned
+//     xi = u - c cell in [0, cell] is the position inside the cell.
+// Either way grid point (base - t) mod K carries stencil weight w[t].  Binning
+// and every spread and gather call this same function, so a particle's base
+// (and with it its brick) is the same everywhere.
+template <typename T>
+__device__ __forceinline__ T stencil_coord(T x, double invL, int K, int cell, int& base) {
+  if (cell == 0) return scaled(x, invL, K, base);
+  double s = static_cast<double>(x) * invL;
+  s -= floor(s);
+  double u = s * K;
+  const int Kc = K / cell;
+  int c = static_cast<int>(floor(u / cell));
+  if (c >= Kc) {  // u rounded up to K: the first cell
+    c -= Kc;
+    u -= K;
+  }
+  if (c < 0) {    // u slightly below 0 (see scaled): the last cell
+    c += Kc;
+    u += K;
+  }
+  // a non-finite coordinate must not index outside the grid (its NaN weights
+  // still propagate into the results)
+  if (!(c >= 0 && c < Kc)) {
+    c = 0;
+    u = 0.0;
+  }
+  int b = (c + 1) * cell;
+  if (b >= K) b -= K;
+  base = b;
+  return static_cast<T>(u - static_cast<double>(c) * cell);
+}
+
+// prod_{r != s} (s - r) over the nodes 0..P-1.
+__host__ __device__ constexpr double lagrange_denom(int s, int P) {
+  double d = 1.0;
+  for (int r = 0; r < P; ++r)
+    if (r != s) d *= static_cast<double>(s - r);
+  return d;
+}
+
+// Lagrange basis of the P integer nodes 0..P-1 of one cell (Eq. interp1d with
+// the cell mapped onto them) at xi: w[t] = l_{P-1-t}(xi) with
+// l_s(xi) = prod_{r != s} (xi - r) / (s - r), and dw[t] its derivative in xi,
+// from prefix and suffix products of (xi - r) and their derivatives.
+template <typename T, int P>
+__device__ __forceinline__ void lagrange(T xi, T* w, T* dw) {
+  T pre[P + 1], dpre[P + 1], suf[P + 1], dsuf[P + 1];
+  pre[0] = T(1);
+  dpre[0] = T(0);
+#pragma unroll
+  for (int r = 0; r < P; ++r) {
+    pre[r + 1] = pre[r] * (xi - T(r));
+    dpre[r + 1] = dpre[r] * (xi - T(r)) + pre[r];
+  }
+  suf[P] = T(1);
+  dsuf[P] = T(0);
+#pragma unroll
+  for (int r = P - 1; r >= 0; --r) {
+    suf[r] = suf[r + 1] * (xi - T(r));
+    dsuf[r] = dsuf[r + 1] * (xi - T(r)) + suf[r + 1];
+  }
+#pragma unroll
+  for (int s = 0; s < P; ++s) {
+    const T inv = static_cast<T>(1.0 / lagrange_denom(s, P));
+    w[P - 1 - s] = pre[s] * suf[s + 1] * inv;
+    dw[P - 1 - s] = (dpre[s] * suf[s + 1] + pre[s] * dsuf[s + 1]) * inv;
+  }
+}
+
+// Stencil weights and their derivatives in u for either rule.
+template <typename T, int P>
+__device__ __forceinline__ void stencil_weights(T f, int cell, T* w, T* dw) {
+  if (cell == 0)
+    bspline<T, P>(f, w, dw);
+  else
+    lagrange<T, P>(f, w, dw);
 }
 
 template <typename T>
@@ -123,8 +216,8 @@ __global__ __launch_bounds__(256) void gather_direct(long n, const T* __restrict
   int base[3];
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
-    const T f = scaled(pos[3 * i + j], g.invL[j], g.K[j], base[j]);
-    bspline<T, P>(f, w[j], dw[j]);
+    const T f = stencil_coord(pos[3 * i + j], g.invL[j], g.K[j], g.cell, base[j]);
+    stencil_weights<T, P>(f, g.cell, w[j], dw[j]);
   }
   const int K1 = g.K[0], K2 = g.K[1], K3 = g.K[2];
   int kc[P];
@@ -178,7 +271,7 @@ __device__ __forceinline__ int brick_of_particle(const T* __restrict__ pos, long
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
     int base;
-    (void)scaled(pos[3 * i + j], g.invL[j], g.K[j], base);
+    (void)stencil_coord(pos[3 * i + j], g.invL[j], g.K[j], g.cell, base);
     // edges are 8 unless the axis is shorter (a uniform branch)
     bid = bid * bg.nb[j] + (bg.edge[j] == 8 ? base >> 3 : base / bg.edge[j]);
   }
@@ -484,7 +577,7 @@ __global__ __launch_bounds__(256) void spread_brick(const T* __restrict__ sorted
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
           int base;
-          (void)scaled(sorted[4L * i + j], g.invL[j], g.K[j], base);
+          (void)stencil_coord(sorted[4L * i + j], g.invL[j], g.K[j], g.cell, base);
           bool any = false;
 #pragma unroll
           for (int t = 0; t < P; ++t) {
@@ -515,8 +608,8 @@ __global__ __launch_bounds__(256) void spread_brick(const T* __restrict__ sorted
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
         int base;
-        const T f = scaled(sorted[4 * i + j], g.invL[j], g.K[j], base);
-        bspline<T, P>(f, w3[j], dw);
+        const T f = stencil_coord(sorted[4 * i + j], g.invL[j], g.K[j], g.cell, base);
+        stencil_weights<T, P>(f, g.cell, w3[j], dw);
 #pragma unroll
         for (int t = 0; t < P; ++t) {
           int k = base - t;
@@ -599,8 +692,8 @@ __global__ __launch_bounds__(256) void spread_home(const T* __restrict__ sorted,
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
       int base;
-      const T f = scaled(sorted[4L * i + j], g.invL[j], g.K[j], base);
-      bspline<T, P>(f, w[j], dw);
+      const T f = stencil_coord(sorted[4L * i + j], g.invL[j], g.K[j], g.cell, base);
+      stencil_weights<T, P>(f, g.cell, w[j], dw);
       // the particle was binned by the same floor, so base lies in this
       // brick; the clamp only keeps a corrupted input inside the tile
       l[j] = min(max(base - lo[j] + P - 1, P - 1), H[j] - 1);
@@ -621,6 +714,186 @@ __global__ __launch_bounds__(256) void spread_home(const T* __restrict__ sorted,
   __syncthreads();
   T* out = tiles + static_cast<long>(brick) * ntile;
   for (int e = threadIdx.x; e < ntile; e += blockDim.x) out[e] = static_cast<T>(tile[e]);
+}
+
+// Home-computes spread, pass 1, on the matrix cores (float grids): the tile of
+// a brick is T[a][b][c] = sum_i s_i(a) wy_i(b) wz_i(c), with s_i(a) =
+// q_i wx_i(a) the charge-weighted x weight of particle i at tile plane a (zero
+// off its stencil) and wy_i, wz_i its y and z weights placed at their tile
+// positions.  Plane a is therefore one 16 x 16 rank-n update,
+// T_a = sum_k (s_k(a) wy_k) wz_k^T, taken four particles at a time by
+// v_mfma_f32_16x16x4f32 (A = s(a) wy, B = wz; FP32 accumulation).  The
+// particles of a chunk are ordered by their x base in the brick with a
+// stable, ballot-based counting sort, so that the particles reaching plane a
+// (bases a - P + 1 .. a) form one contiguous range and each plane's k-steps
+// cover only that range.  Wave w accumulates planes w, w + 4, w + 8, w + 12
+// in its MFMA accumulators over every chunk and stores them at the end; the
+// tile values are exact products rounded to FP32 and summed in FP32 in a
+// fixed order.  Needs every tile extent <= 16 (edge + P - 1).
+constexpr int kMfmaChunk = 256;   // particles staged per chunk (one per thread)
+
+__device__ __forceinline__ unsigned long long lanemask_lt() {
+  const unsigned lane = threadIdx.x & 63;
+  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void spread_home_mfma(const float* __restrict__ sorted,
+                                                       const int* __restrict__ offset,
+                                                       float* __restrict__ tiles,
+                                                       int* __restrict__ count, GridGeom g,
+                                                       BinGeom bg) {
+  static_assert(P <= 9, "tile extents must stay within 16 (brick edge 8)");
+  // padded per-particle rows, in sorted slot order: q wx at its x planes
+  // (plane-permuted, see below), wy at its y positions, wz at its z
+  // positions (zero elsewhere)
+  __shared__ __attribute__((aligned(16))) float sx[kMfmaChunk][16];
+  __shared__ __attribute__((aligned(16))) float sy[kMfmaChunk][16];
+  __shared__ __attribute__((aligned(16))) float sz[kMfmaChunk][16];
+  __shared__ int wcount[4][16];   // per wave, particles per x base
+  __shared__ int boff[4][17];     // per wave, first slot of each x base
+  __shared__ int bstart[17];      // first slot of each x base in the chunk
+  const int brick = xcd_order(blockIdx.x, gridDim.x);
+  if (threadIdx.x == 0) count[brick] = 0;  // the scatter has read it: ready for the next binning
+  int own[3], rest = brick;
+  own[2] = rest % bg.nb[2]; rest /= bg.nb[2];
+  own[1] = rest % bg.nb[1];
+  own[0] = rest / bg.nb[1];
+  int lo[3], H[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    lo[j] = own[j] * bg.edge[j];
+    H[j] = bg.edge[j] + P - 1;
+  }
+  const int E0 = bg.edge[0];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int col = lane & 15, kq = lane >> 4;
+  floatx4 acc[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) acc[u] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const int i0 = offset[brick], i1 = offset[brick + 1];
+  for (int c0 = i0; c0 < i1; c0 += kMfmaChunk) {
+    const int n = min(kMfmaChunk, i1 - c0);
+    // this thread's particle: tile bases and weights
+    const int t = threadIdx.x;
+    float w[3][P], dw[P];
+    int l[3] = {0, 0, 0};
+    int bin = -1;
+    float qi = 0.f;
+    if (t < n) {
+      const long i = c0 + t;
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        int base;
+        const float f = stencil_coord(sorted[4L * i + j], g.invL[j], g.K[j], g.cell, base);
+        stencil_weights<float, P>(f, g.cell, w[j], dw);
+        l[j] = min(max(base - lo[j] + P - 1, P - 1), H[j] - 1);
+      }
+      qi = sorted[4L * i + 3];
+      bin = l[0] - (P - 1);
+    }
+    // stable counting sort by x base: ballots give the rank inside the wave
+    int rank = 0;
+    for (int v = 0; v < E0; ++v) {
+      const unsigned long long m = __ballot(bin == v);
+      if (bin == v) rank = __popcll(m & lanemask_lt());
+      if (lane == 0) wcount[wave][v] = __popcll(m);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int acc_s = 0;
+      for (int v = 0; v < E0; ++v) {
+        bstart[v] = acc_s;
+        for (int ww = 0; ww < 4; ++ww) {
+          boff[ww][v] = acc_s;
+          acc_s += wcount[ww][v];
+        }
+      }
+      bstart[E0] = acc_s;
+    }
+    __syncthreads();
+    if (t < n) {
+      const int slot = boff[wave][bin] + rank;
+      float rx[16], ry[16], rz[16];
+#pragma unroll
+      for (int e = 0; e < 16; ++e) { rx[e] = 0.f; ry[e] = 0.f; rz[e] = 0.f; }
+      // tile index l_j - s carries weight w_j[s]; the x row is stored with
+      // plane a at position 4 (a % 4) + a / 4, so that wave w reads the
+      // scalars of its planes w, w + 4, w + 8, w + 12 as one float4
+#pragma unroll
+      for (int e = 0; e < 16; ++e)
+#pragma unroll
+        for (int s = 0; s < P; ++s) {
+          if (e == l[0] - s) rx[4 * (e & 3) + (e >> 2)] = qi * w[0][s];
+          if (e == l[1] - s) ry[e] = w[1][s];
+          if (e == l[2] - s) rz[e] = w[2][s];
+        }
+#pragma unroll
+      for (int e = 0; e < 16; e += 4) {
+        *reinterpret_cast<float4*>(&sx[slot][e]) = make_float4(rx[e], rx[e + 1], rx[e + 2], rx[e + 3]);
+        *reinterpret_cast<float4*>(&sy[slot][e]) = make_float4(ry[e], ry[e + 1], ry[e + 2], ry[e + 3]);
+        *reinterpret_cast<float4*>(&sz[slot][e]) = make_float4(rz[e], rz[e + 1], rz[e + 2], rz[e + 3]);
+      }
+    }
+    __syncthreads();
+    // planes a = wave + 4u; the particles reaching plane a have x base in
+    // [a - P + 1, a]: slots [bstart[max(0, a - P + 1)], bstart[min(a, E0 - 1) + 1])
+    int ps[4], pe[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int a = wave + 4 * u;
+      ps[u] = 0;
+      pe[u] = 0;
+      if (a < H[0]) {
+        ps[u] = bstart[max(0, a - P + 1)];
+        pe[u] = bstart[min(a, E0 - 1) + 1];
+      }
+    }
+    const int ks = min(min(ps[0], ps[1]), min(ps[2], ps[3]));
+    const int ke = max(max(pe[0], pe[1]), max(pe[2], pe[3]));
+    // operands of particle k for this lane: row b = col of A (y weight),
+    // column c = col of B (z weight), and the wave's four plane scalars
+    float yb = 0.f, zc = 0.f;
+    float4 s4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (ks + kq < min(ke, n)) {
+      yb = sy[ks + kq][col];
+      zc = sz[ks + kq][col];
+      s4 = *reinterpret_cast<const float4*>(&sx[ks + kq][4 * wave]);
+    }
+    for (int k0 = ks; k0 < ke; k0 += 4) {
+      // the next step's operands are read while this step's products run
+      float ybn = 0.f, zcn = 0.f;
+      float4 s4n = make_float4(0.f, 0.f, 0.f, 0.f);
+      const int kn = k0 + 4 + kq;
+      if (k0 + 4 < ke && kn < n) {
+        ybn = sy[kn][col];
+        zcn = sz[kn][col];
+        s4n = *reinterpret_cast<const float4*>(&sx[kn][4 * wave]);
+      }
+      const float sv[4] = {s4.x, s4.y, s4.z, s4.w};
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (k0 + 4 > ps[u] && k0 < pe[u])        // wave-uniform
+          acc[u] = mfma_k4(sv[u] * yb, zc, acc[u]);
+      yb = ybn;
+      zc = zcn;
+      s4 = s4n;
+    }
+    __syncthreads();   // the rows are rewritten by the next chunk
+  }
+  // D[b][c] with b = 4 kq + r, c = col in register r
+  const int ntile = H[0] * H[1] * H[2];
+  float* out = tiles + static_cast<long>(brick) * ntile;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int a = wave + 4 * u;
+    if (a >= H[0] || col >= H[2]) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int b = 4 * kq + r;
+      if (b < H[1]) out[(a * H[1] + b) * H[2] + col] = acc[u][r];
+    }
+  }
 }
 
 // Pass 2: one workgroup per grid brick sums, for each of its points and in a
@@ -726,8 +999,8 @@ __global__ __launch_bounds__(256) void gather_sorted(long n, const T* __restrict
     int base[3];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      const T f = scaled(sorted[4 * s + j], g.invL[j], g.K[j], base[j]);
-      bspline<T, P>(f, w[j], dw[j]);
+      const T f = stencil_coord(sorted[4 * s + j], g.invL[j], g.K[j], g.cell, base[j]);
+      stencil_weights<T, P>(f, g.cell, w[j], dw[j]);
     }
     const int K1 = g.K[0], K2 = g.K[1], K3 = g.K[2];
     int kc[P];
@@ -817,8 +1090,8 @@ __global__ __launch_bounds__(256) void gather_sorted_planes(long n, const T* __r
     int base[3];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-      const T f = scaled(sorted[4 * s + j], g.invL[j], g.K[j], base[j]);
-      bspline<T, P>(f, w[j], dw[j]);
+      const T f = stencil_coord(sorted[4 * s + j], g.invL[j], g.K[j], g.cell, base[j]);
+      stencil_weights<T, P>(f, g.cell, w[j], dw[j]);
     }
     qi = sorted[4 * s + 3];
     const int K1 = g.K[0], K2 = g.K[1], K3 = g.K[2];
@@ -934,8 +1207,8 @@ __global__ __launch_bounds__(256) void gather_brick(const T* __restrict__ sorted
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
       int base;
-      const T f = scaled(sorted[4L * s + j], g.invL[j], g.K[j], base);
-      bspline<T, P>(f, w[j], dw[j]);
+      const T f = stencil_coord(sorted[4L * s + j], g.invL[j], g.K[j], g.cell, base);
+      stencil_weights<T, P>(f, g.cell, w[j], dw[j]);
       // binned by the same floor: base lies in this brick (the clamp only
       // keeps a corrupted input inside the tile)
       l[j] = min(max(base - lo[j] + P - 1, P - 1), H[j] - 1);
@@ -1015,8 +1288,8 @@ __global__ __launch_bounds__(256) void gather_backward(
   int base[3];
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
-    const T f = scaled(sorted[4 * s + j], g.invL[j], g.K[j], base[j]);
-    bspline<T, P>(f, w[j], dw[j]);
+    const T f = stencil_coord(sorted[4 * s + j], g.invL[j], g.K[j], g.cell, base[j]);
+    stencil_weights<T, P>(f, g.cell, w[j], dw[j]);
   }
   const int K1 = g.K[0], K2 = g.K[1], K3 = g.K[2];
   int kc[P];
@@ -1258,9 +1531,15 @@ hipError_t spread_brick_p(const GridGeom& g, const Bins& b, const void* src, voi
     return hipGetLastError();
   }
   const int ntile = (b.geom.edge[0] + P - 1) * (b.geom.edge[1] + P - 1) * (b.geom.edge[2] + P - 1);
-  hipLaunchKernelGGL((spread_home<T, P>), dim3(b.geom.nbricks), dim3(kHomeThreads),
-                     sizeof(double) * ntile, st, srt, b.offset, static_cast<T*>(b.tiles), b.count,
-                     g, b.geom);
+  if constexpr (sizeof(T) == 4 && P <= 9) {
+    // float grids: the matrix-core tile spread (every brick edge <= 8)
+    hipLaunchKernelGGL((spread_home_mfma<P>), dim3(b.geom.nbricks), dim3(256), 0, st, srt,
+                       b.offset, static_cast<float*>(b.tiles), b.count, g, b.geom);
+  } else {
+    hipLaunchKernelGGL((spread_home<T, P>), dim3(b.geom.nbricks), dim3(kHomeThreads),
+                       sizeof(double) * ntile, st, srt, b.offset, static_cast<T*>(b.tiles),
+                       b.count, g, b.geom);
+  }
   hipLaunchKernelGGL((spread_combine<T, P>), dim3(b.geom.nbricks), dim3(512), 0, st,
                      static_cast<const T*>(b.tiles), b.nbr, static_cast<T*>(grid), part2, g,
                      b.geom);

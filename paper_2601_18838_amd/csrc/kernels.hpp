@@ -105,6 +105,10 @@ struct GridGeom {
   double L[3];
   double invL[3];  // 1 / L
   int p;
+  // interpolation: 0 = order-p cardinal B-splines; c > 0 = per-cell Lagrange
+  // interpolation on cells of c = p - 1 grid intervals (p nodes per axis,
+  // end points shared with the neighbouring cells)
+  int cell = 0;
 };
 
 // Record length of the per-axis neighbour table: {count, up to 4 bricks}.

@@ -77,8 +77,8 @@ std::pair<double, double> best_rule_h(const WeightedArgs& wa, int N) {
 }  // namespace
 
 bool build_factors_quadrature(const double box[3], const int K[3], int p, double beta,
-                              int rank, double tol, double h, FactorSet* out,
-                              std::string* err) {
+                              int rank, double tol, double h, const KernelSpec& ks,
+                              FactorSet* out, std::string* err) {
   const double V = box[0] * box[1] * box[2];
   const double s = std::pow(std::max(box[0], std::max(box[1], box[2])), 2);
   // folded half domain: h_j = |m'_j| in [0, K_j / 2], multiplicity 1 or 2
@@ -86,12 +86,12 @@ bool build_factors_quadrature(const double box[3], const int K[3], int p, double
   std::vector<double> bm[3], mh2[3], mult[3];
   for (int j = 0; j < 3; ++j) {
     H[j] = K[j] / 2 + 1;
-    const std::vector<double> full = bspline_moduli(K[j], p);
+    const std::vector<double> full = ks.lagrange ? std::vector<double>() : bspline_moduli(K[j], p);
     bm[j].resize(H[j]);
     mh2[j].resize(H[j]);
     mult[j].resize(H[j]);
     for (int i = 0; i < H[j]; ++i) {
-      bm[j][i] = full[i];
+      bm[j][i] = ks.axis_factor(full, i);
       const double mh = i / box[j];
       mh2[j][i] = mh * mh;
       mult[j][i] = (i == 0 || (K[j] % 2 == 0 && i == K[j] / 2)) ? 1.0 : 2.0;

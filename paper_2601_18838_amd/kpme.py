@@ -34,21 +34,24 @@ class PlanInfo(ctypes.Structure):
                 ("trunc_err", ctypes.c_double), ("zero_mode", ctypes.c_double),
                 ("workspace_bytes", ctypes.c_size_t), ("skp_method", ctypes.c_int),
                 ("quad_N", ctypes.c_int), ("quad_h", ctypes.c_double),
-                ("sym_err", ctypes.c_double)]
+                ("sym_err", ctypes.c_double), ("interpolation", ctypes.c_int),
+                ("mode_cutoff", ctypes.c_int), ("skp_form", ctypes.c_int)]
 
 
 class PlanOptions(ctypes.Structure):
     _fields_ = [("skp_method", ctypes.c_int), ("quad_h", ctypes.c_double),
-                ("interpolation", ctypes.c_int), ("mode_cutoff", ctypes.c_int)]
+                ("interpolation", ctypes.c_int), ("mode_cutoff", ctypes.c_int),
+                ("skp_form", ctypes.c_int)]
 
 
 METHODS = {"nested_svd": 0, "sinc": 1}
-INTERPOLATIONS = {"bspline": 0}
+INTERPOLATIONS = {"bspline": 0, "lagrange": 1}
+FORMS = {"circulant": 0, "rect": 1}
 
 
-def _options(method, quad_h, interpolation="bspline", mode_cutoff=0):
+def _options(method, quad_h, interpolation="bspline", mode_cutoff=0, form="circulant"):
     return PlanOptions(METHODS[method], float(quad_h), INTERPOLATIONS[interpolation],
-                       int(mode_cutoff))
+                       int(mode_cutoff), FORMS[form])
 
 
 _lib = None
@@ -129,7 +132,7 @@ def device_count():
 
 
 def factors_compute(box, grid, order, beta, rank=0, tol=1e-6, max_terms=4096,
-                    method="nested_svd", quad_h=0.0):
+                    method="nested_svd", quad_h=0.0, interpolation="bspline", mode_cutoff=0):
     """Host FP64 factor construction (no device needed): dict of numpy arrays."""
     L = lib()
     K = [int(k) for k in grid]
@@ -138,7 +141,7 @@ def factors_compute(box, grid, order, beta, rank=0, tol=1e-6, max_terms=4096,
     v = [np.zeros(max_terms * K[j]) for j in range(3)]
     grp = np.zeros(max_terms, np.int32)
     info = np.zeros(6)
-    opts = _options(method, quad_h)
+    opts = _options(method, quad_h, interpolation, mode_cutoff)
     dp = lambda a: a.ctypes.data_as(_DP)
     _check(L.kpme_factors_compute_ex(_dbl3(box), _int3(K), int(order), float(beta), int(rank),
                                      float(tol), ctypes.byref(opts), max_terms, ctypes.byref(n),
@@ -160,7 +163,8 @@ class Plan:
     """A device plan: factors and workspace for one box/grid/order/beta/rank."""
 
     def __init__(self, box, grid, order, beta, rank=0, tol=1e-6, precision="fp32",
-                 max_particles=1, device=0, method="nested_svd", quad_h=0.0):
+                 max_particles=1, device=0, method="nested_svd", quad_h=0.0,
+                 interpolation="bspline", mode_cutoff=0, form="circulant"):
         import torch
         self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         self.dtype = torch.float64 if self.precision == FP64 else torch.float32
@@ -170,7 +174,7 @@ class Plan:
         self.beta = float(beta)
         self.device = torch.device("cuda", device)
         self._h = _P()
-        opts = _options(method, quad_h)
+        opts = _options(method, quad_h, interpolation, mode_cutoff, form)
         _check(lib().kpme_plan_create_ex(ctypes.byref(self._h), _dbl3(box), _int3(grid),
                                          self.order, self.beta, int(rank), float(tol),
                                          self.precision, int(max_particles), int(device),

@@ -114,6 +114,13 @@ WATER_200K_NONCUBIC = Workload("water_n200001_g80x100x120_p4", (120.0, 150.0, 18
                                (80, 100, 120), 4, 0.34, tol=1e-6, kind="water",
                                n=200001, seed=4)
 
+# The paper's own discretisation (per-cell Lagrange interpolation with the
+# mode-truncated kernel): 10 cells of 8 nodes per axis (70 grid points),
+# |m_j| <= 10, a 20^3 box at beta = 0.35 (the Gaussian is e^-20 at m = 10).
+LAGRANGE_M10 = Workload("lagrange_pm1_n100000_c10_L8_m10", (20.0, 20.0, 20.0), (70, 70, 70), 8,
+                        0.35, tol=1e-6, kind="pm1", n=100000, seed=6,
+                        extra={"interpolation": "lagrange", "mode_cutoff": 10, "cells": 10})
+
 BATCH_GRIDS = [(32, 32, 32), (48, 48, 48), (64, 64, 64), (64, 64, 96),
                (80, 96, 112), (96, 96, 96), (96, 128, 160)]
 

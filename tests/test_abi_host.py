@@ -175,3 +175,69 @@ def test_sinc_quadrature_rejects_an_even_rank():
     with pytest.raises(kpme.KpmeError) as e:
         kpme.factors_compute((20, 20, 20), (16, 16, 16), 4, 0.35, rank=8, method="sinc")
     assert e.value.status == 1
+
+
+@pytest.mark.parametrize("box,Kc,L,M,beta,rank", [
+    ((10.0, 11.0, 12.0), (4, 4, 4), 6, 5, 0.6, None),
+    ((20.0, 20.0, 20.0), (5, 5, 5), 8, 12, 0.35, 40),
+    ((18.0, 21.0, 24.0), (6, 7, 8), 4, 8, 0.5, 30),
+])
+def test_lagrange_factors_match_the_oracle(box, Kc, L, M, beta, rank):
+    """Library factors of the mode-truncated kernel on the Lagrange grid
+    (K_j = K_c,j (L - 1) points, |m_j| <= M) against the oracle's nested SVD
+    of the same symbol: the kept operator, the truncation and the correction
+    constant."""
+    from oracle import lagrange as lg
+    orc = lg.Plan(box, Kc, L, M, beta, rank=rank)
+    grid = orc.K
+    lib = kpme.factors_compute(box, grid, L, beta, rank=rank or 10 ** 6,
+                               interpolation="lagrange", mode_cutoff=M)
+    th = orc.theta
+    scale = np.abs(th).max()
+    rec_lib = sum(lib["omega"][r] * _rank1(lib["vec"], r) for r in range(len(lib["omega"])))
+    rec_orc = skp.reconstruct(orc.terms, th.shape)
+    assert len(lib["omega"]) == orc.rank
+    assert np.abs(rec_lib - rec_orc).max() < 1e-11 * scale
+    assert abs(lib["theta_norm"] - np.linalg.norm(th)) < 1e-12 * np.linalg.norm(th)
+    assert abs(lib["trunc_err"] - orc.trunc_err) < 1e-10 * np.linalg.norm(th) + 1e-6 * orc.trunc_err
+    assert abs(lib["zero_mode"] - orc.c0) < 1e-11 * scale
+
+
+def test_lagrange_sinc_quadrature_terms_vanish_beyond_the_cutoff():
+    box, grid, L, M, beta = (10.0, 11.0, 12.0), (20, 20, 20), 6, 5, 0.6
+    lib = kpme.factors_compute(box, grid, L, beta, rank=0, tol=1e-6, method="sinc",
+                               interpolation="lagrange", mode_cutoff=M)
+    from oracle import spme
+    for j in range(3):
+        far = np.abs(spme.signed_modes(grid[j])) > M
+        assert np.all(lib["vec"][j][:, far] == 0.0)
+    from oracle import lagrange as lg
+    th = lg.alpha_hat(box, grid, M, beta)
+    rec = sum(lib["omega"][r] * _rank1(lib["vec"], r) for r in range(len(lib["omega"])))
+    rec[0, 0, 0] = 0.0
+    assert np.abs(rec - th).max() <= 1e-6 * th.max() * (1 + 1e-9)
+
+
+@pytest.mark.parametrize("grid,M,code", [((20, 21, 20), 5, 1), ((20, 20, 20), 10, 1),
+                                         ((20, 20, 20), 0, 1)])
+def test_lagrange_plan_options_are_validated(grid, M, code):
+    h = ctypes.c_void_p()
+    opts = kpme._options("nested_svd", 0.0, "lagrange", M)
+    st = kpme.lib().kpme_plan_create_ex(ctypes.byref(h), kpme._dbl3((10, 11, 12)),
+                                        kpme._int3(grid), 6, 0.6, 8, 0.0, 1, 100, 0,
+                                        ctypes.byref(opts))
+    assert st == code and h.value is None
+    opts = kpme._options("nested_svd", 0.0, "bspline", 3)
+    st = kpme.lib().kpme_plan_create_ex(ctypes.byref(h), kpme._dbl3((10, 11, 12)),
+                                        kpme._int3((20, 20, 20)), 6, 0.6, 8, 0.0, 1, 100, 0,
+                                        ctypes.byref(opts))
+    assert st == 1
+
+
+def test_rect_form_is_refused_for_split_precisions_before_any_device_work():
+    h = ctypes.c_void_p()
+    opts = kpme._options("nested_svd", 0.0, "bspline", 0, "rect")
+    st = kpme.lib().kpme_plan_create_ex(ctypes.byref(h), kpme._dbl3((20, 20, 20)),
+                                        kpme._int3((16, 16, 16)), 4, 0.35, 8, 0.0, 3, 100, 0,
+                                        ctypes.byref(opts))
+    assert st == 2 and h.value is None

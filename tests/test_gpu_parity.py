@@ -95,6 +95,15 @@ CASES = {
     # the largest grid of the batched workload: 96 x 128 x 160, order 6, more
     # than 2048 bricks (the grid sum goes through its own reduction)
     "batch_96x128x160": ((96.0, 128.0, 160.0), (96, 128, 160), 6, 0.34, 7, 31764, "pm1", 19),
+    # the same grid with the particles of system 2 of the 64-system batch
+    # (one of them lies exactly on the box face x = L)
+    "batch64_system2": ((96.0, 128.0, 160.0), (96, 128, 160), 6, 0.34, 7, 31764, "batch", 2),
+    # particles exactly on the box faces x_j = L_j and on grid planes, for
+    # L_j / K_j with and without an exact binary reciprocal (regression: the
+    # fused multiply-subtract of the coordinate scaling once put a particle on
+    # a face one grid point off)
+    "box_faces_p4": ((96.0, 20.0, 24.0), (96, 25, 30), 4, 0.5, 12, 600, "faces", 20),
+    "box_faces_p6": ((21.0, 26.0, 31.0), (20, 25, 30), 6, 0.6, 12, 600, "faces", 21),
 }
 
 
@@ -102,6 +111,18 @@ def make(case):
     box, grid, p, beta, rank, n, kind, seed = CASES[case]
     if kind == "pm1":
         pos, q = systems.uniform_pm1(n, box, seed)
+    elif kind == "batch":
+        wl, pos, q = systems.batch_systems(count=seed + 1)[seed]
+        assert wl.n == n and tuple(wl.grid) == tuple(grid) and wl.rank == rank
+    elif kind == "faces":
+        pos, q = systems.uniform_pm1(n, box, seed)
+        pos = pos.copy()
+        rng = np.random.default_rng(seed + 1000)
+        for j in range(3):
+            pos[rng.choice(n, 40, replace=False), j] = box[j]              # on the face
+            k = rng.integers(0, grid[j], size=40)
+            pos[rng.choice(n, 40, replace=False), j] = k * box[j] / grid[j]  # on grid planes
+        pos = pos.astype(np.float32).astype(np.float64)
     else:
         pos, q = systems.water(n // 3, box, seed)
     return box, grid, p, beta, rank, pos, q
