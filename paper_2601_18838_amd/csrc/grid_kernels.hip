@@ -726,11 +726,13 @@ __global__ __launch_bounds__(256) void spread_home(const T* __restrict__ sorted,
 // particles of a chunk are ordered by their x base in the brick with a
 // stable, ballot-based counting sort, so that the particles reaching plane a
 // (bases a - P + 1 .. a) form one contiguous range and each plane's k-steps
-// cover only that range.  Wave w accumulates planes w, w + 4, w + 8, w + 12
-// in its MFMA accumulators over every chunk and stores them at the end; the
+// cover only that range.  Eight waves: the first four stage the chunk's
+// particles, and wave w accumulates planes w and w + 8 in its MFMA
+// accumulators over every chunk and stores them at the end; the
 // tile values are exact products rounded to FP32 and summed in FP32 in a
 // fixed order.  Needs every tile extent <= 16 (edge + P - 1).
-constexpr int kMfmaChunk = 256;   // particles staged per chunk (one per thread)
+constexpr int kMfmaChunk = 256;   // particles staged per chunk (one per thread of waves 0-3)
+constexpr int kMfmaWaves = 8;     // waves per workgroup; wave w owns planes w, w + 8
 
 __device__ __forceinline__ unsigned long long lanemask_lt() {
   const unsigned lane = threadIdx.x & 63;
@@ -738,15 +740,15 @@ __device__ __forceinline__ unsigned long long lanemask_lt() {
 }
 
 template <int P>
-__global__ __launch_bounds__(256) void spread_home_mfma(const float* __restrict__ sorted,
+__global__ __launch_bounds__(64 * kMfmaWaves) void spread_home_mfma(const float* __restrict__ sorted,
                                                        const int* __restrict__ offset,
                                                        float* __restrict__ tiles,
                                                        int* __restrict__ count, GridGeom g,
                                                        BinGeom bg) {
   static_assert(P <= 9, "tile extents must stay within 16 (brick edge 8)");
-  // padded per-particle rows, in sorted slot order: q wx at its x planes
-  // (plane-permuted, see below), wy at its y positions, wz at its z
-  // positions (zero elsewhere)
+  static_assert(2 * kMfmaWaves >= 16, "two planes per wave cover a 16-plane tile");
+  // padded per-particle rows, in sorted slot order: q wx at its x planes,
+  // wy at its y positions, wz at its z positions (zero elsewhere)
   __shared__ __attribute__((aligned(16))) float sx[kMfmaChunk][16];
   __shared__ __attribute__((aligned(16))) float sy[kMfmaChunk][16];
   __shared__ __attribute__((aligned(16))) float sz[kMfmaChunk][16];
@@ -767,10 +769,11 @@ __global__ __launch_bounds__(256) void spread_home_mfma(const float* __restrict_
   }
   const int E0 = bg.edge[0];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave_u = __builtin_amdgcn_readfirstlane(wave);
   const int col = lane & 15, kq = lane >> 4;
-  floatx4 acc[4];
+  floatx4 acc[2];
 #pragma unroll
-  for (int u = 0; u < 4; ++u) acc[u] = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int u = 0; u < 2; ++u) acc[u] = floatx4{0.f, 0.f, 0.f, 0.f};
   const int i0 = offset[brick], i1 = offset[brick + 1];
   for (int c0 = i0; c0 < i1; c0 += kMfmaChunk) {
     const int n = min(kMfmaChunk, i1 - c0);
@@ -781,23 +784,27 @@ __global__ __launch_bounds__(256) void spread_home_mfma(const float* __restrict_
     int bin = -1;
     float qi = 0.f;
     if (t < n) {
-      const long i = c0 + t;
+      // (x, y, z, q) of one particle in one 16-byte load
+      const float4 pq = reinterpret_cast<const float4*>(sorted)[c0 + t];
+      const float xyz[3] = {pq.x, pq.y, pq.z};
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
         int base;
-        const float f = stencil_coord(sorted[4L * i + j], g.invL[j], g.K[j], g.cell, base);
+        const float f = stencil_coord(xyz[j], g.invL[j], g.K[j], g.cell, base);
         stencil_weights<float, P>(f, g.cell, w[j], dw);
         l[j] = min(max(base - lo[j] + P - 1, P - 1), H[j] - 1);
       }
-      qi = sorted[4L * i + 3];
+      qi = pq.w;
       bin = l[0] - (P - 1);
     }
     // stable counting sort by x base: ballots give the rank inside the wave
     int rank = 0;
-    for (int v = 0; v < E0; ++v) {
-      const unsigned long long m = __ballot(bin == v);
-      if (bin == v) rank = __popcll(m & lanemask_lt());
-      if (lane == 0) wcount[wave][v] = __popcll(m);
+    if (wave_u < 4) {
+      for (int v = 0; v < E0; ++v) {
+        const unsigned long long m = __ballot(bin == v);
+        if (bin == v) rank = __popcll(m & lanemask_lt());
+        if (lane == 0) wcount[wave][v] = __popcll(m);
+      }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -814,70 +821,52 @@ __global__ __launch_bounds__(256) void spread_home_mfma(const float* __restrict_
     __syncthreads();
     if (t < n) {
       const int slot = boff[wave][bin] + rank;
-      float rx[16], ry[16], rz[16];
-#pragma unroll
-      for (int e = 0; e < 16; ++e) { rx[e] = 0.f; ry[e] = 0.f; rz[e] = 0.f; }
-      // tile index l_j - s carries weight w_j[s]; the x row is stored with
-      // plane a at position 4 (a % 4) + a / 4, so that wave w reads the
-      // scalars of its planes w, w + 4, w + 8, w + 12 as one float4
-#pragma unroll
-      for (int e = 0; e < 16; ++e)
-#pragma unroll
-        for (int s = 0; s < P; ++s) {
-          if (e == l[0] - s) rx[4 * (e & 3) + (e >> 2)] = qi * w[0][s];
-          if (e == l[1] - s) ry[e] = w[1][s];
-          if (e == l[2] - s) rz[e] = w[2][s];
-        }
+      // the rows are cleared, then the P weights of each axis are written
+      // at their tile positions (one thread's LDS writes land in order):
+      // tile index l_j - s carries weight w_j[s]
+      const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
       for (int e = 0; e < 16; e += 4) {
-        *reinterpret_cast<float4*>(&sx[slot][e]) = make_float4(rx[e], rx[e + 1], rx[e + 2], rx[e + 3]);
-        *reinterpret_cast<float4*>(&sy[slot][e]) = make_float4(ry[e], ry[e + 1], ry[e + 2], ry[e + 3]);
-        *reinterpret_cast<float4*>(&sz[slot][e]) = make_float4(rz[e], rz[e + 1], rz[e + 2], rz[e + 3]);
+        *reinterpret_cast<float4*>(&sx[slot][e]) = z4;
+        *reinterpret_cast<float4*>(&sy[slot][e]) = z4;
+        *reinterpret_cast<float4*>(&sz[slot][e]) = z4;
+      }
+#pragma unroll
+      for (int s = 0; s < P; ++s) {
+        sx[slot][l[0] - s] = qi * w[0][s];
+        sy[slot][l[1] - s] = w[1][s];
+        sz[slot][l[2] - s] = w[2][s];
       }
     }
     __syncthreads();
-    // planes a = wave + 4u; the particles reaching plane a have x base in
-    // [a - P + 1, a]: slots [bstart[max(0, a - P + 1)], bstart[min(a, E0 - 1) + 1])
-    int ps[4], pe[4];
+    // planes a = wave + 8u; the particles reaching plane a have x base in
+    // [a - P + 1, a]: slots [bstart[max(0, a - P + 1)], bstart[min(a, E0 - 1) + 1]).
+    // The bounds are wave-uniform (read into scalar registers), so each
+    // plane is one straight loop of unconditional products over its range;
+    // the lanes of a step past the range contribute zeros.
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int a = wave + 4 * u;
-      ps[u] = 0;
-      pe[u] = 0;
-      if (a < H[0]) {
-        ps[u] = bstart[max(0, a - P + 1)];
-        pe[u] = bstart[min(a, E0 - 1) + 1];
+    for (int u = 0; u < 2; ++u) {
+      const int a = wave_u + kMfmaWaves * u;
+      if (a >= H[0]) break;
+      const int ps = __builtin_amdgcn_readfirstlane(bstart[max(0, a - P + 1)]);
+      const int pe = __builtin_amdgcn_readfirstlane(bstart[min(a, E0 - 1) + 1]);
+      // operands of particle k for this lane: A[b][k] = s_k(a) wy_k(b) with
+      // b = col, B[k][c] = wz_k(c) with c = col; the next step's operands
+      // are read while this step's product runs
+      // (slots are clamped into the array; a slot at or past pe, whose row
+      // may be stale or uninitialised, is replaced by zeros)
+      int k = min(ps + kq, kMfmaChunk - 1);
+      float yb = sx[k][a] * sy[k][col], zc = sz[k][col];
+      if (ps + kq >= pe) yb = zc = 0.f;
+      for (int k0 = ps; k0 < pe; k0 += 4) {
+        const int kn = k0 + 4 + kq;
+        k = min(kn, kMfmaChunk - 1);
+        const float xn = sx[k][a], yn = sy[k][col], zn = sz[k][col];
+        acc[u] = mfma_k4(yb, zc, acc[u]);
+        const bool in = kn < pe;
+        yb = in ? xn * yn : 0.f;
+        zc = in ? zn : 0.f;
       }
-    }
-    const int ks = min(min(ps[0], ps[1]), min(ps[2], ps[3]));
-    const int ke = max(max(pe[0], pe[1]), max(pe[2], pe[3]));
-    // operands of particle k for this lane: row b = col of A (y weight),
-    // column c = col of B (z weight), and the wave's four plane scalars
-    float yb = 0.f, zc = 0.f;
-    float4 s4 = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (ks + kq < min(ke, n)) {
-      yb = sy[ks + kq][col];
-      zc = sz[ks + kq][col];
-      s4 = *reinterpret_cast<const float4*>(&sx[ks + kq][4 * wave]);
-    }
-    for (int k0 = ks; k0 < ke; k0 += 4) {
-      // the next step's operands are read while this step's products run
-      float ybn = 0.f, zcn = 0.f;
-      float4 s4n = make_float4(0.f, 0.f, 0.f, 0.f);
-      const int kn = k0 + 4 + kq;
-      if (k0 + 4 < ke && kn < n) {
-        ybn = sy[kn][col];
-        zcn = sz[kn][col];
-        s4n = *reinterpret_cast<const float4*>(&sx[kn][4 * wave]);
-      }
-      const float sv[4] = {s4.x, s4.y, s4.z, s4.w};
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (k0 + 4 > ps[u] && k0 < pe[u])        // wave-uniform
-          acc[u] = mfma_k4(sv[u] * yb, zc, acc[u]);
-      yb = ybn;
-      zc = zcn;
-      s4 = s4n;
     }
     __syncthreads();   // the rows are rewritten by the next chunk
   }
@@ -885,8 +874,8 @@ __global__ __launch_bounds__(256) void spread_home_mfma(const float* __restrict_
   const int ntile = H[0] * H[1] * H[2];
   float* out = tiles + static_cast<long>(brick) * ntile;
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int a = wave + 4 * u;
+  for (int u = 0; u < 2; ++u) {
+    const int a = wave + kMfmaWaves * u;
     if (a >= H[0] || col >= H[2]) continue;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -941,26 +930,58 @@ __global__ __launch_bounds__(512) void spread_combine(const T* __restrict__ tile
   const int ntile = H[0] * H[1] * H[2];
   double s = 0.0, m = 0.0;
   const int npts = ext[0] * ext[1] * ext[2];
+  // two home bricks per axis and tiles no longer than the axis (every tile
+  // holds at most one image of a point): the eight tile values of a point
+  // are loaded together, then added in the order of the general loop below
+  const bool two = cnt[0] == 2 && cnt[1] == 2 && cnt[2] == 2 && g.K[0] >= H[0] &&
+                   g.K[1] >= H[1] && g.K[2] >= H[2];
   for (int e = threadIdx.x; e < npts; e += blockDim.x) {
     const int x2 = e % ext[2], x1 = (e / ext[2]) % ext[1], x0 = e / (ext[1] * ext[2]);
     double acc = 0.0;
-    for (int a = 0; a < cnt[0]; ++a) {
-      int l0 = x0 + dlt[0][a];
-      if (l0 >= g.K[0]) l0 -= g.K[0];
-      for (; l0 < H[0]; l0 += g.K[0])
-        for (int b = 0; b < cnt[1]; ++b) {
-          int l1 = x1 + dlt[1][b];
-          if (l1 >= g.K[1]) l1 -= g.K[1];
-          for (; l1 < H[1]; l1 += g.K[1])
-            for (int c = 0; c < cnt[2]; ++c) {
-              int l2 = x2 + dlt[2][c];
-              if (l2 >= g.K[2]) l2 -= g.K[2];
-              const T* t = tiles + static_cast<long>((hid[0][a] * bg.nb[1] + hid[1][b]) * bg.nb[2] +
-                                                     hid[2][c]) * ntile +
-                           (l0 * H[1] + l1) * H[2];
-              for (; l2 < H[2]; l2 += g.K[2]) acc += static_cast<double>(t[l2]);
-            }
+    if (two) {
+      int l[3][2];
+      const int x[3] = {x0, x1, x2};
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          int v = x[j] + dlt[j][h];
+          if (v >= g.K[j]) v -= g.K[j];
+          l[j][h] = v;   // in this tile when < H[j]
         }
+      T v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int a = q >> 2, b = (q >> 1) & 1, c = q & 1;
+        const bool in = l[0][a] < H[0] && l[1][b] < H[1] && l[2][c] < H[2];
+        const long at = static_cast<long>((hid[0][a] * bg.nb[1] + hid[1][b]) * bg.nb[2] + hid[2][c]) *
+                            ntile + (l[0][a] * H[1] + l[1][b]) * H[2] + l[2][c];
+        v[q] = in ? tiles[at] : T(0);
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int a = q >> 2, b = (q >> 1) & 1, c = q & 1;
+        if (l[0][a] < H[0] && l[1][b] < H[1] && l[2][c] < H[2]) acc += static_cast<double>(v[q]);
+      }
+    } else {
+      for (int a = 0; a < cnt[0]; ++a) {
+        int l0 = x0 + dlt[0][a];
+        if (l0 >= g.K[0]) l0 -= g.K[0];
+        for (; l0 < H[0]; l0 += g.K[0])
+          for (int b = 0; b < cnt[1]; ++b) {
+            int l1 = x1 + dlt[1][b];
+            if (l1 >= g.K[1]) l1 -= g.K[1];
+            for (; l1 < H[1]; l1 += g.K[1])
+              for (int c = 0; c < cnt[2]; ++c) {
+                int l2 = x2 + dlt[2][c];
+                if (l2 >= g.K[2]) l2 -= g.K[2];
+                const T* t = tiles + static_cast<long>((hid[0][a] * bg.nb[1] + hid[1][b]) * bg.nb[2] +
+                                                       hid[2][c]) * ntile +
+                             (l0 * H[1] + l1) * H[2];
+                for (; l2 < H[2]; l2 += g.K[2]) acc += static_cast<double>(t[l2]);
+              }
+          }
+      }
     }
     const T v = static_cast<T>(acc);
     grid[(static_cast<long>(lo[0] + x0) * g.K[1] + lo[1] + x1) * g.K[2] + lo[2] + x2] = v;
@@ -1152,21 +1173,41 @@ __global__ __launch_bounds__(256) void gather_sorted_planes(long n, const T* __r
   }
 }
 
+// The binned record (x, y, z, q) of slot s in one 16-byte load (float) or two
+// (double).
+__device__ __forceinline__ void load_record(const float* sorted, long s, float* r) {
+  const float4 v = reinterpret_cast<const float4*>(sorted)[s];
+  r[0] = v.x;
+  r[1] = v.y;
+  r[2] = v.z;
+  r[3] = v.w;
+}
+__device__ __forceinline__ void load_record(const double* sorted, long s, double* r) {
+  const double2 a = reinterpret_cast<const double2*>(sorted)[2 * s];
+  const double2 b = reinterpret_cast<const double2*>(sorted)[2 * s + 1];
+  r[0] = a.x;
+  r[1] = a.y;
+  r[2] = b.x;
+  r[3] = b.y;
+}
+
 // Gather by brick: one workgroup per grid brick stages in LDS the potential
 // values that the stencils of the particles binned in it read -- the brick
 // and the P - 1 planes below it on each axis, H_j = edge_j + P - 1 points,
-// wrapped periodically -- then interpolates those particles from LDS (every
-// stencil point is inside the tile: no masking).  Results go back to the
-// caller's order through perm.  With an energy job, one extra last
-// workgroup runs it.
+// wrapped periodically -- then interpolates those particles from LDS, one
+// particle per thread (every stencil point is inside the tile: no masking).
+// Results go back to the caller's order through perm.  With an energy job,
+// one extra last workgroup runs it.
+constexpr int kGatherThreads = 256;
+
 template <typename T, int P>
-__global__ __launch_bounds__(256) void gather_brick(const T* __restrict__ sorted,
-                                                    const int* __restrict__ offset,
-                                                    const int* __restrict__ perm,
-                                                    const T* __restrict__ grid,
-                                                    T* __restrict__ pot, T* __restrict__ force,
-                                                    EnergyJob ej, GridGeom g,
-                                                    BinGeom bg) {
+__global__ __launch_bounds__(kGatherThreads) void gather_brick(const T* __restrict__ sorted,
+                                                              const int* __restrict__ offset,
+                                                              const int* __restrict__ perm,
+                                                              const T* __restrict__ grid,
+                                                              T* __restrict__ pot,
+                                                              T* __restrict__ force, EnergyJob ej,
+                                                              GridGeom g, BinGeom bg) {
   extern __shared__ __attribute__((aligned(16))) char smem[];
   T* tile = reinterpret_cast<T*>(smem);
   // with an energy job, one extra last workgroup runs it beside the gather
@@ -1187,27 +1228,39 @@ __global__ __launch_bounds__(256) void gather_brick(const T* __restrict__ sorted
     H[j] = bg.edge[j] + P - 1;
   }
   const int K1 = g.K[0], K2 = g.K[1], K3 = g.K[2];
-  const int ntile = H[0] * H[1] * H[2];
-  for (int e = threadIdx.x; e < ntile; e += blockDim.x) {
-    int k2 = lo[2] - (P - 1) + e % H[2], k1 = lo[1] - (P - 1) + (e / H[2]) % H[1],
-        k0 = lo[0] - (P - 1) + e / (H[1] * H[2]);
-    while (k0 < 0) k0 += K1;
-    while (k0 >= K1) k0 -= K1;
-    while (k1 < 0) k1 += K2;
-    while (k1 >= K2) k1 -= K2;
-    while (k2 < 0) k2 += K3;
-    while (k2 >= K3) k2 -= K3;
-    tile[e] = grid[(static_cast<long>(k0) * K2 + k1) * K3 + k2];
+  // the tile, one (t0, t1) row of H2 consecutive k3 values per 16 lanes
+  // (a row start is wrapped once per row; within a row k3 wraps at most
+  // once, every tile extent being below 2 K_j)
+  {
+    const int nrows = H[0] * H[1];
+    const int c16 = threadIdx.x & 15;
+    for (int r = threadIdx.x >> 4; r < nrows; r += kGatherThreads / 16) {
+      const int t0 = r / H[1], t1 = r - t0 * H[1];
+      int k0 = lo[0] - (P - 1) + t0, k1 = lo[1] - (P - 1) + t1;
+      while (k0 < 0) k0 += K1;
+      while (k0 >= K1) k0 -= K1;
+      while (k1 < 0) k1 += K2;
+      while (k1 >= K2) k1 -= K2;
+      const T* src = grid + (static_cast<long>(k0) * K2 + k1) * K3;
+      for (int c = c16; c < H[2]; c += 16) {
+        int k2 = lo[2] - (P - 1) + c;
+        while (k2 < 0) k2 += K3;
+        while (k2 >= K3) k2 -= K3;
+        tile[r * H[2] + c] = src[k2];
+      }
+    }
   }
   __syncthreads();
   const int i0 = offset[brick], i1 = offset[brick + 1];
   for (int s = i0 + threadIdx.x; s < i1; s += blockDim.x) {
+    T rec[4];
+    load_record(sorted, s, rec);
     T w[3][P], dw[3][P];
     int l[3];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
       int base;
-      const T f = stencil_coord(sorted[4L * s + j], g.invL[j], g.K[j], g.cell, base);
+      const T f = stencil_coord(rec[j], g.invL[j], g.K[j], g.cell, base);
       stencil_weights<T, P>(f, g.cell, w[j], dw[j]);
       // binned by the same floor: base lies in this brick (the clamp only
       // keeps a corrupted input inside the tile)
@@ -1247,7 +1300,7 @@ __global__ __launch_bounds__(256) void gather_brick(const T* __restrict__ sorted
       g2 += wa * sa2;
     }
     const long i = perm[s];
-    const T qi = sorted[4L * s + 3];
+    const T qi = rec[3];
     if (pot) pot[i] = phi;
     if (force) {
       force[3 * i + 0] = -qi * g0 * static_cast<T>(K1 * g.invL[0]);
@@ -1533,7 +1586,7 @@ hipError_t spread_brick_p(const GridGeom& g, const Bins& b, const void* src, voi
   const int ntile = (b.geom.edge[0] + P - 1) * (b.geom.edge[1] + P - 1) * (b.geom.edge[2] + P - 1);
   if constexpr (sizeof(T) == 4 && P <= 9) {
     // float grids: the matrix-core tile spread (every brick edge <= 8)
-    hipLaunchKernelGGL((spread_home_mfma<P>), dim3(b.geom.nbricks), dim3(256), 0, st, srt,
+    hipLaunchKernelGGL((spread_home_mfma<P>), dim3(b.geom.nbricks), dim3(64 * kMfmaWaves), 0, st, srt,
                        b.offset, static_cast<float*>(b.tiles), b.count, g, b.geom);
   } else {
     hipLaunchKernelGGL((spread_home<T, P>), dim3(b.geom.nbricks), dim3(kHomeThreads),
@@ -1555,7 +1608,8 @@ hipError_t gather_brick_p(const GridGeom& g, const Bins& b, int64_t n, const voi
                           void* pot, void* force, const EnergyJob& ej, hipStream_t st) {
   if (sizeof(T) == 4 && P > 4) {
     const int ntile = (b.geom.edge[0] + P - 1) * (b.geom.edge[1] + P - 1) * (b.geom.edge[2] + P - 1);
-    hipLaunchKernelGGL((gather_brick<T, P>), dim3(b.geom.nbricks + (ej.e4 ? 1 : 0)), dim3(128),
+    hipLaunchKernelGGL((gather_brick<T, P>), dim3(b.geom.nbricks + (ej.e4 ? 1 : 0)),
+                       dim3(kGatherThreads),
                        sizeof(T) * ntile,
                        st, static_cast<const T*>(b.sorted), b.offset, b.perm,
                        static_cast<const T*>(grid), static_cast<T*>(pot), static_cast<T*>(force),

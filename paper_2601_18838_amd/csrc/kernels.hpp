@@ -86,7 +86,7 @@ __host__ __device__ constexpr int x3_yswz(int NKC, int r) {
 // streams per workgroup (NS).  96 x 96 slabs: two streams of two 48-column
 // waves (four-wave workgroups, two per CU: two waves on every SIMD).
 constexpr int x3_ct(int K1P, int K2P) { return (K1P == 96 && K2P == 96) ? 3 : 2; }
-constexpr int x3_streams(int K1P, int K2P) { return (K1P == 96 && K2P == 96) ? 2 : 1; }
+constexpr int x3_streams(int K1P, int K2P) { return ((K1P == 96 && K2P == 96) || (K1P == 128 && K2P == 128)) ? 2 : 1; }
 
 hipError_t launch_skp_sum(const SkpArgs& a, hipStream_t st);
 // the per-block (sum, max) pairs of launch_skp_sum only, into a.scratch

@@ -90,6 +90,8 @@ CASES = {
     # K2 and K3 padded to 128 (K1P = 64): the 128-row stage-1 tile and the
     # 128-column stage-2 instances
     "k2p_k3p_128": ((40.0, 100.0, 120.0), (40, 100, 120), 4, 0.34, 24, 3000, "pm1", 17),
+    # K1P = K2P = 128: the two-stream 128 x 128 stage-2 instance
+    "k1p_k2p_128": ((50.0, 55.0, 12.0), (100, 110, 24), 4, 0.5, 16, 3000, "pm1", 22),
     # K3 = 160 (K3P > 128): the one-wave stage 1 that loops over K chunks
     "k3p_160": ((24.0, 40.0, 160.0), (24, 40, 160), 6, 0.34, 20, 2001, "water", 18),
     # the largest grid of the batched workload: 96 x 128 x 160, order 6, more
