@@ -134,7 +134,8 @@ struct kpme_plan_s {
   void* Phig = nullptr;
   void* pot = nullptr;        // internal potentials (max_n)
   Bins bins{};                // binned particle layout (evaluate, spread)
-  double* part2 = nullptr;    // per-brick (sum, max) of the spread grid
+  double* part2 = nullptr;    // (sum, max) partials of the spread grid (spread_parts of them)
+  int spread_parts = 0;
   void* Q2g = nullptr;        // adjoint: spread of the upstream potential gradient
   void* Psig = nullptr;       // adjoint: Theta applied to it
   void* sorted2 = nullptr;    // adjoint: binned (x, y, z, g_pot)
@@ -824,6 +825,15 @@ kpme_status kpme_plan_create_ex(kpme_plan_t* plan, const double box[3], const in
       }
     }
   }
+  bg.two_homes = 1;
+  for (int j = 0; j < 3; ++j) {
+    const int K = grid[j], E = bg.edge[j];
+    bool two = bg.nb[j] >= 2 && K % E == 0 && K >= E + spline_order - 1;
+    for (int bo = 0; bo < bg.nb[j] && two; ++bo)
+      two = hnbr[(static_cast<size_t>(j) * bg.nbmax + bo) * kNbrRec] == 2;
+    if (!two) bg.two_homes = 0;
+  }
+  pl->spread_parts = spread_partials(bg, spline_order);
   const size_t nY = static_cast<size_t>(r0) * K3 * K1P * K2P;
   void* tmp = nullptr;
   do {
@@ -1018,7 +1028,7 @@ kpme_status do_skp(kpme_plan_t plan, const void* in, void* out, hipStream_t st,
   a.epart = epart;
   // the split stage-1 kernels reduce up to kFoldedSums (sum, max) partials
   // themselves (every workgroup reads them all); more go through sum_final
-  const int np = sum_ready ? plan->bins.geom.nbricks : kSumBlocks;
+  const int np = sum_ready ? plan->spread_parts : kSumBlocks;
   const bool s1_reduces = (plan->prec == PREC_BF16X3 || plan->prec == PREC_FP16X3) &&
                           np <= kFoldedSums;
   a.sum_part = s1_reduces ? (sum_ready ? part2 : plan->scratch) : nullptr;
@@ -1029,7 +1039,7 @@ kpme_status do_skp(kpme_plan_t plan, const void* in, void* out, hipStream_t st,
     if (s1_reduces)
       e = sum_ready ? hipSuccess : launch_sum_partials(a, st);
     else
-      e = sum_ready ? launch_sum_final(part2, plan->bins.geom.nbricks, scalars, st)
+      e = sum_ready ? launch_sum_final(part2, plan->spread_parts, scalars, st)
                     : launch_skp_sum(a, st);
   }
   if (e == hipSuccess && plan->rect) {

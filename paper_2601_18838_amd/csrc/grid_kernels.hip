@@ -282,7 +282,7 @@ __device__ __forceinline__ int brick_of_particle(const T* __restrict__ pos, long
 // workgroup ranks its particles inside the bricks in LDS, then reserves one
 // range per brick with a single global atomic.  count[] must be zero on entry.
 constexpr int kBinPer = 4;        // particles per thread of the scatter
-constexpr int kCountPer = 4;      // particles per thread of the LDS-histogram count
+constexpr int kCountPer = 8;      // particles per thread of the LDS-histogram count
 constexpr int kLdsHist = 8192;    // bricks handled with an LDS histogram
 
 template <typename T>
@@ -309,7 +309,7 @@ __global__ __launch_bounds__(256) void bin_count_lds(long n, const T* __restrict
   __syncthreads();
   // one global atomic per non-empty brick (hist then holds this block's
   // base), issued kFlush at a time so that their round trips overlap
-  constexpr int kFlush = 8;
+  constexpr int kFlush = 16;
   for (int b0 = threadIdx.x; b0 < nb; b0 += kFlush * blockDim.x) {
     int c[kFlush];
 #pragma unroll
@@ -885,6 +885,123 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void spread_home_mfma(const float*
   }
 }
 
+// Pass 2, persistent form for grids where every owner brick is reached by
+// exactly two home bricks per axis (itself and the next one, periodically)
+// and every tile extent is at most the axis length (BinGeom::two_homes):
+// workgroup w takes a contiguous range of owner bricks, derives the home
+// bricks and tile offsets of each from its brick coordinates, and loads the
+// eight tile values of its point in the next brick while it adds and stores
+// those of the current one.  Per point the eight values are added in FP64
+// in the order of spread_combine (home lists ascending per axis), so the
+// grid is the same; the workgroup's FP64 (sum, max) over all its points goes
+// to part2[w].
+constexpr int kCombineThreads = 512;
+constexpr int kCombineMaxBricks = 64;
+
+int combine_workgroups(int nbricks) {
+  const int target = 4 * 256;
+  const int per = std::max(1, (nbricks + target - 1) / target);
+  return (nbricks + per - 1) / per;
+}
+
+template <typename T, int P>
+__global__ __launch_bounds__(kCombineThreads) void spread_combine_pf(
+    const T* __restrict__ tiles, T* __restrict__ grid, double* __restrict__ part2, GridGeom g,
+    BinGeom bg) {
+  __shared__ double red[32];
+  const int wl = xcd_order(blockIdx.x, gridDim.x);
+  const int nb = bg.nbricks;
+  const int b_begin = static_cast<int>(static_cast<long>(wl) * nb / gridDim.x);
+  const int b_end = static_cast<int>(static_cast<long>(wl + 1) * nb / gridDim.x);
+  int H[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) H[j] = bg.edge[j] + P - 1;
+  const int ntile = H[0] * H[1] * H[2];
+  // this thread's point of a brick (edges are the full 8 or the axis)
+  const int e = threadIdx.x;
+  const int npts = bg.edge[0] * bg.edge[1] * bg.edge[2];
+  const bool has = e < npts;
+  const int x2 = e % bg.edge[2], x1 = (e / bg.edge[2]) % bg.edge[1],
+            x0 = e / (bg.edge[1] * bg.edge[2]);
+  const int x[3] = {x0, x1, x2};
+  // the eight (tile, offset) pairs of point x in owner brick `brick`, in the
+  // order of the general kernel, and whether each lies in its tile
+  auto locate = [&](int brick, long* at, bool* in, long* gat) {
+    int own[3], rest = brick;
+    own[2] = rest % bg.nb[2];
+    rest /= bg.nb[2];
+    own[1] = rest % bg.nb[1];
+    own[0] = rest / bg.nb[1];
+    int hid[3][2], l[3][2];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const int nxt = own[j] + 1 == bg.nb[j] ? 0 : own[j] + 1;
+      hid[j][0] = min(own[j], nxt);   // ascending, as the neighbour lists
+      hid[j][1] = max(own[j], nxt);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        int d = (own[j] - hid[j][h]) * bg.edge[j] + P - 1;
+        if (d < 0) d += g.K[j];
+        if (d >= g.K[j]) d -= g.K[j];
+        int v = x[j] + d;
+        if (v >= g.K[j]) v -= g.K[j];
+        l[j][h] = v;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int a = q >> 2, b = (q >> 1) & 1, c = q & 1;
+      in[q] = has && l[0][a] < H[0] && l[1][b] < H[1] && l[2][c] < H[2];
+      at[q] = static_cast<long>((hid[0][a] * bg.nb[1] + hid[1][b]) * bg.nb[2] + hid[2][c]) * ntile +
+              (l[0][a] * H[1] + l[1][b]) * H[2] + l[2][c];
+    }
+    *gat = (static_cast<long>(own[0] * bg.edge[0] + x0) * g.K[1] + own[1] * bg.edge[1] + x1) *
+               g.K[2] + own[2] * bg.edge[2] + x2;
+  };
+  T v[8];
+  bool in[8];
+  long gat = 0;
+  if (b_begin < b_end) {
+    long at[8];
+    locate(b_begin, at, in, &gat);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = in[q] ? tiles[at[q]] : T(0);
+  }
+  double s = 0.0, m = 0.0;
+  for (int brick = b_begin; brick < b_end; ++brick) {
+    T cur[8];
+    bool cin[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      cur[q] = v[q];
+      cin[q] = in[q];
+    }
+    const long cgat = gat;
+    if (brick + 1 < b_end) {   // the next brick's values in flight
+      long at[8];
+      locate(brick + 1, at, in, &gat);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = in[q] ? tiles[at[q]] : T(0);
+    }
+    if (has) {
+      double acc = 0.0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (cin[q]) acc += static_cast<double>(cur[q]);
+      const T val = static_cast<T>(acc);
+      grid[cgat] = val;
+      s += static_cast<double>(val);
+      m = fmax(m, fabs(static_cast<double>(val)));
+    }
+  }
+  double r[2] = {s, m};
+  block_reduce<1, 2>(r, red);
+  if (threadIdx.x == 0) {
+    part2[2 * blockIdx.x] = r[0];
+    part2[2 * blockIdx.x + 1] = r[1];
+  }
+}
+
 // Pass 2: one workgroup per grid brick sums, for each of its points and in a
 // fixed order, the tiles of the home bricks whose stencils reach it (the
 // per-axis lists nbr[axis][brick] = {count, b0, b1, ...}).  Point x_j of the
@@ -1199,6 +1316,16 @@ __device__ __forceinline__ void load_record(const double* sorted, long s, double
 // Results go back to the caller's order through perm.  With an energy job,
 // one extra last workgroup runs it.
 constexpr int kGatherThreads = 256;
+constexpr int kGatherMaxBricks = 64;   // bricks per workgroup of the persistent gather
+
+// Workgroups of the persistent gather: about five per compute unit, each
+// with the same number of bricks up to one (at most kGatherMaxBricks, since
+// the grid has at most 32^3 bricks).
+int gather_pf_workgroups(int nbricks) {
+  const int target = 5 * 256;
+  const int per = std::max(1, (nbricks + target - 1) / target);
+  return (nbricks + per - 1) / per;
+}
 
 template <typename T, int P>
 __global__ __launch_bounds__(kGatherThreads) void gather_brick(const T* __restrict__ sorted,
@@ -1307,6 +1434,172 @@ __global__ __launch_bounds__(kGatherThreads) void gather_brick(const T* __restri
       force[3 * i + 1] = -qi * g1 * static_cast<T>(K2 * g.invL[1]);
       force[3 * i + 2] = -qi * g2 * static_cast<T>(K3 * g.invL[2]);
     }
+  }
+}
+
+// The same gather, persistent and software-pipelined (tile extents <= 16,
+// i.e. P <= 9): workgroup w takes a contiguous range of bricks and, while it
+// interpolates the particles of one brick from LDS, already holds in
+// registers the next brick's tile values (rows (t0, t1) of H2 consecutive
+// values, 16 lanes per row, kPfRows rows per thread) and the records and
+// perm entries of its first kGatherThreads particles.  The brick offsets of
+// the range are staged in LDS once.  Results and summation order per
+// particle are those of gather_brick.
+template <typename T, int P>
+__global__ __launch_bounds__(kGatherThreads) void gather_brick_pf(
+    const T* __restrict__ sorted, const int* __restrict__ offset, const int* __restrict__ perm,
+    const T* __restrict__ grid, T* __restrict__ pot, T* __restrict__ force, EnergyJob ej,
+    GridGeom g, BinGeom bg) {
+  static_assert(P <= 9, "rows of at most 16 values");
+  constexpr int HM = 8 + P - 1;                       // largest tile extent (edge <= 8)
+  constexpr int kPfRows = (HM * HM + kGatherThreads / 16 - 1) / (kGatherThreads / 16);
+  extern __shared__ __attribute__((aligned(16))) char smem[];
+  T* tile = reinterpret_cast<T*>(smem);
+  __shared__ int offs[kGatherMaxBricks + 1];
+  const int nwork = gridDim.x - (ej.e4 ? 1 : 0);
+  if (static_cast<int>(blockIdx.x) == nwork) {
+    run_energy_job(ej);
+    return;
+  }
+  const int wl = xcd_order(blockIdx.x, nwork);
+  const int nb = bg.nbricks;
+  const int b_begin = static_cast<int>(static_cast<long>(wl) * nb / nwork);
+  const int b_end = static_cast<int>(static_cast<long>(wl + 1) * nb / nwork);
+  const int tid = threadIdx.x;
+  for (int k = tid; k <= b_end - b_begin; k += kGatherThreads) offs[k] = offset[b_begin + k];
+  int H[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) H[j] = bg.edge[j] + P - 1;
+  const int K1 = g.K[0], K2 = g.K[1], K3 = g.K[2];
+  const int nrows = H[0] * H[1];
+  const int c16 = tid & 15;
+  auto lo_of = [&](int brick, int* lo) {
+    int rest = brick;
+    const int o2 = rest % bg.nb[2];
+    rest /= bg.nb[2];
+    lo[2] = o2 * bg.edge[2];
+    lo[1] = (rest % bg.nb[1]) * bg.edge[1];
+    lo[0] = (rest / bg.nb[1]) * bg.edge[0];
+  };
+  // the tile values of a brick this thread stages: row r = tid / 16 + 16 k
+  auto load_tile = [&](int brick, T* reg) {
+    int lo[3];
+    lo_of(brick, lo);
+    int r = tid >> 4;
+    int t0 = r / H[1], t1 = r - t0 * H[1];
+    int k2 = lo[2] - (P - 1) + c16;
+    while (k2 < 0) k2 += K3;
+    while (k2 >= K3) k2 -= K3;
+#pragma unroll
+    for (int k = 0; k < kPfRows; ++k) {
+      reg[k] = T(0);
+      if (r < nrows && c16 < H[2]) {
+        int k0 = lo[0] - (P - 1) + t0, k1 = lo[1] - (P - 1) + t1;
+        while (k0 < 0) k0 += K1;
+        while (k0 >= K1) k0 -= K1;
+        while (k1 < 0) k1 += K2;
+        while (k1 >= K2) k1 -= K2;
+        reg[k] = grid[(static_cast<long>(k0) * K2 + k1) * K3 + k2];
+      }
+      r += kGatherThreads / 16;
+      t1 += kGatherThreads / 16;
+      while (t1 >= H[1]) {
+        t1 -= H[1];
+        ++t0;
+      }
+    }
+  };
+  auto store_tile = [&](const T* reg) {
+    int r = tid >> 4;
+#pragma unroll
+    for (int k = 0; k < kPfRows; ++k) {
+      if (r < nrows && c16 < H[2]) tile[r * H[2] + c16] = reg[k];
+      r += kGatherThreads / 16;
+    }
+  };
+  T treg[kPfRows];
+  T rec[4] = {T(0), T(0), T(0), T(0)};
+  int pm = 0;
+  __syncthreads();   // offs
+  if (b_begin < b_end) {
+    load_tile(b_begin, treg);
+    const int s = offs[0] + tid;
+    if (s < offs[1]) {
+      load_record(sorted, s, rec);
+      pm = perm[s];
+    }
+  }
+  for (int b = b_begin; b < b_end; ++b) {
+    store_tile(treg);
+    __syncthreads();
+    const int i0 = offs[b - b_begin], i1 = offs[b - b_begin + 1];
+    T rc[4] = {rec[0], rec[1], rec[2], rec[3]};
+    int pc = pm;
+    if (b + 1 < b_end) {   // next brick's values in flight during this one
+      load_tile(b + 1, treg);
+      const int s = i1 + tid;
+      if (s < offs[b - b_begin + 2]) {
+        load_record(sorted, s, rec);
+        pm = perm[s];
+      }
+    }
+    int lo[3];
+    lo_of(b, lo);
+    for (int s = i0 + tid; s < i1; s += kGatherThreads) {
+      if (s != i0 + tid) {
+        load_record(sorted, s, rc);
+        pc = perm[s];
+      }
+      T w[3][P], dw[3][P];
+      int l[3];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        int base;
+        const T f = stencil_coord(rc[j], g.invL[j], g.K[j], g.cell, base);
+        stencil_weights<T, P>(f, g.cell, w[j], dw[j]);
+        l[j] = min(max(base - lo[j] + P - 1, P - 1), H[j] - 1);
+      }
+      T phi = 0, g0 = 0, g1 = 0, g2 = 0;
+      constexpr int UB = P <= 8 ? P : 1;
+#pragma unroll 1
+      for (int a = 0; a < P; ++a) {
+        T wa = w[0][0], dwa = dw[0][0];
+#pragma unroll
+        for (int t = 1; t < P; ++t)
+          if (a == t) {
+            wa = w[0][t];
+            dwa = dw[0][t];
+          }
+        T sa = 0, sa1 = 0, sa2 = 0;
+#pragma unroll UB
+        for (int bb = 0; bb < P; ++bb) {
+          const T* row = tile + ((l[0] - a) * H[1] + l[1] - bb) * H[2] + l[2];
+          T sv = 0, s2 = 0;
+#pragma unroll
+          for (int c = 0; c < P; ++c) {
+            const T v = row[-c];
+            sv += w[2][c] * v;
+            s2 += dw[2][c] * v;
+          }
+          sa += w[1][bb] * sv;
+          sa1 += dw[1][bb] * sv;
+          sa2 += w[1][bb] * s2;
+        }
+        phi += wa * sa;
+        g0 += dwa * sa;
+        g1 += wa * sa1;
+        g2 += wa * sa2;
+      }
+      const long i = pc;
+      const T qi = rc[3];
+      if (pot) pot[i] = phi;
+      if (force) {
+        force[3 * i + 0] = -qi * g0 * static_cast<T>(K1 * g.invL[0]);
+        force[3 * i + 1] = -qi * g1 * static_cast<T>(K2 * g.invL[1]);
+        force[3 * i + 2] = -qi * g2 * static_cast<T>(K3 * g.invL[2]);
+      }
+    }
+    __syncthreads();   // every tile read done before the next store
   }
 }
 
@@ -1593,6 +1886,15 @@ hipError_t spread_brick_p(const GridGeom& g, const Bins& b, const void* src, voi
                        sizeof(double) * ntile, st, srt, b.offset, static_cast<T*>(b.tiles),
                        b.count, g, b.geom);
   }
+  if (b.geom.two_homes) {
+    const int nw = combine_workgroups(b.geom.nbricks);
+    if ((b.geom.nbricks + nw - 1) / nw > kCombineMaxBricks ||
+        b.geom.edge[0] * b.geom.edge[1] * b.geom.edge[2] > kCombineThreads)
+      return hipErrorInvalidValue;
+    hipLaunchKernelGGL((spread_combine_pf<T, P>), dim3(nw), dim3(kCombineThreads), 0, st,
+                       static_cast<const T*>(b.tiles), static_cast<T*>(grid), part2, g, b.geom);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL((spread_combine<T, P>), dim3(b.geom.nbricks), dim3(512), 0, st,
                      static_cast<const T*>(b.tiles), b.nbr, static_cast<T*>(grid), part2, g,
                      b.geom);
@@ -1606,6 +1908,17 @@ hipError_t spread_brick_p(const GridGeom& g, const Bins& b, const void* src, voi
 template <typename T, int P>
 hipError_t gather_brick_p(const GridGeom& g, const Bins& b, int64_t n, const void* grid,
                           void* pot, void* force, const EnergyJob& ej, hipStream_t st) {
+  if constexpr (sizeof(T) == 4 && P > 4 && P <= 9) {
+    const int ntile = (b.geom.edge[0] + P - 1) * (b.geom.edge[1] + P - 1) * (b.geom.edge[2] + P - 1);
+    const int nw = gather_pf_workgroups(b.geom.nbricks);
+    if ((b.geom.nbricks + nw - 1) / nw > kGatherMaxBricks) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((gather_brick_pf<T, P>), dim3(nw + (ej.e4 ? 1 : 0)),
+                       dim3(kGatherThreads), sizeof(T) * ntile, st,
+                       static_cast<const T*>(b.sorted), b.offset, b.perm,
+                       static_cast<const T*>(grid), static_cast<T*>(pot), static_cast<T*>(force),
+                       ej, g, b.geom);
+    return hipGetLastError();
+  }
   if (sizeof(T) == 4 && P > 4) {
     const int ntile = (b.geom.edge[0] + P - 1) * (b.geom.edge[1] + P - 1) * (b.geom.edge[2] + P - 1);
     hipLaunchKernelGGL((gather_brick<T, P>), dim3(b.geom.nbricks + (ej.e4 ? 1 : 0)),
@@ -1632,6 +1945,12 @@ hipError_t gather_brick_p(const GridGeom& g, const Bins& b, int64_t n, const voi
 
 
 }  // namespace
+
+// Number of (sum, max) pairs the binned spread writes: one per workgroup of
+// the persistent combine, else one per brick.
+int spread_partials(const BinGeom& bg, int p) {
+  return (p > 4 && bg.two_homes) ? combine_workgroups(bg.nbricks) : bg.nbricks;
+}
 
 // Number of (sum q, sum q^2) pairs the scatter writes.
 int scatter_partials(const Bins& b, int64_t n) {

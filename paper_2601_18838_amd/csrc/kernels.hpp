@@ -120,6 +120,8 @@ struct BinGeom {
   int nb[3];     // bricks per axis, ceil(K / edge)
   int nbricks;
   int nbmax;     // row stride of the neighbour table
+  int two_homes; // every owner brick reached by exactly two home bricks per
+                 // axis (itself and the next) and every tile extent <= K_j
 };
 
 // Device buffers of the binned particle layout.
@@ -145,6 +147,7 @@ hipError_t launch_gather_direct(int prec, const GridGeom& g, int64_t n, const vo
 hipError_t launch_bin(int prec, const GridGeom& g, const Bins& b, int64_t n, const void* pos,
                       const void* q, double* qpart, hipStream_t st);
 int scatter_partials(const Bins& b, int64_t n);
+int spread_partials(const BinGeom& bg, int p);
 
 // Final energies of an evaluation, combined by one workgroup: E_rec = 1/2 of
 // the sum of the finalize partials (sum over grid points of Q Phi, equal to
