@@ -66,7 +66,9 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2601_18838_amd", "csrc", "skp_kernels.hip")
+# the stage-2 kernels and the header that picks their instance (tiles, streams)
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2601_18838_amd", "csrc", f)
+                  for f in ("skp_kernels.hip", "kernels.hpp")]
 HBM_PEAK_GBS = 8000.0
 
 
@@ -83,7 +85,10 @@ def committed_traffic(workload, precision, parts):
             if line.startswith("- ") and ": " in line:
                 k, v = line[2:].strip().split(": ", 1)
                 fields[k] = v.strip("` ")
-        sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+        h = hashlib.sha256()
+        for src in KERNEL_SOURCES:
+            h.update(open(src, "rb").read())
+        sha = h.hexdigest()
         if (fields.get("source_sha256") != sha or fields.get("workload") != workload
                 or fields.get("precision") != precision or int(fields.get("stage2_parts", -1)) != parts):
             return None
@@ -324,7 +329,17 @@ def main():
     K1, K2, K3 = wl.grid
     G = K1 * K2 * K3
     R = info["rank"]
-    flops_s2 = 2.0 * G * R * (K1 + K2)                  # grouped stage-2, one product
+    if args.skp_form == "rect":
+        # rectangular form: three thin products into the real mode basis and
+        # three back (the "stage 2" timer covers all six and the scaling);
+        # n_j = min(2 M_j + 1, K_j) rows, M_j the mode cutoff (K_j / 2 for
+        # the full B-spline symbol)
+        cut = wl.extra.get("mode_cutoff", 0)
+        nr = [min(2 * (cut if cut else k // 2) + 1, k) for k in wl.grid]
+        flops_s2 = 2.0 * 2.0 * (nr[2] * K1 * K2 * K3 + nr[1] * nr[2] * K1 * K2
+                                + nr[0] * nr[1] * nr[2] * K1)
+    else:
+        flops_s2 = 2.0 * G * R * (K1 + K2)              # grouped stage-2, one product
     issued = 3.0 * flops_s2 if mixed.endswith("x3") else flops_s2
     ms_s2, cnt_s2 = st_mixed["skp_stage2"]
     avg_s2 = ms_s2 / max(cnt_s2, 1) * 1e-3
@@ -384,7 +399,9 @@ def main():
         "autotune_seconds": tune_s,
         "stage_us": stage_us,
         "stage_us_fp64": stage_us_fp64,
-        "roofline": {"bound": "mfma", "kernel": "skp_stage2", "achieved": achieved,
+        "roofline": {"bound": "mfma",
+                     "kernel": "skp_stage2" if args.skp_form != "rect" else "rect_apply",
+                     "achieved": achieved,
                      "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                      "traffic": committed_traffic(wl.name, mixed, plans[mixed].stage2_parts()),
                      "flops_per_launch": issued,
