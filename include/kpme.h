@@ -315,15 +315,21 @@ kpme_status kpme_factors_compute_ex(const double box[3], const int grid[3],
                                     int* group, double* info6);
 
 /* Batched evaluation of independent systems (each with its own box, grid,
- * spline order and rank R = skp_rank[s] >= 1).  kpme_batch_create builds one
- * plan per system (one precision for all; host arrays box3[3*count],
- * grid3[3*count], spline_order, beta, skp_rank, max_particles), autotunes
- * every distinct (grid, order, R, precision) class once, and assigns the
- * systems to parallel branches by longest-processing-time on an estimated
+ * spline order and rank R = skp_rank[s] >= 1; the batched form of the
+ * Kronecker-product method's term independence, Conclusion).
+ * kpme_batch_create builds one plan per system (one precision for all; host
+ * arrays box3[3*count], grid3[3*count], spline_order, beta, skp_rank,
+ * max_particles), autotunes every distinct (grid, order, R, precision) class
+ * once, and orders the systems by longest-processing-time on an estimated
  * cost.  kpme_batch_evaluate records, for a new argument signature (n[] and
- * the five pointers), every system's kpme_evaluate launch sequence into one
- * HIP graph with parallel branches, and replays it as a single launch on
- * `stream`; an unchanged signature only replays.  A signature change after
+ * the five pointers), one HIP graph and replays it as a single launch on
+ * `stream`; an unchanged signature only replays.  The recording is, where
+ * every system's kernels have a batched form (the mixed-precision paths),
+ * one kernel launch per stage and kernel instance whose grid holds every
+ * system's workgroups (a per-launch table of argument tuples and system
+ * slices in device memory, largest systems first); otherwise every system's
+ * kpme_evaluate launch sequence on parallel graph branches.  The environment
+ * variable KPME_BATCH_FUSED=0 forces the second form.  A signature change after
  * the first recording synchronises `stream` and then the whole device
  * before the previous recording is released and the new one captured, so
  * no recording ever overlaps a running replay; callers that evaluate in a
@@ -338,6 +344,10 @@ kpme_status kpme_batch_create(kpme_batch_t* batch, int count,
                               const int* skp_rank, int precision,
                               const int64_t* max_particles, int device);
 kpme_status kpme_batch_destroy(kpme_batch_t batch);
+/* The form of the batch's current recording (host outputs, may be NULL):
+ * *form = 1 batched launches, 0 per-system graph, -1 nothing recorded yet;
+ * *launches = kernel launches (graph nodes) replayed per evaluation. */
+kpme_status kpme_batch_info(kpme_batch_t batch, int* form, int* launches);
 kpme_status kpme_batch_evaluate(kpme_batch_t batch, const int64_t* n,
                                 const void* pos, const void* q, void* pot,
                                 void* force, double* energy4, void* stream);

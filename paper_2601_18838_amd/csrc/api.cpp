@@ -19,12 +19,24 @@
 #include <string>
 #include <vector>
 
+#include "batch_launch.hpp"
 #include "factors.hpp"
 #include "kernels.hpp"
 #include "noalloc.hpp"
 #include "rect.hpp"
 
 using namespace kpme;
+
+namespace kpme {
+LaunchRecorder*& launch_recorder() {
+  static thread_local LaunchRecorder* r = nullptr;
+  return r;
+}
+hipError_t batched_set_lds(const void* kernel, size_t bytes) {
+  return hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             static_cast<int>(bytes));
+}
+}  // namespace kpme
 
 namespace {
 
@@ -158,6 +170,7 @@ struct kpme_plan_s {
 };
 
 constexpr int kBatchBranches = 4;  // parallel branches of the batch graph
+constexpr double kSparseDensity = 64.0;  // particles per brick below which orders > 4 go sparse
 constexpr uint32_t kBatchMagic = 0x4b42544eu;
 
 struct kpme_batch_s {
@@ -172,6 +185,11 @@ struct kpme_batch_s {
   hipGraphExec_t exec = nullptr;       // recorded graph for the last signature
   std::vector<int64_t> sig_n;
   const void* sig_ptr[5] = {};
+  // batched form: one launch per stage and kernel instance for all systems
+  bool fused_allowed = true;
+  int mode = 0;                        // recorded form: 1 batched launches, 0 per-system graph
+  int launches = 0;                    // kernel launches in the recorded graph
+  void* table = nullptr;               // device argument tuples and slices of the batched launches
 };
 
 namespace {
@@ -268,6 +286,7 @@ void batch_free(kpme_batch_s* b) {
   (void)hipSetDevice(b->device);
   (void)hipDeviceSynchronize();
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->table) (void)hipFree(b->table);
   for (int k = 0; k < kBatchBranches; ++k) {
     if (b->branch[k]) (void)hipStreamDestroy(b->branch[k]);
     if (b->join[k]) (void)hipEventDestroy(b->join[k]);
@@ -833,6 +852,15 @@ kpme_status kpme_plan_create_ex(kpme_plan_t* plan, const double box[3], const in
       two = hnbr[(static_cast<size_t>(j) * bg.nbmax + bo) * kNbrRec] == 2;
     if (!two) bg.two_homes = 0;
   }
+  // Few particles per brick (planned for max_particles): the home tiles of
+  // orders above 4 would write and re-read (edge + p - 1)^3 values per brick
+  // for a handful of particles, so the owner spread (FP64 LDS tile of the
+  // brick itself) and the direct gather are used instead.
+  // Tuning override: KPME_SPARSE=0/1.
+  bg.sparse = spline_order > 4 && spline_order <= 9 &&
+              static_cast<double>(max_particles) < kSparseDensity * bg.nbricks;
+  if (const char* env = std::getenv("KPME_SPARSE"))
+    bg.sparse = spline_order > 4 && spline_order <= 9 && std::atoi(env) != 0;
   pl->spread_parts = spread_partials(bg, spline_order);
   const size_t nY = static_cast<size_t>(r0) * K3 * K1P * K2P;
   void* tmp = nullptr;
@@ -1372,6 +1400,190 @@ kpme_status kpme_evaluate_backward(kpme_plan_t plan, int64_t n, const void* pos,
                   "adjoint gather");
 }
 
+}  // extern "C"
+
+namespace {
+
+// Estimated cost of one system's evaluation (longest-processing-time order).
+double batch_cost(const kpme_plan_s* pl) {
+  const double G = static_cast<double>(pl->K[0]) * pl->K[1] * pl->K[2];
+  return G * pl->R * (pl->K[0] + pl->K[1]) * (pl->prec == KPME_FP64 ? 16.0 : 1.0) +
+         static_cast<double>(pl->max_n) * pl->p * pl->p * pl->p * 200.0;
+}
+
+// The per-system form: every system's kpme_evaluate launch sequence in one
+// graph with kBatchBranches parallel branches.
+kpme_status batch_record_graph(kpme_batch_s* batch, const int64_t* n, const void* pos,
+                               const void* q, void* pot, void* force, double* energy4) {
+  const int count = static_cast<int>(batch->plans.size());
+  const size_t es = batch->plans[0]->esize();
+  hipError_t e = hipStreamBeginCapture(batch->capture, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return from_hip(e, "batch capture");
+  kpme_status s = KPME_SUCCESS;
+  (void)hipEventRecord(batch->fork, batch->capture);
+  for (int k = 0; k < kBatchBranches; ++k) (void)hipStreamWaitEvent(batch->branch[k], batch->fork, 0);
+  int64_t off = 0;
+  for (int k = 0; k < count && s == KPME_SUCCESS; ++k) {
+    const char* P = static_cast<const char*>(pos);
+    const char* Q = static_cast<const char*>(q);
+    s = kpme_evaluate(batch->plans[k], n[k], P ? P + 3 * off * es : nullptr,
+                      Q ? Q + off * es : nullptr,
+                      pot ? static_cast<char*>(pot) + off * es : nullptr,
+                      force ? static_cast<char*>(force) + 3 * off * es : nullptr,
+                      energy4 ? energy4 + 4 * k : nullptr, batch->branch[batch->branch_of[k]]);
+    off += n[k];
+  }
+  for (int k = 0; k < kBatchBranches; ++k) {
+    (void)hipEventRecord(batch->join[k], batch->branch[k]);
+    (void)hipStreamWaitEvent(batch->capture, batch->join[k], 0);
+  }
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(batch->capture, &graph);
+  if (s != KPME_SUCCESS) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return s;
+  }
+  if (e != hipSuccess) return from_hip(e, "batch capture");
+  size_t nodes = 0;
+  (void)hipGraphGetNodes(graph, nullptr, &nodes);
+  e = hipGraphInstantiate(&batch->exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    batch->exec = nullptr;
+    return from_hip(e, "graph instantiate");
+  }
+  batch->mode = 0;
+  batch->launches = static_cast<int>(nodes);
+  return KPME_SUCCESS;
+}
+
+// The batched form: every system's launches are recorded (not issued),
+// grouped by stage and kernel instance, and each group becomes one launch
+// whose grid holds the systems' grids one after another, largest estimated
+// cost first; the argument tuples and slice table live in one device buffer
+// written here.  Returns KPME_ERROR_NOT_SUPPORTED (nothing recorded) when a
+// system reaches a launch without a batched form.
+kpme_status batch_record_fused(kpme_batch_s* batch, const int64_t* n, const void* pos,
+                               const void* q, void* pot, void* force, double* energy4) {
+  if (!batch->fused_allowed) return KPME_ERROR_NOT_SUPPORTED;
+  const int count = static_cast<int>(batch->plans.size());
+  const size_t es = batch->plans[0]->esize();
+  LaunchRecorder rec;
+  std::vector<int> sys_of;
+  launch_recorder() = &rec;
+  kpme_status s = KPME_SUCCESS;
+  int64_t off = 0;
+  for (int k = 0; k < count && s == KPME_SUCCESS; ++k) {
+    const char* P = static_cast<const char*>(pos);
+    const char* Q = static_cast<const char*>(q);
+    s = kpme_evaluate(batch->plans[k], n[k], P ? P + 3 * off * es : nullptr,
+                      Q ? Q + off * es : nullptr,
+                      pot ? static_cast<char*>(pot) + off * es : nullptr,
+                      force ? static_cast<char*>(force) + 3 * off * es : nullptr,
+                      energy4 ? energy4 + 4 * k : nullptr, batch->capture);
+    sys_of.resize(rec.recs.size(), k);
+    off += n[k];
+  }
+  launch_recorder() = nullptr;
+  if (s != KPME_SUCCESS) return s;
+  if (rec.unsupported) return KPME_ERROR_NOT_SUPPORTED;
+  // groups by (stage, kernel instance), in stage order; systems by cost
+  struct Group {
+    int stage;
+    const void* kernel;
+    int threads;
+    size_t lds = 0;
+    size_t tsz;
+    std::vector<int> recs;
+    size_t args_off = 0, slice_off = 0;
+    int total = 0;
+  };
+  std::vector<Group> groups;
+  for (size_t i = 0; i < rec.recs.size(); ++i) {
+    const LaunchRecord& r = rec.recs[i];
+    Group* g = nullptr;
+    for (Group& c : groups)
+      if (c.stage == r.stage && c.kernel == r.kernel) g = &c;
+    if (!g) {
+      groups.push_back(Group{r.stage, r.kernel, r.threads, 0, r.tuple_size, {}});
+      g = &groups.back();
+    }
+    if (g->threads != r.threads || g->tsz != r.tuple_size) return KPME_ERROR_NOT_SUPPORTED;
+    g->lds = std::max(g->lds, r.lds);
+    g->recs.push_back(static_cast<int>(i));
+  }
+  std::stable_sort(groups.begin(), groups.end(),
+                   [](const Group& a, const Group& b) { return a.stage < b.stage; });
+  size_t bytes = 0;
+  auto align = [](size_t v) { return (v + 255) & ~static_cast<size_t>(255); };
+  for (Group& g : groups) {
+    std::stable_sort(g.recs.begin(), g.recs.end(), [&](int a, int b) {
+      return batch_cost(batch->plans[sys_of[a]]) > batch_cost(batch->plans[sys_of[b]]);
+    });
+    g.args_off = bytes;
+    bytes = align(bytes + g.recs.size() * g.tsz);
+    g.slice_off = bytes;
+    bytes = align(bytes + (g.recs.size() + 1) * sizeof(BatchSlice));
+  }
+  std::vector<unsigned char> host(bytes, 0);
+  for (Group& g : groups) {
+    int first = 0;
+    for (size_t j = 0; j < g.recs.size(); ++j) {
+      const LaunchRecord& r = rec.recs[g.recs[j]];
+      std::memcpy(&host[g.args_off + j * g.tsz], r.args.data(), g.tsz);
+      const BatchSlice sl{first, r.nx, r.ny, r.nz};
+      std::memcpy(&host[g.slice_off + j * sizeof(BatchSlice)], &sl, sizeof(sl));
+      const long wgs = static_cast<long>(r.nx) * r.ny * r.nz;
+      if (first + wgs > (1L << 30)) return KPME_ERROR_NOT_SUPPORTED;
+      first += static_cast<int>(wgs);
+    }
+    const BatchSlice end{first, 1, 1, 1};
+    std::memcpy(&host[g.slice_off + g.recs.size() * sizeof(BatchSlice)], &end, sizeof(end));
+    g.total = first;
+  }
+  hipError_t e = hipMalloc(&batch->table, std::max<size_t>(bytes, 256));
+  if (e != hipSuccess) {
+    batch->table = nullptr;
+    return from_hip(e, "batch table");
+  }
+  e = hipMemcpy(batch->table, host.data(), bytes, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return from_hip(e, "batch table");
+  e = hipStreamBeginCapture(batch->capture, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return from_hip(e, "batch capture");
+  int launched = 0;
+  for (Group& g : groups) {
+    if (g.total == 0) continue;
+    const void* args = static_cast<const char*>(batch->table) + g.args_off;
+    const BatchSlice* sl = reinterpret_cast<const BatchSlice*>(
+        static_cast<const char*>(batch->table) + g.slice_off);
+    int nsys = static_cast<int>(g.recs.size());
+    void* kargs[] = {&args, &sl, &nsys};
+    e = hipLaunchKernel(g.kernel, dim3(g.total), dim3(g.threads), kargs, g.lds, batch->capture);
+    if (e != hipSuccess) break;
+    ++launched;
+  }
+  hipGraph_t graph = nullptr;
+  const hipError_t e2 = hipStreamEndCapture(batch->capture, &graph);
+  if (e == hipSuccess) e = e2;
+  if (e != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return from_hip(e, "batch capture");
+  }
+  e = hipGraphInstantiate(&batch->exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    batch->exec = nullptr;
+    return from_hip(e, "graph instantiate");
+  }
+  batch->mode = 1;
+  batch->launches = launched;
+  return KPME_SUCCESS;
+}
+
+}  // namespace
+
+extern "C" {
+
 kpme_status kpme_batch_create(kpme_batch_t* batch, int count, const double* box3,
                               const int* grid3, const int* spline_order, const double* beta,
                               const int* skp_rank, int precision,
@@ -1437,12 +1649,9 @@ kpme_status kpme_batch_create(kpme_batch_t* batch, int count, const double* box3
   // longest-processing-time assignment of systems to graph branches
   std::vector<int> idx(count);
   for (int k = 0; k < count; ++k) idx[k] = k;
-  auto cost = [&](int k) {
-    const kpme_plan_s* pl = b->plans[k];
-    const double G = static_cast<double>(pl->K[0]) * pl->K[1] * pl->K[2];
-    return G * pl->R * (pl->K[0] + pl->K[1]) * (pl->prec == KPME_FP64 ? 16.0 : 1.0) +
-           static_cast<double>(pl->max_n) * pl->p * pl->p * pl->p * 200.0;
-  };
+  auto cost = [&](int k) { return batch_cost(b->plans[k]); };
+  // tuning override: KPME_BATCH_FUSED=0 keeps the per-system graph form
+  if (const char* env = std::getenv("KPME_BATCH_FUSED")) b->fused_allowed = std::atoi(env) != 0;
   std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return cost(x) > cost(y); });
   double load[kBatchBranches] = {0};
   b->branch_of.assign(count, 0);
@@ -1454,6 +1663,13 @@ kpme_status kpme_batch_create(kpme_batch_t* batch, int count, const double* box3
     load[best] += cost(k);
   }
   *batch = b;
+  return KPME_SUCCESS;
+}
+
+kpme_status kpme_batch_info(kpme_batch_t batch, int* form, int* launches) {
+  if (!batch || batch->magic != kBatchMagic) return fail(KPME_ERROR_INVALID_VALUE, "invalid batch handle");
+  if (form) *form = batch->exec ? batch->mode : -1;
+  if (launches) *launches = batch->exec ? batch->launches : 0;
   return KPME_SUCCESS;
 }
 
@@ -1494,40 +1710,13 @@ kpme_status kpme_batch_evaluate(kpme_batch_t batch, const int64_t* n, const void
       (void)hipGraphExecDestroy(batch->exec);
       batch->exec = nullptr;
     }
-    const size_t es = batch->plans[0]->esize();
-    hipError_t e = hipStreamBeginCapture(batch->capture, hipStreamCaptureModeThreadLocal);
-    if (e != hipSuccess) return from_hip(e, "batch capture");
-    kpme_status s = KPME_SUCCESS;
-    (void)hipEventRecord(batch->fork, batch->capture);
-    for (int k = 0; k < kBatchBranches; ++k) (void)hipStreamWaitEvent(batch->branch[k], batch->fork, 0);
-    int64_t off = 0;
-    for (int k = 0; k < count && s == KPME_SUCCESS; ++k) {
-      const char* P = static_cast<const char*>(pos);
-      const char* Q = static_cast<const char*>(q);
-      s = kpme_evaluate(batch->plans[k], n[k], P ? P + 3 * off * es : nullptr,
-                        Q ? Q + off * es : nullptr,
-                        pot ? static_cast<char*>(pot) + off * es : nullptr,
-                        force ? static_cast<char*>(force) + 3 * off * es : nullptr,
-                        energy4 ? energy4 + 4 * k : nullptr, batch->branch[batch->branch_of[k]]);
-      off += n[k];
+    if (batch->table) {
+      (void)hipFree(batch->table);
+      batch->table = nullptr;
     }
-    for (int k = 0; k < kBatchBranches; ++k) {
-      (void)hipEventRecord(batch->join[k], batch->branch[k]);
-      (void)hipStreamWaitEvent(batch->capture, batch->join[k], 0);
-    }
-    hipGraph_t graph = nullptr;
-    e = hipStreamEndCapture(batch->capture, &graph);
-    if (s != KPME_SUCCESS) {
-      if (graph) (void)hipGraphDestroy(graph);
-      return s;
-    }
-    if (e != hipSuccess) return from_hip(e, "batch capture");
-    e = hipGraphInstantiate(&batch->exec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    if (e != hipSuccess) {
-      batch->exec = nullptr;
-      return from_hip(e, "graph instantiate");
-    }
+    kpme_status s = batch_record_fused(batch, n, pos, q, pot, force, energy4);
+    if (s == KPME_ERROR_NOT_SUPPORTED) s = batch_record_graph(batch, n, pos, q, pot, force, energy4);
+    if (s != KPME_SUCCESS) return s;
     batch->sig_n = sig;
     std::copy(ptrs, ptrs + 5, batch->sig_ptr);
   }

@@ -3,6 +3,7 @@
 // B-spline form named in Sec. 2.2), and the FP64 energy reduction.
 #include <algorithm>
 
+#include "batch_launch.hpp"
 #include "device_common.hpp"
 #include "kernels.hpp"
 
@@ -191,16 +192,17 @@ __device__ void run_energy_job(const EnergyJob& ej) {
   }
 }
 
+__device__ __forceinline__ void energy_job_body(EnergyJob ej, const Wg) { run_energy_job(ej); }
 __global__ __launch_bounds__(256) void energy_job_kernel(EnergyJob ej) { run_energy_job(ej); }
 
 // Per-workgroup FP64 (sum q, sum q^2) of the scatter.  Every thread calls it.
-__device__ void charge_partials(double s1, double s2, double* qpart) {
+__device__ void charge_partials(double s1, double s2, double* qpart, int blk) {
   __shared__ double red[32];
   double v[2] = {s1, s2};
   block_reduce<2, 2>(v, red);
   if (threadIdx.x == 0) {
-    qpart[2 * blockIdx.x] = v[0];
-    qpart[2 * blockIdx.x + 1] = v[1];
+    qpart[2 * blk] = v[0];
+    qpart[2 * blk + 1] = v[1];
   }
 }
 
@@ -286,16 +288,17 @@ constexpr int kCountPer = 8;      // particles per thread of the LDS-histogram c
 constexpr int kLdsHist = 8192;    // bricks handled with an LDS histogram
 
 template <typename T>
-__global__ __launch_bounds__(256) void bin_count_lds(long n, const T* __restrict__ pos,
+__device__ __forceinline__ void bin_count_lds_body(long n, const T* __restrict__ pos,
                                                      GridGeom g, BinGeom bg,
                                                      int* __restrict__ brick_of,
                                                      int* __restrict__ slot,
-                                                     int* __restrict__ count) {
+                                                     int* __restrict__ count,
+    const Wg wg) {
   __shared__ int hist[kLdsHist];
   const int nb = bg.nbricks;
   for (int b = threadIdx.x; b < nb; b += blockDim.x) hist[b] = 0;
   __syncthreads();
-  const long base = static_cast<long>(blockIdx.x) * blockDim.x * kCountPer;
+  const long base = static_cast<long>(wg.x) * blockDim.x * kCountPer;
   int bid[kCountPer], loc[kCountPer];
 #pragma unroll
   for (int k = 0; k < kCountPer; ++k) {
@@ -335,6 +338,15 @@ __global__ __launch_bounds__(256) void bin_count_lds(long n, const T* __restrict
       slot[i] = hist[bid[k]] + loc[k];
     }
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void bin_count_lds(long n, const T* __restrict__ pos,
+                                                     GridGeom g, BinGeom bg,
+                                                     int* __restrict__ brick_of,
+                                                     int* __restrict__ slot,
+                                                     int* __restrict__ count) {
+  bin_count_lds_body<T>(n, pos, g, bg, brick_of, slot, count, Wg::plain());
 }
 
 template <typename T>
@@ -395,7 +407,7 @@ __global__ __launch_bounds__(1024) void bin_scan(int* __restrict__ count, int nb
 // scatters kBinPer particles per thread; the counts are cleared later, by
 // the spread (one workgroup per brick), for the next binning.
 template <typename T>
-__global__ __launch_bounds__(256) void bin_scan_scatter(long n, const T* __restrict__ pos,
+__device__ __forceinline__ void bin_scan_scatter_body(long n, const T* __restrict__ pos,
                                                         const T* __restrict__ q,
                                                         const int* __restrict__ brick_of,
                                                         const int* __restrict__ slot,
@@ -403,7 +415,8 @@ __global__ __launch_bounds__(256) void bin_scan_scatter(long n, const T* __restr
                                                         int nbricks, int* __restrict__ offset,
                                                         T* __restrict__ sorted,
                                                         int* __restrict__ perm,
-                                                        double* __restrict__ qpart) {
+                                                        double* __restrict__ qpart,
+    const Wg wg) {
   __shared__ int off[kLdsHist + 1];
   __shared__ int wsum[4];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -434,12 +447,12 @@ __global__ __launch_bounds__(256) void bin_scan_scatter(long n, const T* __restr
   for (int b = b0; b < b1; ++b) off[b] += base;
   if (t == 255) off[nbricks] = base + s;  // thread 255's range ends at nbricks
   __syncthreads();
-  if (blockIdx.x == 0)
+  if (wg.x == 0)
     for (int b = t; b <= nbricks; b += 256) offset[b] = off[b];
   double s1 = 0.0, s2 = 0.0;
 #pragma unroll
   for (int k = 0; k < kBinPer; ++k) {
-    const long i = (blockIdx.x * static_cast<long>(kBinPer) + k) * 256 + t;
+    const long i = (wg.x * static_cast<long>(kBinPer) + k) * 256 + t;
     if (i >= n) break;
     const long d = off[brick_of[i]] + slot[i];
     const T qi = q[i];
@@ -451,7 +464,20 @@ __global__ __launch_bounds__(256) void bin_scan_scatter(long n, const T* __restr
     s1 += static_cast<double>(qi);
     s2 += static_cast<double>(qi) * static_cast<double>(qi);
   }
-  if (qpart) charge_partials(s1, s2, qpart);
+  if (qpart) charge_partials(s1, s2, qpart, wg.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void bin_scan_scatter(long n, const T* __restrict__ pos,
+                                                        const T* __restrict__ q,
+                                                        const int* __restrict__ brick_of,
+                                                        const int* __restrict__ slot,
+                                                        const int* __restrict__ count,
+                                                        int nbricks, int* __restrict__ offset,
+                                                        T* __restrict__ sorted,
+                                                        int* __restrict__ perm,
+                                                        double* __restrict__ qpart) {
+  bin_scan_scatter_body<T>(n, pos, q, brick_of, slot, count, nbricks, offset, sorted, perm, qpart, Wg::plain());
 }
 
 template <typename T>
@@ -476,7 +502,7 @@ __global__ __launch_bounds__(256) void bin_scatter(long n, const T* __restrict__
     s1 = static_cast<double>(qi);
     s2 = s1 * s1;
   }
-  if (qpart) charge_partials(s1, s2, qpart);
+  if (qpart) charge_partials(s1, s2, qpart, blockIdx.x);
 }
 
 // Owner-computes spread: one workgroup per grid brick.  It visits the
@@ -502,14 +528,15 @@ static_assert(kHomeThreads % 64 == 0 && kHomeThreads <= 256, "spread_home's laun
 constexpr int kSpreadCand = 1024;  // candidates examined per pass, 256 per wave
 
 template <typename T, int P, bool E8>
-__global__ __launch_bounds__(256) void spread_brick(const T* __restrict__ sorted,
+__device__ __forceinline__ void spread_brick_body(const T* __restrict__ sorted,
                                                     const int* __restrict__ offset,
                                                     const int* __restrict__ nbr,
                                                     T* __restrict__ grid,
                                                     double* __restrict__ part2,
                                                     int* __restrict__ count, GridGeom g,
-                                                    BinGeom bg) {
-  static_assert(P <= 4, "owner-computes spread is for spline orders up to 4");
+                                                    BinGeom bg,
+    const Wg wg) {
+  static_assert(P <= 9, "at most four home bricks per axis (8-point bricks)");
   extern __shared__ __attribute__((aligned(16))) char smem[];
   double* tile = reinterpret_cast<double*>(smem);
   __shared__ int hstart[64], hpre[65];
@@ -518,7 +545,7 @@ __global__ __launch_bounds__(256) void spread_brick(const T* __restrict__ sorted
   const int E0 = E8 ? 8 : bg.edge[0], E1 = E8 ? 8 : bg.edge[1], E2 = E8 ? 8 : bg.edge[2];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   // neighbouring bricks (which read overlapping particle lists) share an XCD
-  const int brick = xcd_order(blockIdx.x, gridDim.x);
+  const int brick = wg_order(wg, wg.x, wg.nx);
   if (threadIdx.x == 0) count[brick] = 0;  // the scatter has read it: ready for the next binning
   int own[3], rest = brick;
   own[2] = rest % bg.nb[2]; rest /= bg.nb[2];
@@ -655,6 +682,17 @@ __global__ __launch_bounds__(256) void spread_brick(const T* __restrict__ sorted
   }
 }
 
+template <typename T, int P, bool E8>
+__global__ __launch_bounds__(256) void spread_brick(const T* __restrict__ sorted,
+                                                    const int* __restrict__ offset,
+                                                    const int* __restrict__ nbr,
+                                                    T* __restrict__ grid,
+                                                    double* __restrict__ part2,
+                                                    int* __restrict__ count, GridGeom g,
+                                                    BinGeom bg) {
+  spread_brick_body<T, P, E8>(sorted, offset, nbr, grid, part2, count, g, bg, Wg::plain());
+}
+
 // Home-computes spread, pass 1: one workgroup (kHomeThreads threads, one
 // particle per thread at a time) per grid brick adds the stencils of
 // the particles binned in that brick into an LDS tile covering the brick and
@@ -740,11 +778,12 @@ __device__ __forceinline__ unsigned long long lanemask_lt() {
 }
 
 template <int P>
-__global__ __launch_bounds__(64 * kMfmaWaves) void spread_home_mfma(const float* __restrict__ sorted,
+__device__ __forceinline__ void spread_home_mfma_body(const float* __restrict__ sorted,
                                                        const int* __restrict__ offset,
                                                        float* __restrict__ tiles,
                                                        int* __restrict__ count, GridGeom g,
-                                                       BinGeom bg) {
+                                                       BinGeom bg,
+    const Wg wg) {
   static_assert(P <= 9, "tile extents must stay within 16 (brick edge 8)");
   static_assert(2 * kMfmaWaves >= 16, "two planes per wave cover a 16-plane tile");
   // padded per-particle rows, in sorted slot order: q wx at its x planes,
@@ -755,7 +794,7 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void spread_home_mfma(const float*
   __shared__ int wcount[4][16];   // per wave, particles per x base
   __shared__ int boff[4][17];     // per wave, first slot of each x base
   __shared__ int bstart[17];      // first slot of each x base in the chunk
-  const int brick = xcd_order(blockIdx.x, gridDim.x);
+  const int brick = wg_order(wg, wg.x, wg.nx);
   if (threadIdx.x == 0) count[brick] = 0;  // the scatter has read it: ready for the next binning
   int own[3], rest = brick;
   own[2] = rest % bg.nb[2]; rest /= bg.nb[2];
@@ -885,6 +924,15 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void spread_home_mfma(const float*
   }
 }
 
+template <int P>
+__global__ __launch_bounds__(64 * kMfmaWaves) void spread_home_mfma(const float* __restrict__ sorted,
+                                                       const int* __restrict__ offset,
+                                                       float* __restrict__ tiles,
+                                                       int* __restrict__ count, GridGeom g,
+                                                       BinGeom bg) {
+  spread_home_mfma_body<P>(sorted, offset, tiles, count, g, bg, Wg::plain());
+}
+
 // Pass 2, persistent form for grids where every owner brick is reached by
 // exactly two home bricks per axis (itself and the next one, periodically)
 // and every tile extent is at most the axis length (BinGeom::two_homes):
@@ -905,14 +953,15 @@ int combine_workgroups(int nbricks) {
 }
 
 template <typename T, int P>
-__global__ __launch_bounds__(kCombineThreads) void spread_combine_pf(
+__device__ __forceinline__ void spread_combine_pf_body(
     const T* __restrict__ tiles, T* __restrict__ grid, double* __restrict__ part2, GridGeom g,
-    BinGeom bg) {
+    BinGeom bg,
+    const Wg wg) {
   __shared__ double red[32];
-  const int wl = xcd_order(blockIdx.x, gridDim.x);
+  const int wl = wg_order(wg, wg.x, wg.nx);
   const int nb = bg.nbricks;
-  const int b_begin = static_cast<int>(static_cast<long>(wl) * nb / gridDim.x);
-  const int b_end = static_cast<int>(static_cast<long>(wl + 1) * nb / gridDim.x);
+  const int b_begin = static_cast<int>(static_cast<long>(wl) * nb / wg.nx);
+  const int b_end = static_cast<int>(static_cast<long>(wl + 1) * nb / wg.nx);
   int H[3];
 #pragma unroll
   for (int j = 0; j < 3; ++j) H[j] = bg.edge[j] + P - 1;
@@ -997,9 +1046,16 @@ __global__ __launch_bounds__(kCombineThreads) void spread_combine_pf(
   double r[2] = {s, m};
   block_reduce<1, 2>(r, red);
   if (threadIdx.x == 0) {
-    part2[2 * blockIdx.x] = r[0];
-    part2[2 * blockIdx.x + 1] = r[1];
+    part2[2 * wg.x] = r[0];
+    part2[2 * wg.x + 1] = r[1];
   }
+}
+
+template <typename T, int P>
+__global__ __launch_bounds__(kCombineThreads) void spread_combine_pf(
+    const T* __restrict__ tiles, T* __restrict__ grid, double* __restrict__ part2, GridGeom g,
+    BinGeom bg) {
+  spread_combine_pf_body<T, P>(tiles, grid, part2, g, bg, Wg::plain());
 }
 
 // Pass 2: one workgroup per grid brick sums, for each of its points and in a
@@ -1117,20 +1173,21 @@ __global__ __launch_bounds__(512) void spread_combine(const T* __restrict__ tile
 // values); results are written back to the caller's order through perm.
 // With an energy job, one extra last workgroup runs it.
 template <typename T, int P>
-__global__ __launch_bounds__(256) void gather_sorted(long n, const T* __restrict__ sorted,
+__device__ __forceinline__ void gather_sorted_body(long n, const T* __restrict__ sorted,
                                                      const int* __restrict__ perm,
                                                      const T* __restrict__ grid,
                                                      T* __restrict__ pot,
                                                      T* __restrict__ force,
-                                                     EnergyJob ej, GridGeom g) {
+                                                     EnergyJob ej, GridGeom g,
+    const Wg wg) {
   // with an energy job, one extra last workgroup runs it beside the gather
-  const int nwork = gridDim.x - (ej.e4 ? 1 : 0);
-  if (static_cast<int>(blockIdx.x) == nwork) {
+  const int nwork = wg.nx - (ej.e4 ? 1 : 0);
+  if (static_cast<int>(wg.x) == nwork) {
     run_energy_job(ej);
     return;
   }
   // neighbouring particle blocks (neighbouring bricks) share an XCD's L2
-  const int blk = xcd_order(blockIdx.x, nwork);
+  const int blk = wg_order(wg, wg.x, nwork);
   const long s = blk * static_cast<long>(blockDim.x) + threadIdx.x;
   if (s < n) {
     T w[3][P], dw[3][P];
@@ -1196,26 +1253,37 @@ __global__ __launch_bounds__(256) void gather_sorted(long n, const T* __restrict
   }
 }
 
+template <typename T, int P>
+__global__ __launch_bounds__(256) void gather_sorted(long n, const T* __restrict__ sorted,
+                                                     const int* __restrict__ perm,
+                                                     const T* __restrict__ grid,
+                                                     T* __restrict__ pot,
+                                                     T* __restrict__ force,
+                                                     EnergyJob ej, GridGeom g) {
+  gather_sorted_body<T, P>(n, sorted, perm, grid, pot, force, ej, g, Wg::plain());
+}
+
 // Gather in binned order with P lanes per particle (spline orders up to 4):
 // lane a of a particle's group takes the stencil plane k1 = base0 - a (P^2
 // loads), and the group's plane sums are added by shuffles.  Four times the
 // threads of gather_sorted keep more loads in flight.  Partial sums per
 // workgroup as in gather_sorted.
 template <typename T, int P>
-__global__ __launch_bounds__(256) void gather_sorted_planes(long n, const T* __restrict__ sorted,
+__device__ __forceinline__ void gather_sorted_planes_body(long n, const T* __restrict__ sorted,
                                                             const int* __restrict__ perm,
                                                             const T* __restrict__ grid,
                                                             T* __restrict__ pot,
                                                             T* __restrict__ force,
-                                                            EnergyJob ej, GridGeom g) {
+                                                            EnergyJob ej, GridGeom g,
+    const Wg wg) {
   static_assert(P == 4, "one lane per plane, four lanes per particle");
   // with an energy job, one extra last workgroup runs it beside the gather
-  const int nwork = gridDim.x - (ej.e4 ? 1 : 0);
-  if (static_cast<int>(blockIdx.x) == nwork) {
+  const int nwork = wg.nx - (ej.e4 ? 1 : 0);
+  if (static_cast<int>(wg.x) == nwork) {
     run_energy_job(ej);
     return;
   }
-  const int blk = xcd_order(blockIdx.x, nwork);
+  const int blk = wg_order(wg, wg.x, nwork);
   const long s = (blk * static_cast<long>(blockDim.x) + threadIdx.x) / P;
   const int a = threadIdx.x % P;
   T phi = 0, g0 = 0, g1 = 0, g2 = 0;
@@ -1288,6 +1356,16 @@ __global__ __launch_bounds__(256) void gather_sorted_planes(long n, const T* __r
       force[3 * i + 2] = -qi * g2 * static_cast<T>(g.K[2] * g.invL[2]);
     }
   }
+}
+
+template <typename T, int P>
+__global__ __launch_bounds__(256) void gather_sorted_planes(long n, const T* __restrict__ sorted,
+                                                            const int* __restrict__ perm,
+                                                            const T* __restrict__ grid,
+                                                            T* __restrict__ pot,
+                                                            T* __restrict__ force,
+                                                            EnergyJob ej, GridGeom g) {
+  gather_sorted_planes_body<T, P>(n, sorted, perm, grid, pot, force, ej, g, Wg::plain());
 }
 
 // The binned record (x, y, z, q) of slot s in one 16-byte load (float) or two
@@ -1446,22 +1524,23 @@ __global__ __launch_bounds__(kGatherThreads) void gather_brick(const T* __restri
 // the range are staged in LDS once.  Results and summation order per
 // particle are those of gather_brick.
 template <typename T, int P>
-__global__ __launch_bounds__(kGatherThreads) void gather_brick_pf(
+__device__ __forceinline__ void gather_brick_pf_body(
     const T* __restrict__ sorted, const int* __restrict__ offset, const int* __restrict__ perm,
     const T* __restrict__ grid, T* __restrict__ pot, T* __restrict__ force, EnergyJob ej,
-    GridGeom g, BinGeom bg) {
+    GridGeom g, BinGeom bg,
+    const Wg wg) {
   static_assert(P <= 9, "rows of at most 16 values");
   constexpr int HM = 8 + P - 1;                       // largest tile extent (edge <= 8)
   constexpr int kPfRows = (HM * HM + kGatherThreads / 16 - 1) / (kGatherThreads / 16);
   extern __shared__ __attribute__((aligned(16))) char smem[];
   T* tile = reinterpret_cast<T*>(smem);
   __shared__ int offs[kGatherMaxBricks + 1];
-  const int nwork = gridDim.x - (ej.e4 ? 1 : 0);
-  if (static_cast<int>(blockIdx.x) == nwork) {
+  const int nwork = wg.nx - (ej.e4 ? 1 : 0);
+  if (static_cast<int>(wg.x) == nwork) {
     run_energy_job(ej);
     return;
   }
-  const int wl = xcd_order(blockIdx.x, nwork);
+  const int wl = wg_order(wg, wg.x, nwork);
   const int nb = bg.nbricks;
   const int b_begin = static_cast<int>(static_cast<long>(wl) * nb / nwork);
   const int b_end = static_cast<int>(static_cast<long>(wl + 1) * nb / nwork);
@@ -1601,6 +1680,14 @@ __global__ __launch_bounds__(kGatherThreads) void gather_brick_pf(
     }
     __syncthreads();   // every tile read done before the next store
   }
+}
+
+template <typename T, int P>
+__global__ __launch_bounds__(kGatherThreads) void gather_brick_pf(
+    const T* __restrict__ sorted, const int* __restrict__ offset, const int* __restrict__ perm,
+    const T* __restrict__ grid, T* __restrict__ pot, T* __restrict__ force, EnergyJob ej,
+    GridGeom g, BinGeom bg) {
+  gather_brick_pf_body<T, P>(sorted, offset, perm, grid, pot, force, ej, g, bg, Wg::plain());
 }
 
 // sorted2[d] = (x, y, z, g[perm[d]]): the binned positions with a second
@@ -1824,17 +1911,21 @@ hipError_t bin_t(const GridGeom& g, const Bins& b, int64_t n, const void* pos, h
     if (b.geom.nbricks <= kLdsHist) {
       const long per = 256L * kCountPer;
       const unsigned blocks = static_cast<unsigned>((n + per - 1) / per);
-      hipLaunchKernelGGL((bin_count_lds<T>), dim3(blocks), dim3(256), 0, st,
-                         static_cast<long>(n), static_cast<const T*>(pos), g, b.geom,
-                         b.brick_of, b.slot, b.count);
+      hipError_t e = launch_or_record<256, bin_count_lds_body<T>>(
+          LS_BIN_COUNT, bin_count_lds<T>, dim3(blocks), 0, st, static_cast<long>(n),
+          static_cast<const T*>(pos), g, b.geom, b.brick_of, b.slot, b.count);
+      if (e != hipSuccess) return e;
     } else {
+      if (record_unsupported()) return hipSuccess;
       const unsigned blocks = static_cast<unsigned>((n + 255) / 256);
       hipLaunchKernelGGL((bin_count<T>), dim3(blocks), dim3(256), 0, st, static_cast<long>(n),
                          static_cast<const T*>(pos), g, b.geom, b.brick_of, b.slot, b.count);
     }
   }
-  if (!scan_in_scatter(b, n))
+  if (!scan_in_scatter(b, n)) {
+    if (record_unsupported()) return hipSuccess;
     hipLaunchKernelGGL(bin_scan, dim3(1), dim3(1024), 0, st, b.count, b.geom.nbricks, b.offset);
+  }
   return hipGetLastError();
 }
 
@@ -1844,13 +1935,15 @@ hipError_t scatter_t(const Bins& b, int64_t n, const void* pos, const void* q, d
   if (scan_in_scatter(b, n)) {
     // at least one workgroup: it stores the offsets also for n = 0
     const unsigned blocks = static_cast<unsigned>(scatter_blocks(n));
-    hipLaunchKernelGGL((bin_scan_scatter<T>), dim3(blocks), dim3(256), 0, st,
-                       static_cast<long>(n), static_cast<const T*>(pos), static_cast<const T*>(q),
-                       b.brick_of, b.slot, b.count, b.geom.nbricks, b.offset,
-                       static_cast<T*>(b.sorted), b.perm, qpart);
-    return hipGetLastError();
+    return launch_or_record<256, bin_scan_scatter_body<T>>(
+        LS_BIN_SCATTER, bin_scan_scatter<T>, dim3(blocks), 0, st, static_cast<long>(n),
+        static_cast<const T*>(pos), static_cast<const T*>(q),
+        static_cast<const int*>(b.brick_of), static_cast<const int*>(b.slot),
+        static_cast<const int*>(b.count), b.geom.nbricks, b.offset, static_cast<T*>(b.sorted),
+        b.perm, qpart);
   }
   if (n == 0) return hipSuccess;
+  if (record_unsupported()) return hipSuccess;
   const unsigned blocks = static_cast<unsigned>((n + 255) / 256);
   hipLaunchKernelGGL((bin_scatter<T>), dim3(blocks), dim3(256), 0, st, static_cast<long>(n),
                      static_cast<const T*>(pos), static_cast<const T*>(q), b.brick_of, b.slot,
@@ -1865,23 +1958,34 @@ template <typename T, int P>
 hipError_t spread_brick_p(const GridGeom& g, const Bins& b, const void* src, void* grid,
                           double* part2, hipStream_t st) {
   const T* srt = static_cast<const T*>(src ? src : b.sorted);
-  if constexpr (P <= 4) {
+  bool owner = P <= 4;
+  if constexpr (P <= 9) owner = owner || b.geom.sparse;
+  if (owner) {
     const size_t lds = sizeof(double) * b.geom.edge[0] * b.geom.edge[1] * b.geom.edge[2];
     const bool e8 = b.geom.edge[0] == 8 && b.geom.edge[1] == 8 && b.geom.edge[2] == 8;
-    if (e8)
-      hipLaunchKernelGGL((spread_brick<T, P, true>), dim3(b.geom.nbricks), dim3(256), lds, st,
-                         srt, b.offset, b.nbr, static_cast<T*>(grid), part2, b.count, g, b.geom);
-    else
-      hipLaunchKernelGGL((spread_brick<T, P, false>), dim3(b.geom.nbricks), dim3(256), lds, st,
-                         srt, b.offset, b.nbr, static_cast<T*>(grid), part2, b.count, g, b.geom);
-    return hipGetLastError();
+    const int* off = b.offset;
+    const int* nbr = b.nbr;
+    if constexpr (P <= 9) {
+      if (e8)
+        return launch_or_record<256, spread_brick_body<T, P, true>>(
+            LS_SPREAD, spread_brick<T, P, true>, dim3(b.geom.nbricks), lds, st, srt, off, nbr,
+            static_cast<T*>(grid), part2, b.count, g, b.geom);
+      return launch_or_record<256, spread_brick_body<T, P, false>>(
+          LS_SPREAD, spread_brick<T, P, false>, dim3(b.geom.nbricks), lds, st, srt, off, nbr,
+          static_cast<T*>(grid), part2, b.count, g, b.geom);
+    }
+    return hipErrorInvalidValue;
   }
   const int ntile = (b.geom.edge[0] + P - 1) * (b.geom.edge[1] + P - 1) * (b.geom.edge[2] + P - 1);
   if constexpr (sizeof(T) == 4 && P <= 9) {
     // float grids: the matrix-core tile spread (every brick edge <= 8)
-    hipLaunchKernelGGL((spread_home_mfma<P>), dim3(b.geom.nbricks), dim3(64 * kMfmaWaves), 0, st, srt,
-                       b.offset, static_cast<float*>(b.tiles), b.count, g, b.geom);
+    const int* off = b.offset;
+    hipError_t e = launch_or_record<64 * kMfmaWaves, spread_home_mfma_body<P>>(
+        LS_SPREAD, spread_home_mfma<P>, dim3(b.geom.nbricks), 0, st, srt, off,
+        static_cast<float*>(b.tiles), b.count, g, b.geom);
+    if (e != hipSuccess) return e;
   } else {
+    if (record_unsupported()) return hipSuccess;
     hipLaunchKernelGGL((spread_home<T, P>), dim3(b.geom.nbricks), dim3(kHomeThreads),
                        sizeof(double) * ntile, st, srt, b.offset, static_cast<T*>(b.tiles),
                        b.count, g, b.geom);
@@ -1891,10 +1995,11 @@ hipError_t spread_brick_p(const GridGeom& g, const Bins& b, const void* src, voi
     if ((b.geom.nbricks + nw - 1) / nw > kCombineMaxBricks ||
         b.geom.edge[0] * b.geom.edge[1] * b.geom.edge[2] > kCombineThreads)
       return hipErrorInvalidValue;
-    hipLaunchKernelGGL((spread_combine_pf<T, P>), dim3(nw), dim3(kCombineThreads), 0, st,
-                       static_cast<const T*>(b.tiles), static_cast<T*>(grid), part2, g, b.geom);
-    return hipGetLastError();
+    return launch_or_record<kCombineThreads, spread_combine_pf_body<T, P>>(
+        LS_COMBINE, spread_combine_pf<T, P>, dim3(nw), 0, st, static_cast<const T*>(b.tiles),
+        static_cast<T*>(grid), part2, g, b.geom);
   }
+  if (record_unsupported()) return hipSuccess;
   hipLaunchKernelGGL((spread_combine<T, P>), dim3(b.geom.nbricks), dim3(512), 0, st,
                      static_cast<const T*>(b.tiles), b.nbr, static_cast<T*>(grid), part2, g,
                      b.geom);
@@ -1908,38 +2013,40 @@ hipError_t spread_brick_p(const GridGeom& g, const Bins& b, const void* src, voi
 template <typename T, int P>
 hipError_t gather_brick_p(const GridGeom& g, const Bins& b, int64_t n, const void* grid,
                           void* pot, void* force, const EnergyJob& ej, hipStream_t st) {
+  if (P < 4 || (P > 4 && (sizeof(T) == 8 || b.geom.sparse))) {
+    // direct stencil reads per particle (low orders, FP64, or few particles
+    // per brick)
+    const unsigned blocks = static_cast<unsigned>((n + 255) / 256) + (ej.e4 ? 1 : 0);
+    return launch_or_record<256, gather_sorted_body<T, P>>(
+        LS_GATHER, gather_sorted<T, P>, dim3(blocks), 0, st, static_cast<long>(n),
+        static_cast<const T*>(b.sorted), static_cast<const int*>(b.perm),
+        static_cast<const T*>(grid), static_cast<T*>(pot), static_cast<T*>(force), ej, g);
+  }
   if constexpr (sizeof(T) == 4 && P > 4 && P <= 9) {
     const int ntile = (b.geom.edge[0] + P - 1) * (b.geom.edge[1] + P - 1) * (b.geom.edge[2] + P - 1);
     const int nw = gather_pf_workgroups(b.geom.nbricks);
     if ((b.geom.nbricks + nw - 1) / nw > kGatherMaxBricks) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((gather_brick_pf<T, P>), dim3(nw + (ej.e4 ? 1 : 0)),
-                       dim3(kGatherThreads), sizeof(T) * ntile, st,
-                       static_cast<const T*>(b.sorted), b.offset, b.perm,
-                       static_cast<const T*>(grid), static_cast<T*>(pot), static_cast<T*>(force),
-                       ej, g, b.geom);
-    return hipGetLastError();
+    return launch_or_record<kGatherThreads, gather_brick_pf_body<T, P>>(
+        LS_GATHER, gather_brick_pf<T, P>, dim3(nw + (ej.e4 ? 1 : 0)), sizeof(T) * ntile, st,
+        static_cast<const T*>(b.sorted), static_cast<const int*>(b.offset),
+        static_cast<const int*>(b.perm), static_cast<const T*>(grid), static_cast<T*>(pot),
+        static_cast<T*>(force), ej, g, b.geom);
   }
-  if (sizeof(T) == 4 && P > 4) {
-    const int ntile = (b.geom.edge[0] + P - 1) * (b.geom.edge[1] + P - 1) * (b.geom.edge[2] + P - 1);
-    hipLaunchKernelGGL((gather_brick<T, P>), dim3(b.geom.nbricks + (ej.e4 ? 1 : 0)),
-                       dim3(kGatherThreads),
-                       sizeof(T) * ntile,
-                       st, static_cast<const T*>(b.sorted), b.offset, b.perm,
-                       static_cast<const T*>(grid), static_cast<T*>(pot), static_cast<T*>(force),
-                       ej, g, b.geom);
-  } else if (P == 4) {
+  if (P == 4) {
     const unsigned blocks = static_cast<unsigned>((n + 63) / 64) + (ej.e4 ? 1 : 0);
-    hipLaunchKernelGGL((gather_sorted_planes<T, 4>), dim3(blocks), dim3(256), 0, st,
-                       static_cast<long>(n), static_cast<const T*>(b.sorted), b.perm,
-                       static_cast<const T*>(grid), static_cast<T*>(pot), static_cast<T*>(force),
-                       ej, g);
-  } else {
-    const unsigned blocks = static_cast<unsigned>((n + 255) / 256) + (ej.e4 ? 1 : 0);
-    hipLaunchKernelGGL((gather_sorted<T, P>), dim3(blocks), dim3(256), 0, st,
-                       static_cast<long>(n), static_cast<const T*>(b.sorted), b.perm,
-                       static_cast<const T*>(grid), static_cast<T*>(pot), static_cast<T*>(force),
-                       ej, g);
+    return launch_or_record<256, gather_sorted_planes_body<T, 4>>(
+        LS_GATHER, gather_sorted_planes<T, 4>, dim3(blocks), 0, st, static_cast<long>(n),
+        static_cast<const T*>(b.sorted), static_cast<const int*>(b.perm),
+        static_cast<const T*>(grid), static_cast<T*>(pot), static_cast<T*>(force), ej, g);
   }
+  // FP32, P > 9: the brick tile without prefetch
+  if (record_unsupported()) return hipSuccess;
+  const int ntile = (b.geom.edge[0] + P - 1) * (b.geom.edge[1] + P - 1) * (b.geom.edge[2] + P - 1);
+  hipLaunchKernelGGL((gather_brick<T, P>), dim3(b.geom.nbricks + (ej.e4 ? 1 : 0)),
+                     dim3(kGatherThreads), sizeof(T) * ntile, st,
+                     static_cast<const T*>(b.sorted), b.offset, b.perm,
+                     static_cast<const T*>(grid), static_cast<T*>(pot), static_cast<T*>(force),
+                     ej, g, b.geom);
   return hipGetLastError();
 }
 
@@ -1949,7 +2056,7 @@ hipError_t gather_brick_p(const GridGeom& g, const Bins& b, int64_t n, const voi
 // Number of (sum, max) pairs the binned spread writes: one per workgroup of
 // the persistent combine, else one per brick.
 int spread_partials(const BinGeom& bg, int p) {
-  return (p > 4 && bg.two_homes) ? combine_workgroups(bg.nbricks) : bg.nbricks;
+  return (p > 4 && !bg.sparse && bg.two_homes) ? combine_workgroups(bg.nbricks) : bg.nbricks;
 }
 
 // Number of (sum q, sum q^2) pairs the scatter writes.
@@ -2041,8 +2148,7 @@ hipError_t launch_gather_backward(int prec, const GridGeom& g, const Bins& b, in
 
 hipError_t launch_energy_job(const EnergyJob& ej, hipStream_t st) {
   if (!ej.e4) return hipSuccess;
-  hipLaunchKernelGGL(energy_job_kernel, dim3(1), dim3(256), 0, st, ej);
-  return hipGetLastError();
+  return launch_or_record<256, energy_job_body>(LS_GATHER, energy_job_kernel, dim3(1), 0, st, ej);
 }
 
 hipError_t launch_energy(int prec, int64_t n, const void* q, const void* pot, double beta,

@@ -23,6 +23,7 @@
 #include <cmath>
 #include <vector>
 
+#include "batch_launch.hpp"
 #include "device_common.hpp"
 #include "kernels.hpp"
 #include "rect.hpp"
@@ -135,6 +136,7 @@ void rect_destroy_handle(void* handle) {
 }
 
 hipError_t launch_rect_apply(const RectArgs& a, hipStream_t st) {
+  if (record_unsupported()) return hipSuccess;
   rocblas_handle h = static_cast<rocblas_handle>(a.handle);
   rocblas_status s = rocblas_set_stream(h, st);
   const bool f64 = a.fp64;
@@ -163,6 +165,7 @@ hipError_t launch_rect_apply(const RectArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_rect_finalize(const RectArgs& a, hipStream_t st) {
+  if (record_unsupported()) return hipSuccess;
   dim3 gf((a.K[1] + 31) / 32, (a.K[2] + 31) / 32, a.K[0]);
   if (a.fp64)
     hipLaunchKernelGGL((rect_finalize<double>), gf, dim3(256), 0, st, static_cast<double*>(a.Phi),

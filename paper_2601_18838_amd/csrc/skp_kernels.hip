@@ -20,6 +20,7 @@
 // Precisions: FP64 and FP32 use the 16x16x4 MFMAs; BF16X3 splits every
 // operand into bf16 hi + lo and issues hi*hi + hi*lo + lo*hi on the
 // 16x16x32 bf16 MFMA with FP32 accumulation.
+#include "batch_launch.hpp"
 #include "device_common.hpp"
 #include "kernels.hpp"
 
@@ -86,19 +87,20 @@ __device__ float grid_scalars(const double* __restrict__ part, int np, double* _
 }
 
 template <typename H>
-__global__ __launch_bounds__(64) void stage1_x3(
+__device__ __forceinline__ void stage1_x3_body(
     const float* __restrict__ Q, const H* __restrict__ Chi, const H* __restrict__ Clo,
     H* __restrict__ Yhi, H* __restrict__ Ylo, int K1, int K2, int K3, int K3P, int K2P,
     long slab, int nrows, const double* __restrict__ part, int np, double* __restrict__ sums,
-    int scale_q, float sy) {
+    int scale_q, float sy,
+    const Wg wg) {
   typedef typename HVec<H>::v8 v8;
   const int lane = threadIdx.x, q = lane >> 4, m = lane & 15;
   // logical order: the n splits of one position tile are consecutive (and so
   // share an XCD and its L2 copy of the Q tile)
-  const int L = xcd_order(linear_block(), num_blocks());
-  const long p0 = static_cast<long>(L / gridDim.x) * 64;
-  const int nt0 = (L % gridDim.x) * kS1Tiles;
-  const float sq = grid_scalars(part, np, sums, scale_q != 0, linear_block() == 0);
+  const int L = wg_order(wg, wg.linear(), wg.count());
+  const long p0 = static_cast<long>(L / wg.nx) * 64;
+  const int nt0 = (L % wg.nx) * kS1Tiles;
+  const float sq = grid_scalars(part, np, sums, scale_q != 0, wg.linear() == 0);
   const bool vec4 = (K3 & 3) == 0;  // rows 16-byte aligned, 4-float groups all in or out
   // Q rows of this lane's A-operand rows: tile u holds p = p0 + 16 (m / 4) + 4 u + m % 4
   const float* row[4];
@@ -205,6 +207,15 @@ __global__ __launch_bounds__(64) void stage1_x3(
   }
 }
 
+template <typename H>
+__global__ __launch_bounds__(64) void stage1_x3(
+    const float* __restrict__ Q, const H* __restrict__ Chi, const H* __restrict__ Clo,
+    H* __restrict__ Yhi, H* __restrict__ Ylo, int K1, int K2, int K3, int K3P, int K2P,
+    long slab, int nrows, const double* __restrict__ part, int np, double* __restrict__ sums,
+    int scale_q, float sy) {
+  stage1_x3_body<H>(Q, Chi, Clo, Yhi, Ylo, K1, K2, K3, K3P, K2P, slab, nrows, part, np, sums, scale_q, sy, Wg::plain());
+}
+
 // Stage 1, split precision, K3P <= 128 (NK = K3P / 32 chunks): a workgroup
 // of four waves takes one tile of 64 positions; its Q rows are split into
 // hi/lo once, into LDS, and every wave keeps the A fragments of the whole K
@@ -215,18 +226,19 @@ __global__ __launch_bounds__(64) void stage1_x3(
 // as in stage1_x3.
 
 template <typename H, int NK>
-__global__ __launch_bounds__(256) void stage1_x3_lds(
+__device__ __forceinline__ void stage1_x3_lds_body(
     const float* __restrict__ Q, const H* __restrict__ Chi, const H* __restrict__ Clo,
     H* __restrict__ Yhi, H* __restrict__ Ylo, int K1, int K2, int K3, int K2P, long slab,
     int nrows, const double* __restrict__ part, int np, double* __restrict__ sums, int scale_q,
-    float sy) {
+    float sy,
+    const Wg wg) {
   typedef typename HVec<H>::v8 v8;
   constexpr int K3P = 32 * NK, QSTR = K3P + 8;
   __shared__ __attribute__((aligned(16))) H Qh[64 * QSTR], Ql[64 * QSTR];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, q = lane >> 4, m = lane & 15;
   // logical order: the splits of one position tile are consecutive (one XCD)
-  const int L = xcd_order(linear_block(), num_blocks());
-  const int nsplit = gridDim.x;
+  const int L = wg_order(wg, wg.linear(), wg.count());
+  const int nsplit = wg.nx;
   const long p0 = static_cast<long>(L / nsplit) * 64;
   const int split = L % nsplit;
   // Q tile (row r = p - p0, zero outside the grid and for k >= K3) into
@@ -253,7 +265,7 @@ __global__ __launch_bounds__(256) void stage1_x3_lds(
       for (int h = 0; h < 4; ++h) x[it][h] = (valid && k + h < K3) ? row[k + h] : 0.f;
     }
   }
-  const float sq = grid_scalars(part, np, sums, scale_q != 0, linear_block() == 0);
+  const float sq = grid_scalars(part, np, sums, scale_q != 0, wg.linear() == 0);
   // scaled and split into LDS hi/lo
 #pragma unroll
   for (int it = 0; it < QIT; ++it) {
@@ -338,6 +350,15 @@ __global__ __launch_bounds__(256) void stage1_x3_lds(
   }
 }
 
+template <typename H, int NK>
+__global__ __launch_bounds__(256) void stage1_x3_lds(
+    const float* __restrict__ Q, const H* __restrict__ Chi, const H* __restrict__ Clo,
+    H* __restrict__ Yhi, H* __restrict__ Ylo, int K1, int K2, int K3, int K2P, long slab,
+    int nrows, const double* __restrict__ part, int np, double* __restrict__ sums, int scale_q,
+    float sy) {
+  stage1_x3_lds_body<H, NK>(Q, Chi, Clo, Yhi, Ylo, K1, K2, K3, K2P, slab, nrows, part, np, sums, scale_q, sy, Wg::plain());
+}
+
 // Stage 1, FP32 / FP64 (16x16x4 MFMA).  C: [nrows][K3P]; Y: [nrows][slab].
 template <typename T>
 __global__ __launch_bounds__(256) void stage1_k4(const T* __restrict__ Q,
@@ -410,12 +431,12 @@ __global__ __launch_bounds__(256) void stage1_k4(const T* __restrict__ Q,
 // accumulator registers.  K1P = 128 runs with one wave per SIMD, which may
 // then use the full register file.
 template <typename H, int RT, int NKC, int CT, int NS>
-__global__ __launch_bounds__(64 * (2 * NKC / CT) * NS)
-__attribute__((amdgpu_waves_per_eu(RT >= 8 ? 1 : 2))) void stage2_x3(
+__device__ __forceinline__ void stage2_x3_body(
     const H* __restrict__ Yhi, const H* __restrict__ Ylo, const H* __restrict__ vec,
     const int* __restrict__ step_term, const int* __restrict__ step_group,
     const int* __restrict__ step_begin, float* __restrict__ Phi_part, int K1, int K2, int K3,
-    float st) {
+    float st,
+    const Wg wg) {
   typedef typename HVec<H>::v8 v8;
   typedef typename HVec<H>::v4 v4;
   static_assert((2 * NKC) % CT == 0, "column tiles must divide K2P / 16");
@@ -433,8 +454,8 @@ __attribute__((amdgpu_waves_per_eu(RT >= 8 ? 1 : 2))) void stage2_x3(
   H* vbase = Ysl + K1P * YSTR;                  // [NS][2][tsz]
   // logical order: the term ranges of one slab are consecutive (one XCD and
   // L2 for the slab's Y planes)
-  const int L = xcd_order(linear_block(), num_blocks());
-  const int s = L / gridDim.y, part = L % gridDim.y;
+  const int L = wg_order(wg, wg.linear(), wg.count());
+  const int s = L / wg.ny, part = L % wg.ny;
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int lane = tid & 63, wave = tid >> 6, q = lane >> 4, m = lane & 15;
   const int strm = wave / WPS, cw = wave - strm * WPS, stid = tid - strm * STHR;
@@ -678,6 +699,16 @@ __attribute__((amdgpu_waves_per_eu(RT >= 8 ? 1 : 2))) void stage2_x3(
     }
 }
 
+template <typename H, int RT, int NKC, int CT, int NS>
+__global__ __launch_bounds__(64 * (2 * NKC / CT) * NS)
+__attribute__((amdgpu_waves_per_eu(RT >= 8 ? 1 : 2))) void stage2_x3(
+    const H* __restrict__ Yhi, const H* __restrict__ Ylo, const H* __restrict__ vec,
+    const int* __restrict__ step_term, const int* __restrict__ step_group,
+    const int* __restrict__ step_begin, float* __restrict__ Phi_part, int K1, int K2, int K3,
+    float st) {
+  stage2_x3_body<H, RT, NKC, CT, NS>(Yhi, Ylo, vec, step_term, step_group, step_begin, Phi_part, K1, K2, K3, st, Wg::plain());
+}
+
 // Stage 2, FP32 / FP64 with the 16x16x4 MFMAs.  The factors are symmetric,
 
 // Stage 2, FP32 / FP64 with the 16x16x4 MFMAs.  The factors are symmetric,
@@ -766,16 +797,17 @@ __global__ __launch_bounds__(512) void stage2_k4(
 // With epart, the workgroup also writes the FP64 sum of Q * Phi over the
 // values it stores (the reciprocal energy is half the total).
 template <typename A, typename O>
-__global__ __launch_bounds__(256) void finalize(const A* __restrict__ part, int nparts,
+__device__ __forceinline__ void finalize_body(const A* __restrict__ part, int nparts,
                                                 O* __restrict__ Phi, int K1, int K2,
                                                 int K3, const double* __restrict__ sumQ,
                                                 double c0, const double* __restrict__ qscale,
                                                 double const_scale, const O* __restrict__ Q,
-                                                double* __restrict__ epart) {
+                                                double* __restrict__ epart,
+    const Wg wg) {
   __shared__ A tile[32][33];
   __shared__ double red[16];
   double e = 0.0;
-  const int k1 = blockIdx.z, k2b = blockIdx.x * 32, k3b = blockIdx.y * 32;
+  const int k1 = wg.z, k2b = wg.x * 32, k3b = wg.y * 32;
   const int t = threadIdx.x;
   const long pstride = static_cast<long>(K3) * K1 * K2;
   const bool vec = sizeof(A) == 4 && (K2 & 3) == 0 && (K3 & 3) == 0 && k2b + 32 <= K2 &&
@@ -835,8 +867,18 @@ __global__ __launch_bounds__(256) void finalize(const A* __restrict__ part, int 
   if (epart) {
     double v[1] = {e};
     block_reduce<1, 1>(v, red);
-    if (t == 0) epart[(static_cast<long>(blockIdx.z) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = v[0];
+    if (t == 0) epart[(static_cast<long>(wg.z) * wg.ny + wg.y) * wg.nx + wg.x] = v[0];
   }
+}
+
+template <typename A, typename O>
+__global__ __launch_bounds__(256) void finalize(const A* __restrict__ part, int nparts,
+                                                O* __restrict__ Phi, int K1, int K2,
+                                                int K3, const double* __restrict__ sumQ,
+                                                double c0, const double* __restrict__ qscale,
+                                                double const_scale, const O* __restrict__ Q,
+                                                double* __restrict__ epart) {
+  finalize_body<A, O>(part, nparts, Phi, K1, K2, K3, sumQ, c0, qscale, const_scale, Q, epart, Wg::plain());
 }
 
 }  // namespace
@@ -870,8 +912,9 @@ __global__ __launch_bounds__(256) void sum_partial(const T* __restrict__ x, long
 // out[0] = sum; out[1] = 2^(13 - floor(log2 max|x|)), the power of two that
 // brings the largest grid value into [2^13, 2^14) for the FP16X3 split
 // (1 for an all-zero or non-finite grid).
-__global__ __launch_bounds__(256) void sum_final(const double* __restrict__ part, int np,
-                                                 double* __restrict__ out) {
+__device__ __forceinline__ void sum_final_body(const double* __restrict__ part, int np,
+                                                 double* __restrict__ out,
+    const Wg wg) {
   __shared__ double red[32];
   double v[2] = {0.0, 0.0};
   for (int i0 = threadIdx.x; i0 < np; i0 += 8 * 256) {  // eight pairs in flight
@@ -895,6 +938,11 @@ __global__ __launch_bounds__(256) void sum_final(const double* __restrict__ part
   }
 }
 
+__global__ __launch_bounds__(256) void sum_final(const double* __restrict__ part, int np,
+                                                 double* __restrict__ out) {
+  sum_final_body(part, np, out, Wg::plain());
+}
+
 template <typename K>
 hipError_t set_lds(K kernel, size_t bytes) {
   return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
@@ -910,15 +958,28 @@ hipError_t launch_s2_x3(const SkpArgs& a, hipStream_t st, bool prep) {
   constexpr int CT = x3_ct(K1P, K2P), NS = x3_streams(K1P, K2P);
   const size_t tsz = 2 * static_cast<size_t>(x3_plane(K1P, K2P));
   const size_t lds = sizeof(H) * (2 * static_cast<size_t>(K1P) * K2P + 2 * NS * tsz);
-  if (prep) return set_lds(stage2_x3<H, RT, NKC, CT, NS>, lds);
-  const int threads = 64 * (K2P / (16 * CT)) * NS;
+  constexpr int NT = 64 * (2 * NKC / CT) * NS, W = RT >= 8 ? 1 : 2;
+  const H* yh = static_cast<const H*>(a.Y[0]);
+  const H* yl = static_cast<const H*>(a.Y[1]);
+  const H* vec = static_cast<const H*>(a.vec);
+  const int* sterm = a.step_term;
+  const int* sgroup = a.step_group;
+  const int* sbegin = a.step_begin;
+  float* ppart = static_cast<float*>(a.Phi_part);
+  if (prep) {
+    // the plain instance and the batched one
+    hipError_t e = set_lds(stage2_x3<H, RT, NKC, CT, NS>, lds);
+    if (e != hipSuccess) return e;
+    return batched_set_lds(
+        batched_kernel_w_of<NT, W, stage2_x3_body<H, RT, NKC, CT, NS>>(
+            yh, yl, vec, sterm, sgroup, sbegin, ppart, a.K[0], a.K[1], a.K[2], a.st),
+        lds);
+  }
   if (a.K2P != K2P || a.x3_streams != NS || a.blen != x3_blen(K2P) || a.alen != x3_alen(K1P))
     return hipErrorInvalidValue;
-  hipLaunchKernelGGL((stage2_x3<H, RT, NKC, CT, NS>), dim3(a.K[2], a.nparts), dim3(threads),
-                     lds, st, static_cast<const H*>(a.Y[0]), static_cast<const H*>(a.Y[1]),
-                     static_cast<const H*>(a.vec), a.step_term, a.step_group, a.step_begin,
-                     static_cast<float*>(a.Phi_part), a.K[0], a.K[1], a.K[2], a.st);
-  return hipGetLastError();
+  return launch_or_record_w<NT, W, stage2_x3_body<H, RT, NKC, CT, NS>>(
+      LS_STAGE2, stage2_x3<H, RT, NKC, CT, NS>, dim3(a.K[2], a.nparts), lds, st, yh, yl, vec,
+      sterm, sgroup, sbegin, ppart, a.K[0], a.K[1], a.K[2], a.st);
 }
 
 template <typename H, int RT>
@@ -938,6 +999,7 @@ hipError_t launch_s2_k4(const SkpArgs& a, hipStream_t st, bool prep) {
   size_t lds = sizeof(T) * static_cast<size_t>(K1P) * (a.K2P + 1);
   if (AL) lds += sizeof(T) * static_cast<size_t>(K1P) * (K1P + 1);
   if (prep) return set_lds(stage2_k4<T, RT, CT, AL>, lds);
+  if (record_unsupported()) return hipSuccess;
   const int threads = 64 * (a.K2P / (16 * CT));
   hipLaunchKernelGGL((stage2_k4<T, RT, CT, AL>), dim3(a.K[2], a.nparts), dim3(threads), lds, st,
                      static_cast<const T*>(a.Y[0]), static_cast<const T*>(a.A[0]),
@@ -984,6 +1046,7 @@ size_t stage2_lds_bytes(int prec, int K1P, int K2P) {
 }
 
 hipError_t launch_skp_sum(const SkpArgs& a, hipStream_t st) {
+  if (record_unsupported()) return hipSuccess;
   const long G = static_cast<long>(a.K[0]) * a.K[1] * a.K[2];
   // sum(Q) in FP64, fixed reduction order
   if (a.prec == PREC_FP64)
@@ -997,6 +1060,7 @@ hipError_t launch_skp_sum(const SkpArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_sum_partials(const SkpArgs& a, hipStream_t st) {
+  if (record_unsupported()) return hipSuccess;
   const long G = static_cast<long>(a.K[0]) * a.K[1] * a.K[2];
   if (a.prec == PREC_FP64)
     hipLaunchKernelGGL((sum_partial<double>), dim3(kSumBlocks), dim3(256), 0, st,
@@ -1008,8 +1072,8 @@ hipError_t launch_sum_partials(const SkpArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_sum_final(const double* part2, int np, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(sum_final, dim3(1), dim3(256), 0, st, part2, np, out);
-  return hipGetLastError();
+  return launch_or_record<256, sum_final_body>(LS_GRID_SUM, sum_final, dim3(1), 0, st, part2, np,
+                                               out);
 }
 
 template <typename H>
@@ -1019,26 +1083,29 @@ hipError_t launch_s1_x3(const SkpArgs& a, int scale_q, float sy, hipStream_t st)
   const int ntiles = (nrows + 15) / 16;
   const unsigned ptiles = static_cast<unsigned>(slab / 64);
   const unsigned s1split = static_cast<unsigned>(std::max(1, std::min(a.s1_split, ntiles)));
-#define KPME_S1(NK)                                                                        \
-  hipLaunchKernelGGL((stage1_x3_lds<H, NK>), dim3(s1split, ptiles), dim3(256), 0, st,     \
-                     static_cast<const float*>(a.Q), static_cast<const H*>(a.C[0]),        \
-                     static_cast<const H*>(a.C[1]), static_cast<H*>(a.Y[0]),               \
-                     static_cast<H*>(a.Y[1]), a.K[0], a.K[1], a.K[2], a.K2P, slab, nrows,  \
-                     a.sum_part, a.sum_np, a.sumQ, scale_q, sy)
+  const float* Q = static_cast<const float*>(a.Q);
+  const H* ch = static_cast<const H*>(a.C[0]);
+  const H* cl = static_cast<const H*>(a.C[1]);
+  H* yh = static_cast<H*>(a.Y[0]);
+  H* yl = static_cast<H*>(a.Y[1]);
+  const double* spart = a.sum_part;
+#define KPME_S1(NK)                                                                          \
+  return launch_or_record<256, stage1_x3_lds_body<H, NK>>(                                   \
+      LS_STAGE1, stage1_x3_lds<H, NK>, dim3(s1split, ptiles), 0, st, Q, ch, cl, yh, yl,       \
+      a.K[0], a.K[1], a.K[2], a.K2P, slab, nrows, spart, a.sum_np, a.sumQ, scale_q, sy)
   switch (a.K3P) {
-    case 32: KPME_S1(1); return hipGetLastError();
-    case 64: KPME_S1(2); return hipGetLastError();
-    case 96: KPME_S1(3); return hipGetLastError();
-    case 128: KPME_S1(4); return hipGetLastError();
+    case 32: KPME_S1(1);
+    case 64: KPME_S1(2);
+    case 96: KPME_S1(3);
+    case 128: KPME_S1(4);
     default: break;
   }
 #undef KPME_S1
   dim3 grid((ntiles + kS1Tiles - 1) / kS1Tiles, ptiles);
-  hipLaunchKernelGGL((stage1_x3<H>), grid, dim3(64), 0, st, static_cast<const float*>(a.Q),
-                     static_cast<const H*>(a.C[0]), static_cast<const H*>(a.C[1]),
-                     static_cast<H*>(a.Y[0]), static_cast<H*>(a.Y[1]), a.K[0], a.K[1], a.K[2],
-                     a.K3P, a.K2P, slab, nrows, a.sum_part, a.sum_np, a.sumQ, scale_q, sy);
-  return hipGetLastError();
+  return launch_or_record<64, stage1_x3_body<H>>(LS_STAGE1, stage1_x3<H>, grid, 0, st, Q, ch, cl,
+                                                 yh, yl, a.K[0], a.K[1], a.K[2], a.K3P, a.K2P,
+                                                 slab, nrows, spart, a.sum_np, a.sumQ, scale_q,
+                                                 sy);
 }
 
 hipError_t launch_skp_stage1(const SkpArgs& a, hipStream_t st) {
@@ -1047,6 +1114,7 @@ hipError_t launch_skp_stage1(const SkpArgs& a, hipStream_t st) {
   dim3 g1(static_cast<unsigned>(slab / S1), (nrows + S1 - 1) / S1);
   if (a.prec == PREC_BF16X3) return launch_s1_x3<bf16>(a, 0, 1.0f, st);
   if (a.prec == PREC_FP16X3) return launch_s1_x3<f16>(a, 1, a.sy, st);
+  if (record_unsupported()) return hipSuccess;
   if (a.prec == PREC_FP32)
     hipLaunchKernelGGL((stage1_k4<float>), g1, dim3(256), 0, st, static_cast<const float*>(a.Q),
                        static_cast<const float*>(a.C[0]), static_cast<float*>(a.Y[0]), a.K[0],
@@ -1067,17 +1135,19 @@ hipError_t prepare_skp_stage2(const SkpArgs& a) { return stage2_dispatch(a, null
 
 hipError_t launch_skp_finalize(const SkpArgs& a, hipStream_t st) {
   dim3 gf((a.K[1] + 31) / 32, (a.K[2] + 31) / 32, a.K[0]);
+  if (a.prec == PREC_FP64 && record_unsupported()) return hipSuccess;
   if (a.prec == PREC_FP64)
     hipLaunchKernelGGL((finalize<double, double>), gf, dim3(256), 0, st,
                        static_cast<const double*>(a.Phi_part), a.nparts,
                        static_cast<double*>(a.Phi), a.K[0], a.K[1], a.K[2], a.sumQ, a.c0,
                        nullptr, 1.0, static_cast<const double*>(a.eQ), a.epart);
   else
-    hipLaunchKernelGGL((finalize<float, float>), gf, dim3(256), 0, st,
-                       static_cast<const float*>(a.Phi_part), a.nparts,
-                       static_cast<float*>(a.Phi), a.K[0], a.K[1], a.K[2], a.sumQ, a.c0,
-                       a.prec == PREC_FP16X3 ? a.sumQ + 1 : nullptr, a.const_scale,
-                       static_cast<const float*>(a.eQ), a.epart);
+    return launch_or_record<256, finalize_body<float, float>>(
+        LS_FINALIZE, finalize<float, float>, gf, 0, st, static_cast<const float*>(a.Phi_part),
+        a.nparts, static_cast<float*>(a.Phi), a.K[0], a.K[1], a.K[2],
+        static_cast<const double*>(a.sumQ), a.c0,
+        static_cast<const double*>(a.prec == PREC_FP16X3 ? a.sumQ + 1 : nullptr),
+        a.const_scale, static_cast<const float*>(a.eQ), a.epart);
   return hipGetLastError();
 }
 

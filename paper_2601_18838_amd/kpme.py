@@ -82,6 +82,7 @@ _SIGNATURES = {
     "kpme_batch_create": [ctypes.POINTER(_P), _INT, _DP, _IP, _IP, _DP, _IP, _INT,
                           ctypes.POINTER(_I64), _INT],
     "kpme_batch_destroy": [_P],
+    "kpme_batch_info": [_P, _IP, _IP],
     "kpme_plan_profile": [_P, _INT],
     "kpme_plan_autotune": [_P, _P],
     "kpme_plan_profile_read": [_P, _DP, ctypes.POINTER(_I64)],
@@ -317,7 +318,9 @@ class Plan:
 
 
 class BatchPlan:
-    """Independent systems evaluated by one replayed HIP graph (kpme_batch_*)."""
+    """Independent systems evaluated by one replayed HIP graph (kpme_batch_*):
+    batched launches (one per stage and kernel instance over all systems)
+    where every system's kernels have that form, else per-system branches."""
 
     def __init__(self, boxes, grids, orders, betas, ranks, precision="fp16x3",
                  max_particles=None, device=0):
@@ -372,6 +375,14 @@ class BatchPlan:
         _check(lib().kpme_batch_evaluate(self._h, nn, p(pos), p(q), p(pot), p(force),
                                          p(energy), _stream()))
         return energy, pot, force
+
+    def info(self):
+        """(form, launches) of the current recording: form 1 = one launch per
+        stage and kernel instance for all systems, 0 = per-system graph
+        branches, -1 = nothing recorded; launches = kernels per replay."""
+        form, launches = ctypes.c_int(), ctypes.c_int()
+        _check(lib().kpme_batch_info(self._h, ctypes.byref(form), ctypes.byref(launches)))
+        return form.value, launches.value
 
 
 def _autograd_function():

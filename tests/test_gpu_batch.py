@@ -1,7 +1,8 @@
 """GPU checks of the batched evaluation (one replayed HIP graph for many
 independent systems): every system against its own single-plan evaluation,
 every graph replay against the eager result (with eager work and
-synchronisation between replays), and a small FP64 batch against the oracle.
+synchronisation between replays), the batched-launch form against the
+per-system graph form, and a small FP64 batch against the oracle.
 
 Tolerances: batch vs single plan relE <= 1e-6 and relative RMS <= 1e-5 (the
 same kernels; only the order of floating-point atomics in the spread and the
@@ -46,6 +47,9 @@ def test_batch_matches_single_plans_and_graph_replays():
     bp, pos, q, n = build(batch, "fp16x3")
     e0, pot0, f0 = [x.clone() for x in bp.evaluate(n, pos, q)]
     torch.cuda.synchronize()
+    form, launches = bp.info()
+    print(f"  form {form}, {launches} launches per replay", flush=True)
+    assert form == 1 and launches < 10 * 4   # one launch per stage and kernel instance
     # replays, with unrelated eager work in between; the second call passes
     # fresh output buffers after a host synchronisation, which re-records
     for rep in range(3):
@@ -121,12 +125,42 @@ def test_small_fp64_batch_against_oracle():
         cases.append((wl, pos, q))
     bp, pos, q, n = build(cases, "fp64")
     e4, pot, f = bp.evaluate(n, pos, q)
+    assert bp.info()[0] == 0   # FP64 stage kernels have no batched form: per-system graph
     off = 0
     for k, (wl, p_np, q_np) in enumerate(cases):
         ref = skp.Plan(wl.box, wl.grid, wl.order, wl.beta, rank=wl.rank).evaluate(p_np, q_np)
         assert abs(e4[k, 0].item() - ref["E_rec"]) < 1e-10 * abs(ref["E_rec"])
         assert relrms(pot[off:off + wl.n].cpu().numpy(), ref["phi"]) < 1e-10
         assert relrms(f[off:off + wl.n].cpu().numpy(), ref["F"]) < 1e-10
+        off += wl.n
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp16x3"])
+def test_batched_launches_match_per_system_graph(prec, monkeypatch):
+    """The 64-system batch in its two recorded forms -- one launch per stage
+    and kernel instance over all systems, and every system's own launch
+    sequence on parallel graph branches -- runs the same kernel bodies on the
+    same arguments: energies to 1e-6 relative, potentials and forces to 1e-5
+    relative RMS (binning assigns slots with atomics, so FP32 sums may be
+    added in another order)."""
+    batch = systems.batch_systems(count=64)
+    print(f"[batch] batched vs per-system graph, 64 systems {prec}", flush=True)
+    bp, pos, q, n = build(batch, prec)
+    ea, pa, fa = [x.clone() for x in bp.evaluate(n, pos, q)]
+    assert bp.info()[0] == 1
+    del bp
+    monkeypatch.setenv("KPME_BATCH_FUSED", "0")
+    bp, pos, q, n = build(batch, prec)
+    eb, pb, fb = bp.evaluate(n, pos, q)
+    form, launches = bp.info()
+    assert form == 0 and launches > 64
+    ea, eb = ea.cpu().numpy(), eb.cpu().numpy()
+    assert np.all(np.abs(ea[:, 0] - eb[:, 0]) <= 1e-6 * np.abs(eb[:, 0]))
+    off = 0
+    for k, (wl, _, _) in enumerate(batch):
+        sl = slice(off, off + wl.n)
+        assert relrms(pa[sl].double().cpu().numpy(), pb[sl].double().cpu().numpy()) < 1e-5, k
+        assert relrms(fa[sl].double().cpu().numpy(), fb[sl].double().cpu().numpy()) < 1e-5, k
         off += wl.n
 
 

@@ -136,10 +136,23 @@ TOL = {"fp64": dict(grid=1e-11, pot=1e-11, force=1e-11, energy=1e-11),
        "fp16x3": dict(grid=1e-5, pot=1e-5, force=2e-5, energy=1e-5)}
 
 
+def _forms():
+    # orders above 4 have two spread/gather forms, chosen by particles per
+    # brick (home tiles + combine + tiled gather, or owner spread + direct
+    # gather); each case runs as chosen and forced into either form
+    for case in CASES:
+        yield pytest.param(case, "auto", id=f"{case}")
+        if CASES[case][2] > 4:
+            yield pytest.param(case, "dense", id=f"{case}-dense")
+            yield pytest.param(case, "sparse", id=f"{case}-sparse")
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "fp16x3"])
-@pytest.mark.parametrize("case", list(CASES))
-def test_stages_match_oracle(case, prec):
-    print(f"[parity] {case} {prec}", flush=True)
+@pytest.mark.parametrize("case,form", list(_forms()))
+def test_stages_match_oracle(case, form, prec, monkeypatch):
+    print(f"[parity] {case} {form} {prec}", flush=True)
+    if form != "auto":
+        monkeypatch.setenv("KPME_SPARSE", "1" if form == "sparse" else "0")
     box, grid, p, beta, rank, pos, q = make(case)
     orc = oracle_plan(box, grid, p, beta, rank=rank)
     ref = orc.evaluate(pos, q)
