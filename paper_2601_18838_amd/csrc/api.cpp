@@ -855,7 +855,7 @@ kpme_status kpme_plan_create_ex(kpme_plan_t* plan, const double box[3], const in
   // Few particles per brick (planned for max_particles): the home tiles of
   // orders above 4 would write and re-read (edge + p - 1)^3 values per brick
   // for a handful of particles, so the owner spread (FP64 LDS tile of the
-  // brick itself) and the direct gather are used instead.
+  // brick itself) is used instead.
   // Tuning override: KPME_SPARSE=0/1.
   bg.sparse = spline_order > 4 && spline_order <= 9 &&
               static_cast<double>(max_particles) < kSparseDensity * bg.nbricks;

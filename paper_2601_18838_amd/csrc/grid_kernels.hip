@@ -1600,7 +1600,8 @@ __device__ __forceinline__ void gather_brick_pf_body(
   T rec[4] = {T(0), T(0), T(0), T(0)};
   int pm = 0;
   __syncthreads();   // offs
-  if (b_begin < b_end) {
+  // a brick without particles needs no tile (its offsets are uniform)
+  if (b_begin < b_end && offs[1] > offs[0]) {
     load_tile(b_begin, treg);
     const int s = offs[0] + tid;
     if (s < offs[1]) {
@@ -1609,12 +1610,14 @@ __device__ __forceinline__ void gather_brick_pf_body(
     }
   }
   for (int b = b_begin; b < b_end; ++b) {
-    store_tile(treg);
-    __syncthreads();
     const int i0 = offs[b - b_begin], i1 = offs[b - b_begin + 1];
+    if (i1 > i0) {
+      store_tile(treg);
+      __syncthreads();
+    }
     T rc[4] = {rec[0], rec[1], rec[2], rec[3]};
     int pc = pm;
-    if (b + 1 < b_end) {   // next brick's values in flight during this one
+    if (b + 1 < b_end && offs[b - b_begin + 2] > i1) {   // next brick's values in flight
       load_tile(b + 1, treg);
       const int s = i1 + tid;
       if (s < offs[b - b_begin + 2]) {
@@ -1622,6 +1625,7 @@ __device__ __forceinline__ void gather_brick_pf_body(
         pm = perm[s];
       }
     }
+    if (i1 == i0) continue;
     int lo[3];
     lo_of(b, lo);
     for (int s = i0 + tid; s < i1; s += kGatherThreads) {
@@ -2013,9 +2017,8 @@ hipError_t spread_brick_p(const GridGeom& g, const Bins& b, const void* src, voi
 template <typename T, int P>
 hipError_t gather_brick_p(const GridGeom& g, const Bins& b, int64_t n, const void* grid,
                           void* pot, void* force, const EnergyJob& ej, hipStream_t st) {
-  if (P < 4 || (P > 4 && (sizeof(T) == 8 || b.geom.sparse))) {
-    // direct stencil reads per particle (low orders, FP64, or few particles
-    // per brick)
+  if (P < 4 || (P > 4 && sizeof(T) == 8)) {
+    // direct stencil reads per particle (low orders, FP64)
     const unsigned blocks = static_cast<unsigned>((n + 255) / 256) + (ej.e4 ? 1 : 0);
     return launch_or_record<256, gather_sorted_body<T, P>>(
         LS_GATHER, gather_sorted<T, P>, dim3(blocks), 0, st, static_cast<long>(n),

@@ -122,8 +122,8 @@ struct BinGeom {
   int nbmax;     // row stride of the neighbour table
   int two_homes; // every owner brick reached by exactly two home bricks per
                  // axis (itself and the next) and every tile extent <= K_j
-  int sparse;    // few particles per brick: owner spread and direct gather
-                 // also for orders above 4
+  int sparse;    // few particles per brick: the owner spread also for
+                 // orders above 4
 };
 
 // Device buffers of the binned particle layout.
