@@ -175,10 +175,42 @@ def bench_batch(args):
             out = run()
         torch.cuda.synchronize()
         res[prec] = ((time.perf_counter() - t0) / steps, t_plan, out)
+    form, launches = bp.info()
+    # the same batch recorded as every system's own launch sequence on
+    # parallel graph branches (the library's other form), for comparison
+    prev = os.environ.get("KPME_BATCH_FUSED")
+    os.environ["KPME_BATCH_FUSED"] = "0"
+    try:
+        bp2 = kpme.BatchPlan([w.box for w in wls], [w.grid for w in wls], [w.order for w in wls],
+                             [w.beta for w in wls], [w.rank for w in wls], precision=mixed,
+                             max_particles=n)
+    finally:
+        if prev is None:
+            del os.environ["KPME_BATCH_FUSED"]
+        else:
+            os.environ["KPME_BATCH_FUSED"] = prev
+    dt = torch.float32
+    pos = torch.tensor(np.concatenate([b[1] for b in batch]), dtype=dt, device="cuda")
+    q = torch.tensor(np.concatenate([b[2] for b in batch]), dtype=dt, device="cuda")
+    for _ in range(args.warmup):
+        bp2.evaluate(n, pos, q, energy=outs_b[0], pot=outs_b[1], force=outs_b[2])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        bp2.evaluate(n, pos, q, energy=outs_b[0], pot=outs_b[1], force=outs_b[2])
+    torch.cuda.synchronize()
+    t_graph = (time.perf_counter() - t0) / args.steps
+    form2, launches2 = bp2.info()
+    del bp2
     e_mixed = res[mixed][2][0][:, 0].cpu().numpy()
     e_ref = np.array([o[0][0].item() for o in res["fp64"][2]])
     rel = np.abs(e_mixed - e_ref) / np.abs(e_ref)
     t = res[mixed][0]
+    # stage-2 flops of every system (issued: three products per split
+    # product) over the whole batch time: a lower bound on the matrix cores'
+    # use across the batch
+    flops = sum(3.0 * 2.0 * (w.grid[0] * w.grid[1] * w.grid[2]) * w.rank * (w.grid[0] + w.grid[1])
+                for w in wls)
     out = {"metric": "batched reciprocal PME: systems/s for 64 independent systems in one graph",
            "value": 64.0 / t, "unit": "systems/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": t * 1e3, "higher_is_better": True,
@@ -189,6 +221,15 @@ def bench_batch(args):
            "fp64_loop_ms": res["fp64"][0] * 1e3,
            "speedup_vs_fp64_loop": res["fp64"][0] / t,
            "max_rel_energy_err": float(rel.max()),
+           "batched_form": {"form": "one launch per stage and kernel instance" if form == 1
+                            else "per-system graph branches", "launches_per_batch": launches},
+           "per_system_graph": {"ms_per_step": t_graph * 1e3, "launches_per_batch": launches2,
+                                "form": form2},
+           "speedup_vs_per_system_graph": t_graph / t,
+           "roofline": {"bound": "mfma", "kernel": "all stage-2 flops over the batch time",
+                        "achieved": flops / t / 1e12, "peak": PEAK_TFLOPS[mixed],
+                        "unit": "TFLOP/s", "frac": flops / t / 1e12 / PEAK_TFLOPS[mixed],
+                        "traffic": None, "flops_per_batch": flops},
            "plan_seconds": {mixed: res[mixed][1], "fp64": res["fp64"][1]}}
     print(json.dumps(out), flush=True)
 
