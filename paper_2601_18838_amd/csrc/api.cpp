@@ -1192,7 +1192,7 @@ extern "C" kpme_status kpme_plan_autotune(kpme_plan_t plan, void* stream) {
     if (e != hipSuccess) s = from_hip(e, "autotune");
   }
   // stage-1 split (split precisions with the LDS-tiled stage 1): the fastest
-  const bool s1_tiled = (plan->prec == PREC_BF16X3 || plan->prec == PREC_FP16X3) && plan->K3P <= 128;
+  const bool s1_tiled = (plan->prec == PREC_BF16X3 || plan->prec == PREC_FP16X3) && plan->K3P <= 160;
   if (s == KPME_SUCCESS && s1_tiled) {
     int best1 = plan->s1_split;
     float fastest = -1.f;

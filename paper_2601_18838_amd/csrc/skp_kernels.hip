@@ -216,7 +216,7 @@ __global__ __launch_bounds__(64) void stage1_x3(
   stage1_x3_body<H>(Q, Chi, Clo, Yhi, Ylo, K1, K2, K3, K3P, K2P, slab, nrows, part, np, sums, scale_q, sy, Wg::plain());
 }
 
-// Stage 1, split precision, K3P <= 128 (NK = K3P / 32 chunks): a workgroup
+// Stage 1, split precision, K3P <= 160 (NK = K3P / 32 chunks): a workgroup
 // of four waves takes one tile of 64 positions; its Q rows are split into
 // hi/lo once, into LDS, and every wave keeps the A fragments of the whole K
 // range in registers while it streams its share of the 16-row C tiles
@@ -1098,6 +1098,7 @@ hipError_t launch_s1_x3(const SkpArgs& a, int scale_q, float sy, hipStream_t st)
     case 64: KPME_S1(2);
     case 96: KPME_S1(3);
     case 128: KPME_S1(4);
+    case 160: KPME_S1(5);
     default: break;
   }
 #undef KPME_S1

@@ -92,8 +92,10 @@ CASES = {
     "k2p_k3p_128": ((40.0, 100.0, 120.0), (40, 100, 120), 4, 0.34, 24, 3000, "pm1", 17),
     # K1P = K2P = 128: the two-stream 128 x 128 stage-2 instance
     "k1p_k2p_128": ((50.0, 55.0, 12.0), (100, 110, 24), 4, 0.5, 16, 3000, "pm1", 22),
-    # K3 = 160 (K3P > 128): the one-wave stage 1 that loops over K chunks
+    # K3 = 160: the LDS-tiled stage 1 with five K chunks
     "k3p_160": ((24.0, 40.0, 160.0), (24, 40, 160), 6, 0.34, 20, 2001, "water", 18),
+    # K3 = 200 (K3P = 224 > 160): the one-wave stage 1 that loops over K chunks
+    "k3p_224": ((16.0, 24.0, 100.0), (16, 24, 200), 4, 0.6, 12, 1500, "pm1", 23),
     # the largest grid of the batched workload: 96 x 128 x 160, order 6, more
     # than 2048 bricks (the grid sum goes through its own reduction)
     "batch_96x128x160": ((96.0, 128.0, 160.0), (96, 128, 160), 6, 0.34, 7, 31764, "pm1", 19),
