@@ -852,16 +852,16 @@ kpme_status kpme_plan_create_ex(kpme_plan_t* plan, const double box[3], const in
       two = hnbr[(static_cast<size_t>(j) * bg.nbmax + bo) * kNbrRec] == 2;
     if (!two) bg.two_homes = 0;
   }
-  // Few particles per brick (planned for max_particles): the home tiles of
-  // orders above 4 would write and re-read (edge + p - 1)^3 values per brick
-  // for a handful of particles, so the owner spread (FP64 LDS tile of the
-  // brick itself) is used instead.
+  // Few particles per brick (planned for max_particles): the home tiles
+  // (orders 4 and up on float grids) would write and re-read
+  // (edge + p - 1)^3 values per brick for a handful of particles, so the
+  // owner spread (FP64 LDS tile of the brick itself) is used instead.
   // Tuning override: KPME_SPARSE=0/1.
-  bg.sparse = spline_order > 4 && spline_order <= 9 &&
+  bg.sparse = spline_order >= 4 && spline_order <= 9 &&
               static_cast<double>(max_particles) < kSparseDensity * bg.nbricks;
   if (const char* env = std::getenv("KPME_SPARSE"))
-    bg.sparse = spline_order > 4 && spline_order <= 9 && std::atoi(env) != 0;
-  pl->spread_parts = spread_partials(bg, spline_order);
+    bg.sparse = spline_order >= 4 && spline_order <= 9 && std::atoi(env) != 0;
+  pl->spread_parts = spread_partials(bg, spline_order, precision == KPME_FP64);
   const size_t nY = static_cast<size_t>(r0) * K3 * K1P * K2P;
   void* tmp = nullptr;
   do {
@@ -919,7 +919,8 @@ kpme_status kpme_plan_create_ex(kpme_plan_t* plan, const double box[3], const in
     bn.nbr = static_cast<int*>(tmp);
     if ((e = hipMemcpy(tmp, hnbr.data(), hnbr.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess) break;
     if ((e = plan_alloc(pl, &bn.sorted, nmax * 4 * es)) != hipSuccess) break;
-    if (spline_order > 4) {  // per-brick tiles of the two-pass spread
+    if (spline_order > 4 || (spline_order == 4 && precision != KPME_FP64)) {
+      // per-brick tiles of the two-pass spread
       size_t ntile = 1;
       for (int j = 0; j < 3; ++j) ntile *= static_cast<size_t>(bg.edge[j] + spline_order - 1);
       if ((e = plan_alloc(pl, &bn.tiles, static_cast<size_t>(bg.nbricks) * ntile * es)) != hipSuccess)

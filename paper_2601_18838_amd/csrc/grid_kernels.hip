@@ -1962,7 +1962,8 @@ template <typename T, int P>
 hipError_t spread_brick_p(const GridGeom& g, const Bins& b, const void* src, void* grid,
                           double* part2, hipStream_t st) {
   const T* srt = static_cast<const T*>(src ? src : b.sorted);
-  bool owner = P <= 4;
+  // the owner spread for low orders, FP64 at order 4, and sparse plans
+  bool owner = P < 4 || (P == 4 && sizeof(T) == 8);
   if constexpr (P <= 9) owner = owner || b.geom.sparse;
   if (owner) {
     const size_t lds = sizeof(double) * b.geom.edge[0] * b.geom.edge[1] * b.geom.edge[2];
@@ -2058,8 +2059,9 @@ hipError_t gather_brick_p(const GridGeom& g, const Bins& b, int64_t n, const voi
 
 // Number of (sum, max) pairs the binned spread writes: one per workgroup of
 // the persistent combine, else one per brick.
-int spread_partials(const BinGeom& bg, int p) {
-  return (p > 4 && !bg.sparse && bg.two_homes) ? combine_workgroups(bg.nbricks) : bg.nbricks;
+int spread_partials(const BinGeom& bg, int p, bool fp64) {
+  const bool home = p > 4 || (p == 4 && !fp64);
+  return (home && !bg.sparse && bg.two_homes) ? combine_workgroups(bg.nbricks) : bg.nbricks;
 }
 
 // Number of (sum q, sum q^2) pairs the scatter writes.

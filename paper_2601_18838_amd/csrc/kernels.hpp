@@ -123,7 +123,7 @@ struct BinGeom {
   int two_homes; // every owner brick reached by exactly two home bricks per
                  // axis (itself and the next) and every tile extent <= K_j
   int sparse;    // few particles per brick: the owner spread also for
-                 // orders above 4
+                 // orders 4 and up on float grids
 };
 
 // Device buffers of the binned particle layout.
@@ -149,7 +149,7 @@ hipError_t launch_gather_direct(int prec, const GridGeom& g, int64_t n, const vo
 hipError_t launch_bin(int prec, const GridGeom& g, const Bins& b, int64_t n, const void* pos,
                       const void* q, double* qpart, hipStream_t st);
 int scatter_partials(const Bins& b, int64_t n);
-int spread_partials(const BinGeom& bg, int p);
+int spread_partials(const BinGeom& bg, int p, bool fp64);
 
 // Final energies of an evaluation, combined by one workgroup: E_rec = 1/2 of
 // the sum of the finalize partials (sum over grid points of Q Phi, equal to

@@ -139,12 +139,12 @@ TOL = {"fp64": dict(grid=1e-11, pot=1e-11, force=1e-11, energy=1e-11),
 
 
 def _forms():
-    # orders above 4 have two spread/gather forms, chosen by particles per
-    # brick (home tiles + combine + tiled gather, or owner spread + direct
-    # gather); each case runs as chosen and forced into either form
+    # orders 4 and up have two spread forms, chosen by particles per brick
+    # (home tiles + combine, or the owner spread); each case runs as chosen
+    # and forced into either form
     for case in CASES:
         yield pytest.param(case, "auto", id=f"{case}")
-        if CASES[case][2] > 4:
+        if CASES[case][2] >= 4:
             yield pytest.param(case, "dense", id=f"{case}-dense")
             yield pytest.param(case, "sparse", id=f"{case}-sparse")
 
