@@ -788,9 +788,11 @@ __device__ __forceinline__ void spread_home_mfma_body(const float* __restrict__ 
   static_assert(2 * kMfmaWaves >= 16, "two planes per wave cover a 16-plane tile");
   // padded per-particle rows, in sorted slot order: q wx at its x planes,
   // wy at its y positions, wz at its z positions (zero elsewhere)
-  __shared__ __attribute__((aligned(16))) float sx[kMfmaChunk][16];
-  __shared__ __attribute__((aligned(16))) float sy[kMfmaChunk][16];
-  __shared__ __attribute__((aligned(16))) float sz[kMfmaChunk][16];
+  // (eight rows past the chunk: the k-loops read up to seven slots past a
+  // plane's range, and the rows past the chunk's particles are zero)
+  __shared__ __attribute__((aligned(16))) float sx[kMfmaChunk + 8][16];
+  __shared__ __attribute__((aligned(16))) float sy[kMfmaChunk + 8][16];
+  __shared__ __attribute__((aligned(16))) float sz[kMfmaChunk + 8][16];
   __shared__ int wcount[4][16];   // per wave, particles per x base
   __shared__ int boff[4][17];     // per wave, first slot of each x base
   __shared__ int bstart[17];      // first slot of each x base in the chunk
@@ -876,6 +878,14 @@ __device__ __forceinline__ void spread_home_mfma_body(const float* __restrict__ 
         sy[slot][l[1] - s] = w[1][s];
         sz[slot][l[2] - s] = w[2][s];
       }
+    } else if (t < n + 8) {
+      const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+      for (int e = 0; e < 16; e += 4) {
+        *reinterpret_cast<float4*>(&sx[t][e]) = z4;
+        *reinterpret_cast<float4*>(&sy[t][e]) = z4;
+        *reinterpret_cast<float4*>(&sz[t][e]) = z4;
+      }
     }
     __syncthreads();
     // planes a = wave + 8u; the particles reaching plane a have x base in
@@ -892,19 +902,15 @@ __device__ __forceinline__ void spread_home_mfma_body(const float* __restrict__ 
       // operands of particle k for this lane: A[b][k] = s_k(a) wy_k(b) with
       // b = col, B[k][c] = wz_k(c) with c = col; the next step's operands
       // are read while this step's product runs
-      // (slots are clamped into the array; a slot at or past pe, whose row
-      // may be stale or uninitialised, is replaced by zeros)
-      int k = min(ps + kq, kMfmaChunk - 1);
-      float yb = sx[k][a] * sy[k][col], zc = sz[k][col];
-      if (ps + kq >= pe) yb = zc = 0.f;
+      // (no masks: a slot in [pe, n) holds a particle whose x planes lie
+      // above a, so its s(a) is zero, and the rows from n on are zero)
+      float yb = sx[ps + kq][a] * sy[ps + kq][col], zc = sz[ps + kq][col];
       for (int k0 = ps; k0 < pe; k0 += 4) {
-        const int kn = k0 + 4 + kq;
-        k = min(kn, kMfmaChunk - 1);
-        const float xn = sx[k][a], yn = sy[k][col], zn = sz[k][col];
+        const int kn = k0 + 4 + kq;   // <= pe + 6 <= n + 6
+        const float xn = sx[kn][a], yn = sy[kn][col], zn = sz[kn][col];
         acc[u] = mfma_k4(yb, zc, acc[u]);
-        const bool in = kn < pe;
-        yb = in ? xn * yn : 0.f;
-        zc = in ? zn : 0.f;
+        yb = xn * yn;
+        zc = zn;
       }
     }
     __syncthreads();   // the rows are rewritten by the next chunk
