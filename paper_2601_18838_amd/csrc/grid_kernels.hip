@@ -1529,7 +1529,7 @@ __global__ __launch_bounds__(kGatherThreads) void gather_brick(const T* __restri
 // perm entries of its first kGatherThreads particles.  The brick offsets of
 // the range are staged in LDS once.  Results and summation order per
 // particle are those of gather_brick.
-template <typename T, int P>
+template <typename T, int P, bool E8>
 __device__ __forceinline__ void gather_brick_pf_body(
     const T* __restrict__ sorted, const int* __restrict__ offset, const int* __restrict__ perm,
     const T* __restrict__ grid, T* __restrict__ pot, T* __restrict__ force, EnergyJob ej,
@@ -1552,9 +1552,11 @@ __device__ __forceinline__ void gather_brick_pf_body(
   const int b_end = static_cast<int>(static_cast<long>(wl + 1) * nb / nwork);
   const int tid = threadIdx.x;
   for (int k = tid; k <= b_end - b_begin; k += kGatherThreads) offs[k] = offset[b_begin + k];
+  // E8: every brick edge is 8, so the tile strides are compile-time
+  // constants (LDS offsets of the stencil rows become immediates)
   int H[3];
 #pragma unroll
-  for (int j = 0; j < 3; ++j) H[j] = bg.edge[j] + P - 1;
+  for (int j = 0; j < 3; ++j) H[j] = E8 ? 8 + P - 1 : bg.edge[j] + P - 1;
   const int K1 = g.K[0], K2 = g.K[1], K3 = g.K[2];
   const int nrows = H[0] * H[1];
   const int c16 = tid & 15;
@@ -1692,12 +1694,12 @@ __device__ __forceinline__ void gather_brick_pf_body(
   }
 }
 
-template <typename T, int P>
+template <typename T, int P, bool E8>
 __global__ __launch_bounds__(kGatherThreads) void gather_brick_pf(
     const T* __restrict__ sorted, const int* __restrict__ offset, const int* __restrict__ perm,
     const T* __restrict__ grid, T* __restrict__ pot, T* __restrict__ force, EnergyJob ej,
     GridGeom g, BinGeom bg) {
-  gather_brick_pf_body<T, P>(sorted, offset, perm, grid, pot, force, ej, g, bg, Wg::plain());
+  gather_brick_pf_body<T, P, E8>(sorted, offset, perm, grid, pot, force, ej, g, bg, Wg::plain());
 }
 
 // sorted2[d] = (x, y, z, g[perm[d]]): the binned positions with a second
@@ -2036,9 +2038,16 @@ hipError_t gather_brick_p(const GridGeom& g, const Bins& b, int64_t n, const voi
     const int ntile = (b.geom.edge[0] + P - 1) * (b.geom.edge[1] + P - 1) * (b.geom.edge[2] + P - 1);
     const int nw = gather_pf_workgroups(b.geom.nbricks);
     if ((b.geom.nbricks + nw - 1) / nw > kGatherMaxBricks) return hipErrorInvalidValue;
-    return launch_or_record<kGatherThreads, gather_brick_pf_body<T, P>>(
-        LS_GATHER, gather_brick_pf<T, P>, dim3(nw + (ej.e4 ? 1 : 0)), sizeof(T) * ntile, st,
-        static_cast<const T*>(b.sorted), static_cast<const int*>(b.offset),
+    const bool e8 = b.geom.edge[0] == 8 && b.geom.edge[1] == 8 && b.geom.edge[2] == 8;
+    if (e8)
+      return launch_or_record<kGatherThreads, gather_brick_pf_body<T, P, true>>(
+          LS_GATHER, gather_brick_pf<T, P, true>, dim3(nw + (ej.e4 ? 1 : 0)), sizeof(T) * ntile,
+          st, static_cast<const T*>(b.sorted), static_cast<const int*>(b.offset),
+          static_cast<const int*>(b.perm), static_cast<const T*>(grid), static_cast<T*>(pot),
+          static_cast<T*>(force), ej, g, b.geom);
+    return launch_or_record<kGatherThreads, gather_brick_pf_body<T, P, false>>(
+        LS_GATHER, gather_brick_pf<T, P, false>, dim3(nw + (ej.e4 ? 1 : 0)), sizeof(T) * ntile,
+        st, static_cast<const T*>(b.sorted), static_cast<const int*>(b.offset),
         static_cast<const int*>(b.perm), static_cast<const T*>(grid), static_cast<T*>(pot),
         static_cast<T*>(force), ej, g, b.geom);
   }
