@@ -11,28 +11,39 @@ namespace kpme {
 
 namespace {
 
-// w[t] = M_P(f + t), dw[t] = M_P'(f + t) for t = 0..P-1 and f in [0, 1):
-// the order-n values follow from order n-1 by
-//   M_n(f+t) = [(f+t) M_{n-1}(f+t) + (n-f-t) M_{n-1}(f+t-1)] / (n-1),
-// and M_P'(u) = M_{P-1}(u) - M_{P-1}(u-1).
+// w[t] = M_P(f + t), dw[t] = M_P'(f + t) for t = 0..P-1 and f in [0, 1).
+// With W_n = (n-1)! M_n the order-n values follow from order n-1 by
+//   W_n(f+t) = (f+t) W_{n-1}(f+t) + (n-f-t) W_{n-1}(f+t-1),
+// of which only the n entries t = 0..n-1 are non-zero (W_{n-1}(f+n-1) and
+// W_{n-1}(f-1) vanish), and M_P'(u) = M_{P-1}(u) - M_{P-1}(u-1); the
+// factorials are divided out at the end.
 template <typename T, int P>
 __device__ __forceinline__ void bspline(T f, T* w, T* dw) {
   w[0] = T(1);
 #pragma unroll
-  for (int t = 1; t < P; ++t) w[t] = T(0);
-#pragma unroll
   for (int n = 2; n <= P; ++n) {
     if (n == P) {
+      dw[0] = w[0];
 #pragma unroll
-      for (int t = 0; t < P; ++t) dw[t] = w[t] - (t > 0 ? w[t - 1] : T(0));
+      for (int t = 1; t < P - 1; ++t) dw[t] = w[t] - w[t - 1];
+      dw[P - 1] = -w[P - 2];
     }
-    const T inv = T(1) / T(n - 1);
+    w[n - 1] = (T(1) - f) * w[n - 2];
 #pragma unroll
-    for (int t = n - 1; t >= 0; --t) {
-      const T left = (f + T(t)) * w[t];
-      const T right = (t > 0) ? (T(n) - f - T(t)) * w[t - 1] : T(0);
-      w[t] = (left + right) * inv;
-    }
+    for (int t = n - 2; t >= 1; --t) w[t] = (f + T(t)) * w[t] + (T(n - t) - f) * w[t - 1];
+    w[0] = f * w[0];
+  }
+  double fw = 1.0, fd = 1.0;
+#pragma unroll
+  for (int k = 2; k < P; ++k) {
+    fw *= k;
+    if (k < P - 1) fd *= k;
+  }
+  const T sw = static_cast<T>(1.0 / fw), sd = static_cast<T>(1.0 / fd);
+#pragma unroll
+  for (int t = 0; t < P; ++t) {
+    w[t] *= sw;
+    dw[t] *= sd;
   }
 }
 
@@ -771,6 +782,9 @@ __global__ __launch_bounds__(256) void spread_home(const T* __restrict__ sorted,
 // fixed order.  Needs every tile extent <= 16 (edge + P - 1).
 constexpr int kMfmaChunk = 256;   // particles staged per chunk (one per thread of waves 0-3)
 constexpr int kMfmaWaves = 8;     // waves per workgroup; wave w owns planes w, w + 8
+// three workgroups per CU fit in LDS (3 x 51 KB): six waves per SIMD, which
+// caps the kernel at 80 VGPRs
+constexpr int kMfmaWavesPerEu = 6;
 
 __device__ __forceinline__ unsigned long long lanemask_lt() {
   const unsigned lane = threadIdx.x & 63;
@@ -931,7 +945,8 @@ __device__ __forceinline__ void spread_home_mfma_body(const float* __restrict__ 
 }
 
 template <int P>
-__global__ __launch_bounds__(64 * kMfmaWaves) void spread_home_mfma(const float* __restrict__ sorted,
+__global__ __launch_bounds__(64 * kMfmaWaves) __attribute__((amdgpu_waves_per_eu(kMfmaWavesPerEu)))
+void spread_home_mfma(const float* __restrict__ sorted,
                                                        const int* __restrict__ offset,
                                                        float* __restrict__ tiles,
                                                        int* __restrict__ count, GridGeom g,
@@ -1569,23 +1584,28 @@ __device__ __forceinline__ void gather_brick_pf_body(
     lo[0] = (rest / bg.nb[1]) * bg.edge[0];
   };
   // the tile values of a brick this thread stages: row r = tid / 16 + 16 k
+  // k mod K for the tile's grid indices; with 8-point bricks an index is at
+  // most one period off (k in [-(P - 1), K + 7), K >= 8)
+  auto wrap = [](int k, int K) {
+    if (E8) {
+      k = k < 0 ? k + K : k;
+      return k >= K ? k - K : k;
+    }
+    while (k < 0) k += K;
+    while (k >= K) k -= K;
+    return k;
+  };
   auto load_tile = [&](int brick, T* reg) {
     int lo[3];
     lo_of(brick, lo);
     int r = tid >> 4;
     int t0 = r / H[1], t1 = r - t0 * H[1];
-    int k2 = lo[2] - (P - 1) + c16;
-    while (k2 < 0) k2 += K3;
-    while (k2 >= K3) k2 -= K3;
+    const int k2 = wrap(lo[2] - (P - 1) + c16, K3);
 #pragma unroll
     for (int k = 0; k < kPfRows; ++k) {
       reg[k] = T(0);
       if (r < nrows && c16 < H[2]) {
-        int k0 = lo[0] - (P - 1) + t0, k1 = lo[1] - (P - 1) + t1;
-        while (k0 < 0) k0 += K1;
-        while (k0 >= K1) k0 -= K1;
-        while (k1 < 0) k1 += K2;
-        while (k1 >= K2) k1 -= K2;
+        const int k0 = wrap(lo[0] - (P - 1) + t0, K1), k1 = wrap(lo[1] - (P - 1) + t1, K2);
         reg[k] = grid[(static_cast<long>(k0) * K2 + k1) * K3 + k2];
       }
       r += kGatherThreads / 16;
@@ -1652,23 +1672,33 @@ __device__ __forceinline__ void gather_brick_pf_body(
       }
       T phi = 0, g0 = 0, g1 = 0, g2 = 0;
       constexpr int UB = P <= 8 ? P : 1;
+      // the stencil's lowest tile point: every read below is at a
+      // non-negative, compile-time offset (E8) from a plane's start
+      const T* st0 = tile + ((l[0] - (P - 1)) * H[1] + l[1] - (P - 1)) * H[2] + l[2] - (P - 1);
+      // the x weights rotate down one place per plane (no indexed select)
+      T wr[P], dwr[P];
+#pragma unroll
+      for (int t = 0; t < P; ++t) {
+        wr[t] = w[0][t];
+        dwr[t] = dw[0][t];
+      }
 #pragma unroll 1
       for (int a = 0; a < P; ++a) {
-        T wa = w[0][0], dwa = dw[0][0];
+        const T wa = wr[0], dwa = dwr[0];
 #pragma unroll
-        for (int t = 1; t < P; ++t)
-          if (a == t) {
-            wa = w[0][t];
-            dwa = dw[0][t];
-          }
+        for (int t = 0; t + 1 < P; ++t) {
+          wr[t] = wr[t + 1];
+          dwr[t] = dwr[t + 1];
+        }
+        const T* plane = st0 + (P - 1 - a) * (H[1] * H[2]);
         T sa = 0, sa1 = 0, sa2 = 0;
 #pragma unroll UB
         for (int bb = 0; bb < P; ++bb) {
-          const T* row = tile + ((l[0] - a) * H[1] + l[1] - bb) * H[2] + l[2];
+          const T* row = plane + (P - 1 - bb) * H[2];
           T sv = 0, s2 = 0;
 #pragma unroll
           for (int c = 0; c < P; ++c) {
-            const T v = row[-c];
+            const T v = row[P - 1 - c];
             sv += w[2][c] * v;
             s2 += dw[2][c] * v;
           }
@@ -1993,7 +2023,7 @@ hipError_t spread_brick_p(const GridGeom& g, const Bins& b, const void* src, voi
   if constexpr (sizeof(T) == 4 && P <= 9) {
     // float grids: the matrix-core tile spread (every brick edge <= 8)
     const int* off = b.offset;
-    hipError_t e = launch_or_record<64 * kMfmaWaves, spread_home_mfma_body<P>>(
+    hipError_t e = launch_or_record_w<64 * kMfmaWaves, kMfmaWavesPerEu, spread_home_mfma_body<P>>(
         LS_SPREAD, spread_home_mfma<P>, dim3(b.geom.nbricks), 0, st, srt, off,
         static_cast<float*>(b.tiles), b.count, g, b.geom);
     if (e != hipSuccess) return e;
