@@ -377,7 +377,7 @@ kpme_status kpme_plan_profile_read(kpme_plan_t plan, double* total_ms, int64_t* 
 
 /* Project autotuner for the work splits of the Kronecker operator: the
  * stage-2 split (the number of term ranges per k3 slab, 1..8; the smallest
- * within 3% of the fastest is kept) and, for BF16X3/FP16X3 with K3 <= 128,
+ * within 3% of the fastest is kept) and, for BF16X3/FP16X3 with K3 <= 160,
  * the stage-1 split (workgroups per tile of 64 grid positions, 1..6; the
  * fastest is kept).  Times every candidate on `stream` with hipEvents and
  * records the choices in a process-wide cache and, when the environment
@@ -389,7 +389,7 @@ kpme_status kpme_plan_autotune(kpme_plan_t plan, void* stream);
 /* The stage-2 work split in use (-1 for an invalid handle). */
 int kpme_plan_stage2_parts(kpme_plan_t plan);
 /* The stage-1 split in use (workgroups per 64-position tile; used by BF16X3
- * and FP16X3 with K3 <= 128), -1 for an invalid handle. */
+ * and FP16X3 with K3 <= 160), -1 for an invalid handle. */
 int kpme_plan_stage1_split(kpme_plan_t plan);
 
 const char* kpme_status_string(kpme_status s);
