@@ -55,6 +55,9 @@ def parse():
                     help="time only the mixed path (short profiler runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="run 5 device copies of MIB MiB and exit (byte-counter calibration)")
+    ap.add_argument("--gemm-calibration", type=int, default=0, metavar="N",
+                    help="time the vendor library's dense N x N x N FP16 and BF16 GEMM "
+                         "(torch.matmul) and exit (the practical matrix-core rate)")
     a = ap.parse_args()
     if a.precision is None:
         a.precision = "bf16x3" if a.workload == "batch64" else "fp16x3"
@@ -108,6 +111,32 @@ def copy_calibration(mib):
     torch.cuda.synchronize()
     print(json.dumps({"copy_calibration_bytes_read": n * 4, "bytes_written": n * 4,
                       "dispatches": 5}), flush=True)
+
+
+def gemm_calibration(n, reps=20):
+    """Dense square GEMMs through torch.matmul (the vendor BLAS) in FP16 and
+    BF16: achieved TFLOP/s against the dense matrix-core peak, the rate a
+    library GEMM sustains on this device."""
+    import torch
+    out = {"gemm_calibration_n": n, "peak_tflops": 2500.0}
+    for name, dt in (("fp16", torch.float16), ("bf16", torch.bfloat16)):
+        g = torch.Generator(device="cuda").manual_seed(0)
+        a = torch.randn(n, n, device="cuda", dtype=dt, generator=g)
+        b = torch.randn(n, n, device="cuda", dtype=dt, generator=g)
+        for _ in range(3):
+            c = a @ b
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            c = a @ b
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / reps
+        tf = 2.0 * n ** 3 / us / 1e6
+        out[name] = {"us": us, "tflops": tf, "frac": tf / 2500.0}
+        del a, b, c
+    print(json.dumps(out), flush=True)
 
 
 def time_steps(plan, P, Q, out, steps, warmup):
@@ -296,6 +325,9 @@ def main():
     from paper_2601_18838_amd import kpme, systems
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.gemm_calibration:
+        gemm_calibration(args.gemm_calibration)
         return
     if args.workload == "batch64":
         bench_batch(args)

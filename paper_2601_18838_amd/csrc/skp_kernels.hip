@@ -550,6 +550,41 @@ __device__ __forceinline__ void stage2_x3_body(
       bh[j] = *reinterpret_cast<const v8*>(&Bvh[16 * (1 - j)]);
       bl[j] = *reinterpret_cast<const v8*>(&Bvl[16 * (1 - j)]);
     }
+    // T rows 2c, 2c + 1 of column tile j, multiplied by st and split into
+    // 16-bit hi/lo: the B operand of GEMM2's K chunk c (see below).  With
+    // 128 rows (kEarlySplit) chunk c is split once its rows are final, one
+    // column tile per step, while the remaining MFMAs run: in the last K step
+    // of GEMM1 for all but the last chunk, in the first two d steps of GEMM2
+    // for the last.  Other tile counts split every chunk before GEMM2 (the
+    // early form measured slower there: it spills at 96 x 96).
+    constexpr bool kEarlySplit = RT == 8;
+    v8 tbh[RT / 2][CT], tbl[RT / 2][CT];
+    auto split_tile = [&](int c, int j) {
+      v4 h0, l0, h1, l1;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        H h, l;
+        split_h<H>(st * acc1[2 * c][j][r], h, l);
+        h0[r] = h;
+        l0[r] = l;
+        split_h<H>(st * acc1[2 * c + 1][j][r], h, l);
+        h1[r] = h;
+        l1[r] = l;
+      }
+      tbh[c][j] = cat44<v4, v8>(h0, h1);
+      tbl[c][j] = cat44<v4, v8>(l0, l1);
+    };
+    // the split of chunk c, tile j, happens at GEMM1 step i = 2c + 2 + (j * 2 / CT)
+    // of the last kc (rows 2c, 2c + 1 were final at step 2c + 1), or for the
+    // last chunk at GEMM2 step dd = j * 2 / CT
+    auto split_at = [&](int i) {
+      if (!kEarlySplit) return;
+#pragma unroll
+      for (int c = 0; c < RT / 2 - 1; ++c)
+#pragma unroll
+        for (int j = 0; j < CT; ++j)
+          if (2 * c + 2 + (j * 2) / CT == i) split_tile(c, j);
+    };
     v8 ah, al, a1h, a1l;
     yfrag(0, ah, al);
     a1h = ah;
@@ -575,6 +610,7 @@ __device__ __forceinline__ void stage2_x3_body(
         for (int j = 0; j < CT; ++j) acc1[i][j] = mfma_h(ah, bl[j], acc1[i][j]);
 #pragma unroll
         for (int j = 0; j < CT; ++j) acc1[i][j] = mfma_h(al, bh[j], acc1[i][j]);
+        if (kc + 1 == NKC) split_at(i);
         ah = a1h;
         al = a1l;
         a1h = a2h;
@@ -595,25 +631,12 @@ __device__ __forceinline__ void stage2_x3_body(
     // into 16-bit hi/lo in place.  Because A_t is circulant, the A fragment of
     // output row tile i and chunk c depends on d = 2c - i only: the d loop
     // reads each distinct fragment once and applies it to every (c, i) pair.
-    v8 tbh[RT / 2][CT], tbl[RT / 2][CT];
+    if (!kEarlySplit) {
 #pragma unroll
-    for (int c = 0; c < RT / 2; ++c)
+      for (int c = 0; c < RT / 2; ++c)
 #pragma unroll
-      for (int j = 0; j < CT; ++j) {
-        v4 h0, l0, h1, l1;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          H h, l;
-          split_h<H>(st * acc1[2 * c][j][r], h, l);
-          h0[r] = h;
-          l0[r] = l;
-          split_h<H>(st * acc1[2 * c + 1][j][r], h, l);
-          h1[r] = h;
-          l1[r] = l;
-        }
-        tbh[c][j] = cat44<v4, v8>(h0, h1);
-        tbl[c][j] = cat44<v4, v8>(l0, l1);
-      }
+        for (int j = 0; j < CT; ++j) split_tile(c, j);
+    }
     auto afrag = [&](const H* base, int dd) {  // dd = d + RT - 1
       return cat44<v4, v8>(*reinterpret_cast<const v4*>(&base[16 * dd]),
                            *reinterpret_cast<const v4*>(&base[16 * dd + 16]));
@@ -628,6 +651,12 @@ __device__ __forceinline__ void stage2_x3_body(
         nl = afrag(Avl, dd + 1);
       }
       const int d = dd - (RT - 1);
+      // the last chunk (first used at dd = RT - 2 = 6)
+      if (kEarlySplit) {
+#pragma unroll
+        for (int j = 0; j < CT; ++j)
+          if ((j * 2) / CT == dd) split_tile(RT / 2 - 1, j);
+      }
 #pragma unroll
       for (int pass = 0; pass < 3; ++pass)
 #pragma unroll
