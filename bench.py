@@ -458,7 +458,8 @@ def main():
                                  f"{args.quad_tol:g}"),
                    "precision": mixed, "reference": "fp64 GPU path at equal R",
                    "stage2_parts": plans[mixed].stage2_parts(),
-                   "stage1_split": plans[mixed].stage1_split()},
+                   "stage1_split": plans[mixed].stage1_split(),
+                   "stage2_streams": plans[mixed].stage2_streams()},
         "ns_per_particle": t_mixed * 1e9 / n,
         "fp64_evals_per_s": 1.0 / t_ref,
         "fp64_ns_per_particle": t_ref * 1e9 / n,

@@ -375,11 +375,14 @@ enum {
 kpme_status kpme_plan_profile(kpme_plan_t plan, int enable);
 kpme_status kpme_plan_profile_read(kpme_plan_t plan, double* total_ms, int64_t* counts);
 
-/* Project autotuner for the work splits of the Kronecker operator: the
- * stage-2 split (the number of term ranges per k3 slab, 1..8; the smallest
- * within 3% of the fastest is kept) and, for BF16X3/FP16X3 with K3 <= 160,
- * the stage-1 split (workgroups per tile of 64 grid positions, 1..6; the
- * fastest is kept).  Times every candidate on `stream` with hipEvents and
+/* Project autotuner for the work shapes of the Kronecker operator: for
+ * BF16X3/FP16X3 the stage-2 term streams per workgroup (1 or 2: each stream
+ * has its own waves over the shared Y slab, so this sets the waves per
+ * workgroup), for each of them the stage-2 split (the number of term ranges
+ * per k3 slab, 1..8); the stream count of the fastest pair is kept, with the
+ * smallest split within 3% of that count's fastest (other precisions: the
+ * split alone); and, for BF16X3/FP16X3 with K3 <= 160, the stage-1 split
+ * (workgroups per tile of 64 grid positions, 1..6; the fastest is kept).  Times every candidate on `stream` with hipEvents and
  * records the choices in a process-wide cache and, when the environment
  * variable KPME_TUNE_CACHE names a file, on disk ("key value" lines keyed by
  * what is tuned, grid, order, R, r0 and precision), which later plans of the
@@ -391,6 +394,9 @@ int kpme_plan_stage2_parts(kpme_plan_t plan);
 /* The stage-1 split in use (workgroups per 64-position tile; used by BF16X3
  * and FP16X3 with K3 <= 160), -1 for an invalid handle. */
 int kpme_plan_stage1_split(kpme_plan_t plan);
+/* The stage-2 term streams per workgroup in use (BF16X3/FP16X3: 1 or 2;
+ * other precisions 1), -1 for an invalid handle. */
+int kpme_plan_stage2_streams(kpme_plan_t plan);
 
 const char* kpme_status_string(kpme_status s);
 const char* kpme_last_error(void);

@@ -140,6 +140,7 @@ struct kpme_plan_s {
   int* step_group = nullptr;
   int* step_begin = nullptr;
   int nsteps = 0, streams = 1;
+  std::vector<int> group_of;  // outer-SVD group of each term in device order (host)
   double* scratch = nullptr;  // 3 * kSumBlocks doubles
   double* scalars = nullptr;  // [0] sum(Q), [1..4] energy
   void* Qg = nullptr;         // internal grids
@@ -580,7 +581,7 @@ kpme_status kpme_plan_create_ex(kpme_plan_t* plan, const double box[3], const in
     return fail(KPME_ERROR_NOT_SUPPORTED, "K1 > 128 is not supported by the SKP kernels");
   if ((precision == KPME_BF16X3 || precision == KPME_FP16X3) && K1P == 128 && K2P > 128)
     return fail(KPME_ERROR_NOT_SUPPORTED, "split precisions need K2 <= 128 when K1 > 96");
-  if (stage2_lds_bytes(precision, K1P, K2P) > kMaxLds)
+  if (stage2_lds_bytes(precision, K1P, K2P, x3_streams(K1P, K2P)) > kMaxLds)
     return fail(KPME_ERROR_NOT_SUPPORTED, "K1 x K2 slab does not fit in LDS at this precision");
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
@@ -644,6 +645,16 @@ kpme_status kpme_plan_create_ex(kpme_plan_t* plan, const double box[3], const in
     if (tune_lookup(tune_key(pl), &cached) && cached >= 1) pl->nparts = std::min(cached, pl->max_parts);
     pl->s1_split = default_s1_split(r0, K3, K1P, K2P);
     if (tune_lookup(tune_key(pl, "s1split"), &cached) && cached >= 1) pl->s1_split = cached;
+    if (split) {
+      pl->streams = x3_streams(K1P, K2P);
+      if (tune_lookup(tune_key(pl, "s2streams"), &cached) && (cached == 1 || cached == 2))
+        pl->streams = cached;
+      // tuning override: term streams (waves per workgroup) in split stage 2
+      if (const char* env = std::getenv("KPME_STAGE2_STREAMS")) {
+        const int v = std::atoi(env);
+        if (v == 1 || v == 2) pl->streams = v;
+      }
+    }
     // tuning override: workgroups per position tile in split stage 1
     if (const char* env = std::getenv("KPME_STAGE1_SPLIT")) {
       const int v = std::atoi(env);
@@ -658,8 +669,8 @@ kpme_status kpme_plan_create_ex(kpme_plan_t* plan, const double box[3], const in
   const std::vector<int> pb = split_range(R, pl->nparts, pl->max_parts);
   std::vector<int> step_term, step_group;
   if (precision == KPME_BF16X3 || precision == KPME_FP16X3) {
-    pl->streams = x3_streams(K1P, K2P);
     build_steps(group_of, pl->streams, step_term, step_group);
+    pl->group_of = group_of;
   }
   pl->nsteps = static_cast<int>(step_group.size());
   const std::vector<int> sb = split_range(pl->nsteps, pl->nparts, pl->max_parts);
@@ -884,11 +895,13 @@ kpme_status kpme_plan_create_ex(kpme_plan_t* plan, const double box[3], const in
     pl->part_begin = static_cast<int*>(tmp);
     if ((e = hipMemcpy(tmp, pb.data(), pb.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess) break;
     if (pl->nsteps > 0) {
-      if ((e = plan_alloc(pl, &tmp, step_term.size() * sizeof(int))) != hipSuccess) break;
+      // room for the schedule of either stream count: R + r0 entries (a
+      // group's last step may leave a stream idle) and at most R steps
+      if ((e = plan_alloc(pl, &tmp, static_cast<size_t>(R + r0) * sizeof(int))) != hipSuccess) break;
       pl->step_term = static_cast<int*>(tmp);
       if ((e = hipMemcpy(tmp, step_term.data(), step_term.size() * sizeof(int),
                          hipMemcpyHostToDevice)) != hipSuccess) break;
-      if ((e = plan_alloc(pl, &tmp, step_group.size() * sizeof(int))) != hipSuccess) break;
+      if ((e = plan_alloc(pl, &tmp, static_cast<size_t>(R) * sizeof(int))) != hipSuccess) break;
       pl->step_group = static_cast<int*>(tmp);
       if ((e = hipMemcpy(tmp, step_group.data(), step_group.size() * sizeof(int),
                          hipMemcpyHostToDevice)) != hipSuccess) break;
@@ -1129,6 +1142,25 @@ kpme_status do_energy(kpme_plan_t plan, int64_t n, const void* q, const void* po
                   "energy");
 }
 
+// Stage-2 term streams per workgroup of the split paths (1 or 2): rebuilds
+// and uploads the step schedule, then the step ranges of the current split.
+hipError_t set_streams(kpme_plan_t plan, int ns) {
+  if (plan->nsteps == 0 || (ns != 1 && ns != 2)) return hipErrorInvalidValue;
+  std::vector<int> term, group;
+  build_steps(plan->group_of, ns, term, group);
+  if (term.size() > static_cast<size_t>(plan->R + plan->r0) || group.size() > static_cast<size_t>(plan->R))
+    return hipErrorInvalidValue;
+  hipError_t e = hipMemcpy(plan->step_term, term.data(), term.size() * sizeof(int),
+                           hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(plan->step_group, group.data(), group.size() * sizeof(int), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return e;
+  plan->streams = ns;
+  plan->nsteps = static_cast<int>(group.size());
+  const std::vector<int> sb = split_range(plan->nsteps, plan->nparts, plan->max_parts);
+  return hipMemcpy(plan->step_begin, sb.data(), sb.size() * sizeof(int), hipMemcpyHostToDevice);
+}
+
 hipError_t set_parts(kpme_plan_t plan, int np) {
   np = std::max(1, std::min(np, plan->max_parts));
   const std::vector<int> pb = split_range(plan->R, np, plan->max_parts);
@@ -1169,24 +1201,43 @@ extern "C" kpme_status kpme_plan_autotune(kpme_plan_t plan, void* stream) {
       return ms;
     return -1.f;
   };
-  // stage-2 term ranges: time every candidate; keep the smallest split within
-  // 3% of the fastest (fewer partial slabs to write and sum, and a choice
-  // that is stable against timing noise)
-  std::vector<std::pair<int, float>> timed;
-  for (int c : cands) {
-    if (c > plan->max_parts || c > plan->R) continue;
-    hipError_t e = set_parts(plan, c);
-    if (e != hipSuccess) { s = from_hip(e, "autotune"); break; }
-    const float ms = time_skp();
+  // stage-2 shape: for each term-stream count (split paths: 1 or 2 streams,
+  // i.e. the waves per workgroup) time every term-range split; the stream
+  // count of the fastest pair is kept, and with it the smallest split within
+  // 3% of that count's fastest (fewer partial slabs to write and sum, and a
+  // choice that is stable against timing noise)
+  std::vector<int> stream_cands = {plan->streams};
+  if (plan->nsteps > 0) stream_cands = {1, 2};
+  int best = plan->nparts, best_streams = plan->streams;
+  float best_ms = -1.f;
+  for (int ns : stream_cands) {
+    if (plan->nsteps > 0) {
+      hipError_t e = set_streams(plan, ns);
+      if (e != hipSuccess) { s = from_hip(e, "autotune"); break; }
+    }
+    std::vector<std::pair<int, float>> timed;
+    for (int c : cands) {
+      if (c > plan->max_parts || c > plan->R) continue;
+      hipError_t e = set_parts(plan, c);
+      if (e != hipSuccess) { s = from_hip(e, "autotune"); break; }
+      const float ms = time_skp();
+      if (s != KPME_SUCCESS) break;
+      if (ms >= 0.f) timed.emplace_back(c, ms);
+    }
     if (s != KPME_SUCCESS) break;
-    if (ms >= 0.f) timed.emplace_back(c, ms);
-  }
-  int best = plan->nparts;
-  if (!timed.empty()) {
+    if (timed.empty()) continue;
     float fastest = 1e30f;
     for (const auto& t : timed) fastest = std::min(fastest, t.second);
-    for (const auto& t : timed)
-      if (t.second <= 1.03f * fastest) { best = t.first; break; }  // cands ascend
+    if (best_ms < 0.f || fastest < best_ms) {
+      best_ms = fastest;
+      best_streams = ns;
+      for (const auto& t : timed)
+        if (t.second <= 1.03f * fastest) { best = t.first; break; }  // cands ascend
+    }
+  }
+  if (s == KPME_SUCCESS && plan->nsteps > 0) {
+    hipError_t e = set_streams(plan, best_streams);
+    if (e != hipSuccess) s = from_hip(e, "autotune");
   }
   if (s == KPME_SUCCESS) {
     hipError_t e = set_parts(plan, best);
@@ -1210,6 +1261,7 @@ extern "C" kpme_status kpme_plan_autotune(kpme_plan_t plan, void* stream) {
   (void)hipEventDestroy(e1);
   if (s != KPME_SUCCESS) return s;
   if (s1_tiled) tune_store(tune_key(plan, "s1split"), plan->s1_split);
+  if (plan->nsteps > 0) tune_store(tune_key(plan, "s2streams"), plan->streams);
   tune_store(tune_key(plan), best);
   return KPME_SUCCESS;
 }
@@ -1220,6 +1272,10 @@ extern "C" int kpme_plan_stage2_parts(kpme_plan_t plan) {
 
 extern "C" int kpme_plan_stage1_split(kpme_plan_t plan) {
   return (plan && plan->magic == kMagic) ? plan->s1_split : -1;
+}
+
+extern "C" int kpme_plan_stage2_streams(kpme_plan_t plan) {
+  return (plan && plan->magic == kMagic) ? plan->streams : -1;
 }
 
 kpme_status kpme_spread(kpme_plan_t plan, int64_t n, const void* pos, const void* q, void* grid,
@@ -1608,24 +1664,29 @@ kpme_status kpme_batch_create(kpme_batch_t* batch, int count, const double* box3
     b->plans.push_back(pl);
   }
   // autotune each distinct class once (cached in memory and on disk)
-  std::map<std::string, std::pair<int, int>> done;  // class -> (parts, stage-1 split)
+  struct Tuned {
+    int parts, s1_split, streams;
+  };
+  std::map<std::string, Tuned> done;  // class -> tuned values
   for (kpme_plan_t& pl : b->plans) {
     const std::string key = tune_key(pl);
     auto it = done.find(key);
     if (it != done.end()) {
-      const hipError_t e = set_parts(pl, it->second.first);
+      hipError_t e = hipSuccess;
+      if (pl->nsteps > 0 && pl->streams != it->second.streams) e = set_streams(pl, it->second.streams);
+      if (e == hipSuccess) e = set_parts(pl, it->second.parts);
       if (e != hipSuccess) {
         const std::string msg = "system " + std::to_string(&pl - b->plans.data()) +
                                 ": stage-2 split: " + hipGetErrorString(e);
         batch_free(b);
         return fail(e == hipErrorOutOfMemory ? KPME_ERROR_OUT_OF_MEMORY : KPME_ERROR_DEVICE, msg);
       }
-      pl->s1_split = it->second.second;
+      pl->s1_split = it->second.s1_split;
       continue;
     }
     int cached = 0;
     if (tune_lookup(key, &cached)) {
-      done[key] = {pl->nparts, pl->s1_split};
+      done[key] = {pl->nparts, pl->s1_split, pl->streams};
       continue;
     }
     kpme_status s = kpme_plan_autotune(pl, nullptr);
@@ -1633,7 +1694,7 @@ kpme_status kpme_batch_create(kpme_batch_t* batch, int count, const double* box3
       batch_free(b);
       return s;
     }
-    done[key] = {pl->nparts, pl->s1_split};
+    done[key] = {pl->nparts, pl->s1_split, pl->streams};
   }
   for (int k = 0; k < kBatchBranches; ++k) {
     if (hipStreamCreateWithFlags(&b->branch[k], hipStreamNonBlocking) != hipSuccess ||

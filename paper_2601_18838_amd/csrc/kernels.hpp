@@ -83,8 +83,10 @@ __host__ __device__ constexpr int x3_yswz(int NKC, int r) {
   return NKC == 4 ? (r & 15) : NKC == 2 ? ((r >> 1) & 7) : ((r >> 1) & 3);
 }
 // Split-precision stage 2 shape: column tiles of 16 per wave (CT) and term
-// streams per workgroup (NS).  96 x 96 slabs: two streams of two 48-column
-// waves (four-wave workgroups, two per CU: two waves on every SIMD).
+// streams per workgroup (NS, 1 or 2: every stream has its own waves over the
+// shared Y slab, so NS sets the waves per workgroup).  96 x 96 slabs: two
+// streams of two 48-column waves (four-wave workgroups, two per CU: two waves
+// on every SIMD).  x3_streams is the default; the autotuner times both.
 constexpr int x3_ct(int K1P, int K2P) { return (K1P == 96 && K2P == 96) ? 3 : 2; }
 constexpr int x3_streams(int K1P, int K2P) { return ((K1P == 96 && K2P == 96) || (K1P == 128 && K2P == 128)) ? 2 : 1; }
 
@@ -98,7 +100,7 @@ hipError_t launch_skp_stage2(const SkpArgs& a, hipStream_t st);
 // issued between launches (or inside a stream capture).
 hipError_t prepare_skp_stage2(const SkpArgs& a);
 hipError_t launch_skp_finalize(const SkpArgs& a, hipStream_t st);
-size_t stage2_lds_bytes(int prec, int K1P, int K2P);
+size_t stage2_lds_bytes(int prec, int K1P, int K2P, int streams);
 
 struct GridGeom {
   int K[3];

@@ -980,11 +980,12 @@ hipError_t set_lds(K kernel, size_t bytes) {
 }
 
 // prep: only raise the kernel instance's dynamic-LDS limit (plan creation,
-// outside any stream capture); otherwise launch.
-template <typename H, int RT, int NKC>
-hipError_t launch_s2_x3(const SkpArgs& a, hipStream_t st, bool prep) {
+// outside any stream capture); otherwise launch.  NS term streams per
+// workgroup (the plan's step schedule is built for that many).
+template <typename H, int RT, int NKC, int NS>
+hipError_t launch_s2_x3_ns(const SkpArgs& a, hipStream_t st, bool prep) {
   constexpr int K1P = RT * 16, K2P = NKC * 32;
-  constexpr int CT = x3_ct(K1P, K2P), NS = x3_streams(K1P, K2P);
+  constexpr int CT = x3_ct(K1P, K2P);
   const size_t tsz = 2 * static_cast<size_t>(x3_plane(K1P, K2P));
   const size_t lds = sizeof(H) * (2 * static_cast<size_t>(K1P) * K2P + 2 * NS * tsz);
   constexpr int NT = 64 * (2 * NKC / CT) * NS, W = RT >= 8 ? 1 : 2;
@@ -1009,6 +1010,19 @@ hipError_t launch_s2_x3(const SkpArgs& a, hipStream_t st, bool prep) {
   return launch_or_record_w<NT, W, stage2_x3_body<H, RT, NKC, CT, NS>>(
       LS_STAGE2, stage2_x3<H, RT, NKC, CT, NS>, dim3(a.K[2], a.nparts), lds, st, yh, yl, vec,
       sterm, sgroup, sbegin, ppart, a.K[0], a.K[1], a.K[2], a.st);
+}
+
+// One or two term streams; at plan creation (prep) both instances get their
+// LDS limit, since the autotuner may switch the plan between them.
+template <typename H, int RT, int NKC>
+hipError_t launch_s2_x3(const SkpArgs& a, hipStream_t st, bool prep) {
+  if (prep) {
+    hipError_t e = launch_s2_x3_ns<H, RT, NKC, 1>(a, st, true);
+    if (e == hipSuccess) e = launch_s2_x3_ns<H, RT, NKC, 2>(a, st, true);
+    return e;
+  }
+  if (a.x3_streams == 2) return launch_s2_x3_ns<H, RT, NKC, 2>(a, st, false);
+  return launch_s2_x3_ns<H, RT, NKC, 1>(a, st, false);
 }
 
 template <typename H, int RT>
@@ -1064,11 +1078,11 @@ hipError_t stage2_dispatch(const SkpArgs& a, hipStream_t st, bool prep) {
 
 }  // namespace
 
-size_t stage2_lds_bytes(int prec, int K1P, int K2P) {
+size_t stage2_lds_bytes(int prec, int K1P, int K2P, int streams) {
   if (prec == PREC_BF16X3 || prec == PREC_FP16X3) {
     // Y slab (two planes) + two buffers of circulant vectors per stream
     const size_t tsz = 2 * static_cast<size_t>(x3_plane(K1P, K2P));
-    return 2 * (2 * static_cast<size_t>(K1P) * K2P + 2 * x3_streams(K1P, K2P) * tsz);
+    return 2 * (2 * static_cast<size_t>(K1P) * K2P + 2 * static_cast<size_t>(streams) * tsz);
   }
   if (prec == PREC_FP32) return sizeof(float) * static_cast<size_t>(K1P) * (K2P + 1);
   return sizeof(double) * static_cast<size_t>(K1P) * (K2P + 1);

@@ -111,6 +111,8 @@ def lib():
         L.kpme_plan_stage2_parts.restype = ctypes.c_int
         L.kpme_plan_stage1_split.argtypes = [_P]
         L.kpme_plan_stage1_split.restype = ctypes.c_int
+        L.kpme_plan_stage2_streams.argtypes = [_P]
+        L.kpme_plan_stage2_streams.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -274,8 +276,8 @@ class Plan:
         return e4, pot, frc
 
     def autotune(self):
-        """Run the library's autotuner (stage-2 and stage-1 splits) on the current
-        stream; returns the stage-2 split."""
+        """Run the library's autotuner (stage-2 streams and split, stage-1 split)
+        on the current stream; returns the stage-2 split."""
         _check(lib().kpme_plan_autotune(self._h, _stream()))
         return self.stage2_parts()
 
@@ -284,6 +286,9 @@ class Plan:
 
     def stage1_split(self):
         return lib().kpme_plan_stage1_split(self._h)
+
+    def stage2_streams(self):
+        return lib().kpme_plan_stage2_streams(self._h)
 
     def profile(self, enable=True):
         """Switch the library's per-stage hipEvent timers on or off."""

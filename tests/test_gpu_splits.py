@@ -10,7 +10,12 @@
   the largest value, the FP16X3 grid tolerance of the parity tests (the
   per-term contributions exceed the result by the kernel's cancellation, so
   FP32 reordering moves it by a few 1e-6; measured 1.4e-6 on a 96^3 grid).
-Both on a 96^3 grid (two-stream stage 2) and a non-cubic one (one stream).
+* The stage-2 term streams per workgroup (1 or 2; the autotuner picks one)
+  change which terms share an accumulator in the same way: both stream
+  counts agree within the same 1e-5, and each matches the oracle's operator
+  to that bar.
+Both on a 96^3 grid (two-stream stage 2 by default) and a non-cubic one (one
+stream by default).
 """
 import os
 
@@ -78,3 +83,39 @@ def test_stage2_parts_agree(shape):
     scale = np.abs(ref).max()
     for o in outs[1:]:
         assert np.abs(o - ref).max() <= 1e-5 * scale
+
+
+@pytest.mark.parametrize("prec", ["fp16x3", "bf16x3"])
+@pytest.mark.parametrize("shape", SHAPES, ids=["96cubed", "40x50x60"])
+def test_stage2_streams_agree_and_match_the_oracle(shape, prec):
+    from oracle import skp
+    box, grid, rank = shape
+    print(f"[splits] stage-2 streams {grid} {prec}", flush=True)
+    q = random_grid(grid, 13)
+    ref = skp.Plan(box, grid, 4, 0.34, rank=rank).apply(q.cpu().double().numpy())
+    scale = np.abs(ref).max()
+    outs = []
+    for streams in (1, 2):
+        for parts in (1, 3):
+            pl = make_plan(box, grid, rank, prec,
+                           {"KPME_STAGE2_STREAMS": streams, "KPME_STAGE2_PARTS": parts})
+            assert pl.stage2_streams() == streams
+            o = pl.skp_apply(q).cpu().double().numpy()
+            err = np.abs(o - ref).max() / scale
+            print(f"  streams={streams} parts={parts}: {err:.2e}", flush=True)
+            assert err <= (1e-5 if prec == "fp16x3" else 1e-4)
+            outs.append(o)
+    for o in outs[1:]:
+        assert np.abs(o - outs[0]).max() <= (1e-5 if prec == "fp16x3" else 1e-4) * scale
+
+
+def test_autotune_keeps_a_valid_stage2_shape():
+    box, grid, rank = SHAPES[1]
+    print("[splits] autotune shape", flush=True)
+    q = random_grid(grid, 14)
+    pl = make_plan(box, grid, rank, "fp16x3", {})
+    before = pl.skp_apply(q).cpu().double().numpy()
+    parts = pl.autotune()
+    assert 1 <= parts <= 8 and pl.stage2_streams() in (1, 2) and pl.stage1_split() >= 1
+    after = pl.skp_apply(q).cpu().double().numpy()
+    assert np.abs(after - before).max() <= 1e-5 * np.abs(before).max()
