@@ -250,8 +250,10 @@ def bench_batch(args):
            "fp64_loop_ms": res["fp64"][0] * 1e3,
            "speedup_vs_fp64_loop": res["fp64"][0] / t,
            "max_rel_energy_err": float(rel.max()),
-           "batched_form": {"form": "one launch per stage and kernel instance" if form == 1
-                            else "per-system graph branches", "launches_per_batch": launches},
+           "batched_form": {"form": {1: "one launch per stage and kernel instance",
+                                     2: "persistent launches over a work queue"}.get(
+                                         form, "per-system graph branches"),
+                            "launches_per_batch": launches},
            "per_system_graph": {"ms_per_step": t_graph * 1e3, "launches_per_batch": launches2,
                                 "form": form2},
            "speedup_vs_per_system_graph": t_graph / t,

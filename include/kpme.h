@@ -329,7 +329,11 @@ kpme_status kpme_factors_compute_ex(const double box[3], const int grid[3],
  * system's workgroups (a per-launch table of argument tuples and system
  * slices in device memory, largest systems first); otherwise every system's
  * kpme_evaluate launch sequence on parallel graph branches.  The environment
- * variable KPME_BATCH_FUSED=0 forces the second form.  A signature change after
+ * variable KPME_BATCH_FUSED=0 forces the second form; KPME_BATCH_PERSISTENT=1
+ * records the batched launches in their persistent form (a grid of the
+ * resident workgroups that takes the concatenated grid's workgroups from a
+ * device counter in cost order, zeroed by a fill kernel at the head of the
+ * recording).  A signature change after
  * the first recording synchronises `stream` and then the whole device
  * before the previous recording is released and the new one captured, so
  * no recording ever overlaps a running replay; callers that evaluate in a
@@ -345,7 +349,8 @@ kpme_status kpme_batch_create(kpme_batch_t* batch, int count,
                               const int64_t* max_particles, int device);
 kpme_status kpme_batch_destroy(kpme_batch_t batch);
 /* The form of the batch's current recording (host outputs, may be NULL):
- * *form = 1 batched launches, 0 per-system graph, -1 nothing recorded yet;
+ * *form = 2 persistent batched launches, 1 batched launches, 0 per-system
+ * graph, -1 nothing recorded yet;
  * *launches = kernel launches (graph nodes) replayed per evaluation. */
 kpme_status kpme_batch_info(kpme_batch_t batch, int* form, int* launches);
 kpme_status kpme_batch_evaluate(kpme_batch_t batch, const int64_t* n,

@@ -188,7 +188,9 @@ struct kpme_batch_s {
   const void* sig_ptr[5] = {};
   // batched form: one launch per stage and kernel instance for all systems
   bool fused_allowed = true;
-  int mode = 0;                        // recorded form: 1 batched launches, 0 per-system graph
+  bool persistent = false;             // batched launches in their persistent (work-queue) form
+  int mode = 0;                        // recorded form: 2 persistent batched launches,
+                                       // 1 batched launches, 0 per-system graph
   int launches = 0;                    // kernel launches in the recorded graph
   void* table = nullptr;               // device argument tuples and slices of the batched launches
 };
@@ -1548,6 +1550,7 @@ kpme_status batch_record_fused(kpme_batch_s* batch, const int64_t* n, const void
   struct Group {
     int stage;
     const void* kernel;
+    const void* kernel_q;
     int threads;
     size_t lds = 0;
     size_t tsz;
@@ -1562,7 +1565,7 @@ kpme_status batch_record_fused(kpme_batch_s* batch, const int64_t* n, const void
     for (Group& c : groups)
       if (c.stage == r.stage && c.kernel == r.kernel) g = &c;
     if (!g) {
-      groups.push_back(Group{r.stage, r.kernel, r.threads, 0, r.tuple_size, {}});
+      groups.push_back(Group{r.stage, r.kernel, r.kernel_q, r.threads, 0, r.tuple_size, {}});
       g = &groups.back();
     }
     if (g->threads != r.threads || g->tsz != r.tuple_size) return KPME_ERROR_NOT_SUPPORTED;
@@ -1573,6 +1576,9 @@ kpme_status batch_record_fused(kpme_batch_s* batch, const int64_t* n, const void
                    [](const Group& a, const Group& b) { return a.stage < b.stage; });
   size_t bytes = 0;
   auto align = [](size_t v) { return (v + 255) & ~static_cast<size_t>(255); };
+  // persistent form: one queue counter per group at the head of the table
+  const size_t queue_bytes = batch->persistent ? align(groups.size() * sizeof(int)) : 0;
+  bytes = queue_bytes;
   for (Group& g : groups) {
     std::stable_sort(g.recs.begin(), g.recs.end(), [&](int a, int b) {
       return batch_cost(batch->plans[sys_of[a]]) > batch_cost(batch->plans[sys_of[b]]);
@@ -1605,17 +1611,47 @@ kpme_status batch_record_fused(kpme_batch_s* batch, const int64_t* n, const void
   }
   e = hipMemcpy(batch->table, host.data(), bytes, hipMemcpyHostToDevice);
   if (e != hipSuccess) return from_hip(e, "batch table");
+  // persistent form: each group's grid is the workgroups resident at once
+  // (occupancy of its kernel times the CUs), capped by its total
+  std::vector<int> pgrid(groups.size(), 0);
+  if (batch->persistent) {
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, batch->device);
+    if (e != hipSuccess) return from_hip(e, "device properties");
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+      int occ = 0;
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, groups[gi].kernel_q,
+                                                       groups[gi].threads, groups[gi].lds);
+      if (e != hipSuccess) return from_hip(e, "occupancy");
+      pgrid[gi] = std::max(1, std::min(groups[gi].total, std::max(occ, 1) * prop.multiProcessorCount));
+    }
+  }
   e = hipStreamBeginCapture(batch->capture, hipStreamCaptureModeThreadLocal);
   if (e != hipSuccess) return from_hip(e, "batch capture");
   int launched = 0;
-  for (Group& g : groups) {
+  if (batch->persistent) {
+    // the queue counters start at zero on every replay (a fill kernel: no
+    // memset node in the recording)
+    e = launch_zero(batch->table, queue_bytes, batch->capture);
+    if (e == hipSuccess) ++launched;
+  }
+  for (size_t gi = 0; gi < groups.size() && e == hipSuccess; ++gi) {
+    Group& g = groups[gi];
     if (g.total == 0) continue;
     const void* args = static_cast<const char*>(batch->table) + g.args_off;
     const BatchSlice* sl = reinterpret_cast<const BatchSlice*>(
         static_cast<const char*>(batch->table) + g.slice_off);
     int nsys = static_cast<int>(g.recs.size());
-    void* kargs[] = {&args, &sl, &nsys};
-    e = hipLaunchKernel(g.kernel, dim3(g.total), dim3(g.threads), kargs, g.lds, batch->capture);
+    if (batch->persistent) {
+      int total = g.total;
+      int* queue = static_cast<int*>(batch->table) + gi;
+      void* kargs[] = {&args, &sl, &nsys, &total, &queue};
+      e = hipLaunchKernel(g.kernel_q, dim3(pgrid[gi]), dim3(g.threads), kargs, g.lds,
+                          batch->capture);
+    } else {
+      void* kargs[] = {&args, &sl, &nsys};
+      e = hipLaunchKernel(g.kernel, dim3(g.total), dim3(g.threads), kargs, g.lds, batch->capture);
+    }
     if (e != hipSuccess) break;
     ++launched;
   }
@@ -1632,7 +1668,7 @@ kpme_status batch_record_fused(kpme_batch_s* batch, const int64_t* n, const void
     batch->exec = nullptr;
     return from_hip(e, "graph instantiate");
   }
-  batch->mode = 1;
+  batch->mode = batch->persistent ? 2 : 1;
   batch->launches = launched;
   return KPME_SUCCESS;
 }
@@ -1714,6 +1750,8 @@ kpme_status kpme_batch_create(kpme_batch_t* batch, int count, const double* box3
   auto cost = [&](int k) { return batch_cost(b->plans[k]); };
   // tuning override: KPME_BATCH_FUSED=0 keeps the per-system graph form
   if (const char* env = std::getenv("KPME_BATCH_FUSED")) b->fused_allowed = std::atoi(env) != 0;
+  // KPME_BATCH_PERSISTENT=1: batched launches in their persistent work-queue form
+  if (const char* env = std::getenv("KPME_BATCH_PERSISTENT")) b->persistent = std::atoi(env) != 0;
   std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return cost(x) > cost(y); });
   double load[kBatchBranches] = {0};
   b->branch_of.assign(count, 0);

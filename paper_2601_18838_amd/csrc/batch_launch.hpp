@@ -10,6 +10,12 @@
 // grid.  A system's evaluation then becomes, per kernel, one slice of a
 // launch shared by every system that uses the same kernel instance.
 //
+// Persistent form: a grid of at most the resident workgroups takes the
+// workgroups of the concatenated grid from a device counter, one at a time
+// in slice order (systems sorted by cost, largest first: an LPT work queue),
+// until all are done; the counter is zeroed by a fill kernel at the head of
+// the recording.
+//
 // Host side: while a LaunchRecorder is installed on the calling thread
 // (`launch_recorder()`), the launch functions append each launch (stage,
 // batched kernel instance, block size, dynamic LDS, grid, argument tuple) to
@@ -60,13 +66,12 @@ struct BatchSlice {
   int nx, ny, nz;
 };
 
+// Workgroup b of the concatenated grid: its system by binary search over
+// the slices, its coordinates in that system's grid, and the body on that
+// system's argument tuple.
 template <auto Body, typename... A>
-__device__ __forceinline__ void batched_run(const void* args, const BatchSlice* sl, int nsys) {
-  // hardware order: consecutive workgroups go to the XCDs in turn, so every
-  // system's slice is spread over the whole chip (grouping slices by XCD
-  // measured 10% slower on the 64-system batch: the per-workgroup cost
-  // differs between systems and the XCDs finish unevenly)
-  const int b = static_cast<int>(blockIdx.x);
+__device__ __forceinline__ void batched_item(const void* args, const BatchSlice* sl, int nsys,
+                                             int b) {
   int lo = 0, hi = nsys - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -87,6 +92,35 @@ __device__ __forceinline__ void batched_run(const void* args, const BatchSlice* 
   std::apply([&](auto... a) { Body(a..., w); }, t);
 }
 
+template <auto Body, typename... A>
+__device__ __forceinline__ void batched_run(const void* args, const BatchSlice* sl, int nsys) {
+  // hardware order: consecutive workgroups go to the XCDs in turn, so every
+  // system's slice is spread over the whole chip (grouping slices by XCD
+  // measured 10% slower on the 64-system batch: the per-workgroup cost
+  // differs between systems and the XCDs finish unevenly)
+  batched_item<Body, A...>(args, sl, nsys, static_cast<int>(blockIdx.x));
+}
+
+// The persistent loop: thread 0 takes the next item from the queue while the
+// current one runs; barriers keep the body's LDS and the broadcast slot from
+// being reused before every thread is done with them.
+template <auto Body, typename... A>
+__device__ __forceinline__ void batched_run_queue(const void* args, const BatchSlice* sl,
+                                                  int nsys, int total, int* queue) {
+  __shared__ int item;
+  int next = 0;
+  if (threadIdx.x == 0) next = atomicAdd(queue, 1);
+  for (;;) {
+    if (threadIdx.x == 0) item = next;
+    __syncthreads();
+    const int b = item;
+    __syncthreads();
+    if (b >= total) return;
+    if (threadIdx.x == 0) next = atomicAdd(queue, 1);
+    batched_item<Body, A...>(args, sl, nsys, b);
+  }
+}
+
 template <int NT, auto Body, typename... A>
 __global__ __launch_bounds__(NT) void batched_kernel(const void* args, const BatchSlice* sl,
                                                      int nsys) {
@@ -98,6 +132,19 @@ template <int NT, int W, auto Body, typename... A>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(W))) void batched_kernel_w(
     const void* args, const BatchSlice* sl, int nsys) {
   batched_run<Body, A...>(args, sl, nsys);
+}
+
+// Persistent forms of the two.
+template <int NT, auto Body, typename... A>
+__global__ __launch_bounds__(NT) void batched_kernel_q(const void* args, const BatchSlice* sl,
+                                                       int nsys, int total, int* queue) {
+  batched_run_queue<Body, A...>(args, sl, nsys, total, queue);
+}
+
+template <int NT, int W, auto Body, typename... A>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(W))) void batched_kernel_wq(
+    const void* args, const BatchSlice* sl, int nsys, int total, int* queue) {
+  batched_run_queue<Body, A...>(args, sl, nsys, total, queue);
 }
 
 // Stages of one evaluation, in launch order (a system's launches carry
@@ -118,6 +165,7 @@ enum LaunchStage {
 struct LaunchRecord {
   int stage;
   const void* kernel;   // batched kernel instance (groups records)
+  const void* kernel_q; // its persistent form
   int threads;
   size_t lds;
   int nx, ny, nz;
@@ -143,6 +191,7 @@ hipError_t launch_or_record(int stage, K plain, dim3 grid, size_t lds, hipStream
     LaunchRecord rec;
     rec.stage = stage;
     rec.kernel = reinterpret_cast<const void*>(&batched_kernel<NT, Body, A...>);
+    rec.kernel_q = reinterpret_cast<const void*>(&batched_kernel_q<NT, Body, A...>);
     rec.threads = NT;
     rec.lds = lds;
     rec.nx = static_cast<int>(grid.x);
@@ -168,6 +217,7 @@ hipError_t launch_or_record_w(int stage, K plain, dim3 grid, size_t lds, hipStre
     LaunchRecord rec;
     rec.stage = stage;
     rec.kernel = reinterpret_cast<const void*>(&batched_kernel_w<NT, W, Body, A...>);
+    rec.kernel_q = reinterpret_cast<const void*>(&batched_kernel_wq<NT, W, Body, A...>);
     rec.threads = NT;
     rec.lds = lds;
     rec.nx = static_cast<int>(grid.x);
@@ -189,6 +239,10 @@ hipError_t launch_or_record_w(int stage, K plain, dim3 grid, size_t lds, hipStre
 template <int NT, int W, auto Body, typename... A>
 const void* batched_kernel_w_of(A...) {
   return reinterpret_cast<const void*>(&batched_kernel_w<NT, W, Body, A...>);
+}
+template <int NT, int W, auto Body, typename... A>
+const void* batched_kernel_wq_of(A...) {
+  return reinterpret_cast<const void*>(&batched_kernel_wq<NT, W, Body, A...>);
 }
 
 // Marks the recorder when a launch without a batched form is reached.

@@ -997,11 +997,16 @@ hipError_t launch_s2_x3_ns(const SkpArgs& a, hipStream_t st, bool prep) {
   const int* sbegin = a.step_begin;
   float* ppart = static_cast<float*>(a.Phi_part);
   if (prep) {
-    // the plain instance and the batched one
+    // the plain instance and the batched ones (grid and persistent forms)
     hipError_t e = set_lds(stage2_x3<H, RT, NKC, CT, NS>, lds);
     if (e != hipSuccess) return e;
-    return batched_set_lds(
+    e = batched_set_lds(
         batched_kernel_w_of<NT, W, stage2_x3_body<H, RT, NKC, CT, NS>>(
+            yh, yl, vec, sterm, sgroup, sbegin, ppart, a.K[0], a.K[1], a.K[2], a.st),
+        lds);
+    if (e != hipSuccess) return e;
+    return batched_set_lds(
+        batched_kernel_wq_of<NT, W, stage2_x3_body<H, RT, NKC, CT, NS>>(
             yh, yl, vec, sterm, sgroup, sbegin, ppart, a.K[0], a.K[1], a.K[2], a.st),
         lds);
   }

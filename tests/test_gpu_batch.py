@@ -164,6 +164,42 @@ def test_batched_launches_match_per_system_graph(prec, monkeypatch):
         off += wl.n
 
 
+@pytest.mark.parametrize("prec", ["bf16x3", "fp16x3"])
+def test_persistent_batched_launches_match_the_grid_form(prec, monkeypatch):
+    """The batched launches in their persistent form (resident workgroups
+    taking the concatenated grid's workgroups from a zeroed device counter,
+    largest systems first) run the same items as the grid form: energies to
+    1e-6 relative, potentials and forces to 1e-5 relative RMS; two replays of
+    the recording (the counters restart from zero on each) agree."""
+    batch = systems.batch_systems(count=64)
+    print(f"[batch] persistent vs grid form, 64 systems {prec}", flush=True)
+    bp, pos, q, n = build(batch, prec)
+    ea, pa, fa = [x.clone() for x in bp.evaluate(n, pos, q)]
+    assert bp.info()[0] == 1
+    del bp
+    monkeypatch.setenv("KPME_BATCH_PERSISTENT", "1")
+    bp, pos, q, n = build(batch, prec)
+    e4 = torch.empty_like(ea)
+    pot = torch.empty_like(pa)
+    frc = torch.empty_like(fa)
+    outs = []
+    for _ in range(2):
+        bp.evaluate(n, pos, q, energy=e4, pot=pot, force=frc)
+        torch.cuda.synchronize()
+        outs.append((e4.cpu().numpy().copy(), pot.double().cpu().numpy(), frc.double().cpu().numpy()))
+    form, launches = bp.info()
+    assert form == 2 and launches < 45
+    eref = ea.cpu().numpy()
+    for eb, pb, fb in outs:
+        assert np.all(np.abs(eb[:, 0] - eref[:, 0]) <= 1e-6 * np.abs(eref[:, 0]))
+        off = 0
+        for k, (wl, _, _) in enumerate(batch):
+            sl = slice(off, off + wl.n)
+            assert relrms(pb[sl], pa[sl].double().cpu().numpy()) < 1e-5, k
+            assert relrms(fb[sl], fa[sl].double().cpu().numpy()) < 1e-5, k
+            off += wl.n
+
+
 @pytest.mark.skip(reason="a run of this test (re-recording while the previous replay could "
                          "still run) ended in SIGSEGV in a HIP runtime thread; re-recording now "
                          "drains the device first, but the crash's cause was never shown, so "
