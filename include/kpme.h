@@ -320,8 +320,10 @@ kpme_status kpme_factors_compute_ex(const double box[3], const int grid[3],
  * kpme_batch_create builds one plan per system (one precision for all; host
  * arrays box3[3*count], grid3[3*count], spline_order, beta, skp_rank,
  * max_particles), autotunes every distinct (grid, order, R, precision) class
- * once, and orders the systems by longest-processing-time on an estimated
- * cost.  kpme_batch_evaluate records, for a new argument signature (n[] and
+ * once, caps every system's stage-2 split at the smallest value that still
+ * gives the batch two stage-2 workgroups per CU (the systems fill the device
+ * together; override KPME_BATCH_PARTS), and orders the systems by
+ * longest-processing-time on an estimated cost.  kpme_batch_evaluate records, for a new argument signature (n[] and
  * the five pointers), one HIP graph and replays it as a single launch on
  * `stream`; an unchanged signature only replays.  The recording is, where
  * every system's kernels have a batched form (the mixed-precision paths),

@@ -1732,6 +1732,36 @@ kpme_status kpme_batch_create(kpme_batch_t* batch, int count, const double* box3
     }
     done[key] = {pl->nparts, pl->s1_split, pl->streams};
   }
+  // The per-class tuning optimises one system alone on the whole device: it
+  // splits a slab's terms over several workgroups to fill the CUs, at the
+  // cost of a partial slab per range for finalize to write and sum.  In a
+  // batch the systems fill the device together, so every system's split is
+  // capped at the smallest c for which the batch's stage-2 workgroups,
+  // sum_s K3_s min(parts_s, c), still number at least two per CU (on the
+  // 64-system batch: c = 1, 3.13 -> 2.97 ms).  Tuning override:
+  // KPME_BATCH_PARTS=c.
+  int cap = 1;
+  for (; cap < kMaxParts; ++cap) {
+    long wgs = 0;
+    for (kpme_plan_t pl : b->plans) wgs += static_cast<long>(pl->K[2]) * std::min(pl->nparts, cap);
+    if (wgs >= 2 * 256) break;
+  }
+  if (const char* env = std::getenv("KPME_BATCH_PARTS")) {
+    const int v = std::atoi(env);
+    if (v >= 1) cap = v;
+  }
+  {
+    const int v = cap;
+    for (size_t k = 0; k < b->plans.size(); ++k) {
+      kpme_plan_t pl = b->plans[k];
+      const hipError_t e = set_parts(pl, std::min(pl->nparts, v));
+      if (e != hipSuccess) {
+        batch_free(b);
+        const std::string msg = "system " + std::to_string(k) + ": stage-2 split";
+        return from_hip(e, msg.c_str());
+      }
+    }
+  }
   for (int k = 0; k < kBatchBranches; ++k) {
     if (hipStreamCreateWithFlags(&b->branch[k], hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming) != hipSuccess) {
