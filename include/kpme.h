@@ -178,10 +178,10 @@ typedef struct {
  *   grid[3]       host, 4 <= K_j <= 256 and K_j >= spline_order
  *                 (KPME_ERROR_INVALID_VALUE otherwise).  The operator
  *                 kernels further need K1 <= 128, and, for KPME_BF16X3 and
- *                 KPME_FP16X3 with K1 > 96, K2 <= 128; and the K1 x K2
- *                 slab must fit in the 160 KiB of LDS at the plan's
- *                 precision (K1 = K2 = 128 fits every precision).  Grids
- *                 outside these limits return KPME_ERROR_NOT_SUPPORTED.
+ *                 KPME_FP16X3, K2 <= 128; and the K1 x K2 slab must fit in
+ *                 the 160 KiB of LDS at the plan's precision (K1 = K2 = 128
+ *                 fits every precision).  Grids outside these limits return
+ *                 KPME_ERROR_NOT_SUPPORTED before any device work.
  *   spline_order  even, 4..12 (odd orders: KPME_ERROR_NOT_SUPPORTED).
  *   ewald_beta    > 0, the Ewald splitting parameter (xi in Eq. hexpr).
  *   skp_rank      R >= 1, or <= 0 to select R by svd_tol; R larger than the

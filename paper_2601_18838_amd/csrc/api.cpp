@@ -581,8 +581,8 @@ kpme_status kpme_plan_create_ex(kpme_plan_t* plan, const double box[3], const in
   const int K1P = round_up(grid[0], 32), K2P = round_up(grid[1], 32), K3P = round_up(grid[2], 32);
   if (K1P > 128)
     return fail(KPME_ERROR_NOT_SUPPORTED, "K1 > 128 is not supported by the SKP kernels");
-  if ((precision == KPME_BF16X3 || precision == KPME_FP16X3) && K1P == 128 && K2P > 128)
-    return fail(KPME_ERROR_NOT_SUPPORTED, "split precisions need K2 <= 128 when K1 > 96");
+  if ((precision == KPME_BF16X3 || precision == KPME_FP16X3) && K2P > 128)
+    return fail(KPME_ERROR_NOT_SUPPORTED, "split precisions need K2 <= 128");
   if (stage2_lds_bytes(precision, K1P, K2P, x3_streams(K1P, K2P)) > kMaxLds)
     return fail(KPME_ERROR_NOT_SUPPORTED, "K1 x K2 slab does not fit in LDS at this precision");
   int ndev = 0;

@@ -49,6 +49,8 @@ def _create(box=(20, 20, 20), grid=(16, 16, 16), p=4, beta=0.35, rank=8, tol=0.0
     (dict(grid=(16, 16, 300)), 1), (dict(grid=(6, 16, 16), p=8), 1), (dict(beta=-1.0), 1),
     (dict(rank=0, tol=0.0), 1), (dict(rank=0, tol=2.0), 1), (dict(prec=7), 1),
     (dict(nmax=0), 1), (dict(grid=(160, 16, 16)), 2),
+    # the split-precision stage-2 kernels hold at most 128 columns
+    (dict(grid=(32, 160, 32), prec=2), 2), (dict(grid=(32, 160, 32), prec=3), 2),
 ])
 def test_plan_create_validates_before_touching_a_device(kw, code):
     st, h = _create(**kw)
