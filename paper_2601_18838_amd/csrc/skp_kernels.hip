@@ -1048,7 +1048,8 @@ hipError_t launch_s2_k4(const SkpArgs& a, hipStream_t st, bool prep) {
   if (AL) lds += sizeof(T) * static_cast<size_t>(K1P) * (K1P + 1);
   if (prep) return set_lds(stage2_k4<T, RT, CT, AL>, lds);
   if (record_unsupported()) return hipSuccess;
-  const int threads = 64 * (a.K2P / (16 * CT));
+  const int threads = 64 * ((a.K2P + 16 * CT - 1) / (16 * CT));
+  if (threads > 512) return hipErrorInvalidValue;  // the kernel's launch bound
   hipLaunchKernelGGL((stage2_k4<T, RT, CT, AL>), dim3(a.K[2], a.nparts), dim3(threads), lds, st,
                      static_cast<const T*>(a.Y[0]), static_cast<const T*>(a.A[0]),
                      static_cast<const T*>(a.B[0]), a.term_group, a.part_begin,
@@ -1066,7 +1067,12 @@ hipError_t dispatch_s2(const SkpArgs& a, hipStream_t st, bool prep) {
     return full <= kMaxLds ? launch_s2_k4<float, RT, 2, true>(a, st, prep)
                            : launch_s2_k4<float, RT, 2, false>(a, st, prep);
   }
+  // FP64: one 16-column tile per wave up to K2P = 128 (eight waves), two
+  // beyond (at most eight waves for K2P = 256)
   const size_t full = sizeof(double) * static_cast<size_t>(K1P) * (a.K2P + 1 + K1P + 1);
+  if (a.K2P > 128)
+    return full <= kMaxLds ? launch_s2_k4<double, RT, 2, true>(a, st, prep)
+                           : launch_s2_k4<double, RT, 2, false>(a, st, prep);
   return full <= kMaxLds ? launch_s2_k4<double, RT, 1, true>(a, st, prep)
                          : launch_s2_k4<double, RT, 1, false>(a, st, prep);
 }

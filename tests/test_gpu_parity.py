@@ -94,6 +94,9 @@ CASES = {
     "k1p_k2p_128": ((50.0, 55.0, 12.0), (100, 110, 24), 4, 0.5, 16, 3000, "pm1", 22),
     # K3 = 160: the LDS-tiled stage 1 with five K chunks
     "k3p_160": ((24.0, 40.0, 160.0), (24, 40, 160), 6, 0.34, 20, 2001, "water", 18),
+    # K2 = 144 (K2P = 160 > 128): FP64/FP32 stage 2 with 160 columns; the
+    # split precisions refuse the plan (NOT_SUPPORTED) before any device work
+    "k2p_160": ((20.0, 72.0, 16.0), (20, 144, 16), 4, 0.5, 10, 1200, "pm1", 24),
     # K3 = 200 (K3P = 224 > 160): the one-wave stage 1 that loops over K chunks
     "k3p_224": ((16.0, 24.0, 100.0), (16, 24, 200), 4, 0.6, 12, 1500, "pm1", 23),
     # the largest grid of the batched workload: 96 x 128 x 160, order 6, more
@@ -156,6 +159,11 @@ def test_stages_match_oracle(case, form, prec, monkeypatch):
     if form != "auto":
         monkeypatch.setenv("KPME_SPARSE", "1" if form == "sparse" else "0")
     box, grid, p, beta, rank, pos, q = make(case)
+    if prec in ("bf16x3", "fp16x3") and grid[1] > 128:
+        with pytest.raises(kp().KpmeError) as e:
+            kp().Plan(box, grid, p, beta, rank=rank, precision=prec, max_particles=len(q))
+        assert e.value.status == 2
+        return
     orc = oracle_plan(box, grid, p, beta, rank=rank)
     ref = orc.evaluate(pos, q)
     pl = kp().Plan(box, grid, p, beta, rank=rank, precision=prec, max_particles=len(q))
