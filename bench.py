@@ -69,18 +69,32 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-# the stage-2 kernels and the header that picks their instance (tiles, streams)
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2601_18838_amd", "csrc", f)
-                  for f in ("skp_kernels.hip", "kernels.hpp")]
+# what the split-precision stage-2 kernel is built from: its source text in
+# skp_kernels.hip (from the section comment to the FP32/FP64 kernel's), the
+# header that picks its instance (tiles, streams) and the device helpers it
+# calls (fragments, splits, MFMA wrappers)
+CSRC = os.path.join(ROOT, "paper_2601_18838_amd", "csrc")
+STAGE2_SECTION = ("// Stage 2, split precision.", "// Stage 2, FP32 / FP64 with the 16x16x4 MFMAs.")
 HBM_PEAK_GBS = 8000.0
+
+
+def stage2_source_sha():
+    """SHA-256 of the stage-2 kernel's source text and the headers it uses."""
+    import hashlib
+    text = open(os.path.join(CSRC, "skp_kernels.hip"), encoding="utf-8").read()
+    a = text.index(STAGE2_SECTION[0])
+    b = text.index(STAGE2_SECTION[1], a)
+    h = hashlib.sha256(text[a:b].encode())
+    for f in ("kernels.hpp", "device_common.hpp"):
+        h.update(open(os.path.join(CSRC, f), "rb").read())
+    return h.hexdigest()
 
 
 def committed_traffic(workload, precision, parts):
     """HBM bytes per stage-2 launch from the committed rocprofv3 counter summary
     for this workload (FETCH_SIZE and WRITE_SIZE, scaled by the copy-kernel
     calibration), or None when there is none, it is for another configuration,
-    or the kernel source has changed since the counters were taken."""
-    import hashlib
+    or the kernel's source has changed since the counters were taken."""
     summary = os.path.join(ROOT, "profiles", f"stage2_x3_{workload}_traffic.md")
     try:
         fields = {}
@@ -88,10 +102,7 @@ def committed_traffic(workload, precision, parts):
             if line.startswith("- ") and ": " in line:
                 k, v = line[2:].strip().split(": ", 1)
                 fields[k] = v.strip("` ")
-        h = hashlib.sha256()
-        for src in KERNEL_SOURCES:
-            h.update(open(src, "rb").read())
-        sha = h.hexdigest()
+        sha = stage2_source_sha()
         if (fields.get("source_sha256") != sha or fields.get("workload") != workload
                 or fields.get("precision") != precision or int(fields.get("stage2_parts", -1)) != parts):
             return None
