@@ -996,12 +996,26 @@ __device__ __forceinline__ void spread_combine_pf_body(
   const int x[3] = {x0, x1, x2};
   // the eight (tile, offset) pairs of point x in owner brick `brick`, in the
   // order of the general kernel, and whether each lies in its tile
-  auto locate = [&](int brick, long* at, bool* in, long* gat) {
-    int own[3], rest = brick;
+  // brick coordinates, advanced one brick at a time along the range (one
+  // division for the first brick only)
+  int own[3];
+  {
+    int rest = b_begin;
     own[2] = rest % bg.nb[2];
     rest /= bg.nb[2];
     own[1] = rest % bg.nb[1];
     own[0] = rest / bg.nb[1];
+  }
+  auto advance = [&]() {
+    if (++own[2] == bg.nb[2]) {
+      own[2] = 0;
+      if (++own[1] == bg.nb[1]) {
+        own[1] = 0;
+        ++own[0];
+      }
+    }
+  };
+  auto locate = [&](long* at, bool* in, long* gat) {
     int hid[3][2], l[3][2];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
@@ -1022,8 +1036,11 @@ __device__ __forceinline__ void spread_combine_pf_body(
     for (int q = 0; q < 8; ++q) {
       const int a = q >> 2, b = (q >> 1) & 1, c = q & 1;
       in[q] = has && l[0][a] < H[0] && l[1][b] < H[1] && l[2][c] < H[2];
+      // clamped into the tile: every lane loads (no divergent branch), and
+      // the values outside it are dropped by the select below
       at[q] = static_cast<long>((hid[0][a] * bg.nb[1] + hid[1][b]) * bg.nb[2] + hid[2][c]) * ntile +
-              (l[0][a] * H[1] + l[1][b]) * H[2] + l[2][c];
+              (min(l[0][a], H[0] - 1) * H[1] + min(l[1][b], H[1] - 1)) * H[2] +
+              min(l[2][c], H[2] - 1);
     }
     *gat = (static_cast<long>(own[0] * bg.edge[0] + x0) * g.K[1] + own[1] * bg.edge[1] + x1) *
                g.K[2] + own[2] * bg.edge[2] + x2;
@@ -1033,9 +1050,12 @@ __device__ __forceinline__ void spread_combine_pf_body(
   long gat = 0;
   if (b_begin < b_end) {
     long at[8];
-    locate(b_begin, at, in, &gat);
+    locate(at, in, &gat);
 #pragma unroll
-    for (int q = 0; q < 8; ++q) v[q] = in[q] ? tiles[at[q]] : T(0);
+    for (int q = 0; q < 8; ++q) {
+      const T t = tiles[at[q]];
+      v[q] = in[q] ? t : T(0);
+    }
   }
   double s = 0.0, m = 0.0;
   for (int brick = b_begin; brick < b_end; ++brick) {
@@ -1049,9 +1069,13 @@ __device__ __forceinline__ void spread_combine_pf_body(
     const long cgat = gat;
     if (brick + 1 < b_end) {   // the next brick's values in flight
       long at[8];
-      locate(brick + 1, at, in, &gat);
+      advance();
+      locate(at, in, &gat);
 #pragma unroll
-      for (int q = 0; q < 8; ++q) v[q] = in[q] ? tiles[at[q]] : T(0);
+      for (int q = 0; q < 8; ++q) {
+      const T t = tiles[at[q]];
+      v[q] = in[q] ? t : T(0);
+    }
     }
     if (has) {
       double acc = 0.0;
@@ -1602,14 +1626,14 @@ __device__ __forceinline__ void gather_brick_pf_body(
     lo_of(brick, lo);
     int r = tid >> 4;
     int t0 = r / H[1], t1 = r - t0 * H[1];
-    const int k2 = wrap(lo[2] - (P - 1) + c16, K3);
+    const int k2 = wrap(lo[2] - (P - 1) + min(c16, H[2] - 1), K3);
 #pragma unroll
     for (int k = 0; k < kPfRows; ++k) {
-      reg[k] = T(0);
-      if (r < nrows && c16 < H[2]) {
-        const int k0 = wrap(lo[0] - (P - 1) + t0, K1), k1 = wrap(lo[1] - (P - 1) + t1, K2);
-        reg[k] = grid[(static_cast<long>(k0) * K2 + k1) * K3 + k2];
-      }
+      // every lane loads (rows past the tile and lanes past H2 read a
+      // clamped in-tile point, and their values are not stored)
+      const int tt0 = min(t0, H[0] - 1);
+      const int k0 = wrap(lo[0] - (P - 1) + tt0, K1), k1 = wrap(lo[1] - (P - 1) + t1, K2);
+      reg[k] = grid[(static_cast<long>(k0) * K2 + k1) * K3 + k2];
       r += kGatherThreads / 16;
       t1 += kGatherThreads / 16;
       while (t1 >= H[1]) {
