@@ -280,12 +280,15 @@ __device__ __forceinline__ void stage1_x3_lds_body(
     }
   }
   __syncthreads();
-  // A fragments of the whole K range: tile u, lane (q, m) holds row
-  // 16 (m / 4) + 4 u + m % 4, columns 32 kc + 8 q .. + 7
+  // A fragments of the whole K range: tile u, lane (q, m) holds position
+  // row 8 (m / 4) + 4 u + m % 4 (u < 2), 32 + 8 (m / 4) + 4 (u - 2) + m % 4
+  // (u >= 2), columns 32 kc + 8 q .. + 7, so that output lane (q, m) holds
+  // positions 8 q .. 8 q + 7 and 32 + 8 q .. + 7 of column m: each Y store
+  // instruction then writes 64 contiguous bytes per column
   v8 ah[NK][4], al[NK][4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    const int r = 16 * (m >> 2) + 4 * u + (m & 3);
+    const int r = u < 2 ? 8 * (m >> 2) + 4 * u + (m & 3) : 32 + 8 * (m >> 2) + 4 * (u - 2) + (m & 3);
 #pragma unroll
     for (int kc = 0; kc < NK; ++kc) {
       ah[kc][u] = *reinterpret_cast<const v8*>(&Qh[r * QSTR + 32 * kc + 8 * q]);
@@ -341,11 +344,11 @@ __device__ __forceinline__ void stage1_x3_lds_body(
           yh[u >> 1][4 * (u & 1) + r] = h;
           yl[u >> 1][4 * (u & 1) + r] = l;
         }
-      const long o = static_cast<long>(n) * slab + p0 + 16 * q;
+      const long o = static_cast<long>(n) * slab + p0 + 8 * q;
       *reinterpret_cast<v8*>(&Yhi[o]) = yh[0];
-      *reinterpret_cast<v8*>(&Yhi[o + 8]) = yh[1];
+      *reinterpret_cast<v8*>(&Yhi[o + 32]) = yh[1];
       *reinterpret_cast<v8*>(&Ylo[o]) = yl[0];
-      *reinterpret_cast<v8*>(&Ylo[o + 8]) = yl[1];
+      *reinterpret_cast<v8*>(&Ylo[o + 32]) = yl[1];
     }
   }
 }
