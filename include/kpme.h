@@ -198,7 +198,7 @@ kpme_status kpme_plan_create(kpme_plan_t* plan, const double box[3],
 /* kpme_plan_create with options (NULL: defaults): the kernel compression
  * method (nested SVD or sinc quadrature) and its parameters.  Arguments,
  * errors and ownership as for kpme_plan_create; invalid options give
- * KPME_ERROR_INVALID_VALUE, options this build does not implement
+ * KPME_ERROR_INVALID_VALUE, options the library does not implement
  * KPME_ERROR_NOT_SUPPORTED. */
 kpme_status kpme_plan_create_ex(kpme_plan_t* plan, const double box[3],
                                 const int grid[3], int spline_order,
