@@ -870,8 +870,15 @@ kpme_status kpme_plan_create_ex(kpme_plan_t* plan, const double box[3], const in
   // (edge + p - 1)^3 values per brick for a handful of particles, so the
   // owner spread (FP64 LDS tile of the brick itself) is used instead.
   // Tuning override: KPME_SPARSE=0/1.
+  double density = kSparseDensity;
+  // tuning override: KPME_SPARSE_DENSITY = particles per brick below which
+  // a plan goes sparse
+  if (const char* env = std::getenv("KPME_SPARSE_DENSITY")) {
+    const double v = std::atof(env);
+    if (v > 0.0) density = v;
+  }
   bg.sparse = spline_order >= 4 && spline_order <= 9 &&
-              static_cast<double>(max_particles) < kSparseDensity * bg.nbricks;
+              static_cast<double>(max_particles) < density * bg.nbricks;
   if (const char* env = std::getenv("KPME_SPARSE"))
     bg.sparse = spline_order >= 4 && spline_order <= 9 && std::atoi(env) != 0;
   pl->spread_parts = spread_partials(bg, spline_order, precision == KPME_FP64);
