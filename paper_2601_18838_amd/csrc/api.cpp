@@ -172,6 +172,8 @@ struct kpme_plan_s {
 
 constexpr int kBatchBranches = 4;  // parallel branches of the batch graph
 constexpr double kSparseDensity = 64.0;  // particles per brick below which orders > 4 go sparse
+constexpr int kGatherWgsAlone = 16 * 256;  // persistent-gather workgroups: a plan alone
+constexpr int kGatherWgsBatch = 5 * 256;   // and a plan in a batch
 constexpr uint32_t kBatchMagic = 0x4b42544eu;
 
 struct kpme_batch_s {
@@ -879,6 +881,7 @@ kpme_status kpme_plan_create_ex(kpme_plan_t* plan, const double box[3], const in
   }
   bg.sparse = spline_order >= 4 && spline_order <= 9 &&
               static_cast<double>(max_particles) < density * bg.nbricks;
+  bg.gather_wgs = kGatherWgsAlone;
   if (const char* env = std::getenv("KPME_SPARSE"))
     bg.sparse = spline_order >= 4 && spline_order <= 9 && std::atoi(env) != 0;
   pl->spread_parts = spread_partials(bg, spline_order, precision == KPME_FP64);
@@ -1739,6 +1742,9 @@ kpme_status kpme_batch_create(kpme_batch_t* batch, int count, const double* box3
     }
     done[key] = {pl->nparts, pl->s1_split, pl->streams};
   }
+  // The batch's systems fill the device together: their gathers keep several
+  // bricks per workgroup (fewer, longer workgroups)
+  for (kpme_plan_t pl : b->plans) pl->bins.geom.gather_wgs = kGatherWgsBatch;
   // The per-class tuning optimises one system alone on the whole device: it
   // splits a slab's terms over several workgroups to fill the CUs, at the
   // cost of a partial slab per range for finalize to write and sum.  In a

@@ -1441,13 +1441,15 @@ __device__ __forceinline__ void load_record(const double* sorted, long s, double
 constexpr int kGatherThreads = 256;
 constexpr int kGatherMaxBricks = 64;   // bricks per workgroup of the persistent gather
 
-// Workgroups of the persistent gather: one per brick up to sixteen per
-// compute unit, then the same number of bricks per workgroup up to one (at
-// most kGatherMaxBricks, since the grid has at most 32^3 bricks).  On the
-// 1M-atom box (4,096 bricks) one brick per workgroup measured 55.5 us against
-// 57.2 with four (about five workgroups per CU) and 67.4 with six.
-int gather_pf_workgroups(int nbricks) {
-  const int target = 16 * 256;
+// Workgroups of the persistent gather: one per brick up to `target` (the
+// plan's BinGeom::gather_wgs), then the same number of bricks per workgroup
+// up to one (at most kGatherMaxBricks, since the grid has at most 32^3
+// bricks).  A plan alone on the device takes sixteen per CU: on the 1M-atom
+// box (4,096 bricks) one brick per workgroup measured 55.5 us against 57.2
+// with four (about five workgroups per CU) and 67.4 with six.  In a batch,
+// whose systems fill the device together, five per CU keeps the per-workgroup
+// cost down (64-system batch gather 375 -> 329 us).
+int gather_pf_workgroups(int nbricks, int target) {
   const int per = std::max(1, (nbricks + target - 1) / target);
   return (nbricks + per - 1) / per;
 }
@@ -2092,7 +2094,7 @@ hipError_t gather_brick_p(const GridGeom& g, const Bins& b, int64_t n, const voi
   }
   if constexpr (sizeof(T) == 4 && P > 4 && P <= 9) {
     const int ntile = (b.geom.edge[0] + P - 1) * (b.geom.edge[1] + P - 1) * (b.geom.edge[2] + P - 1);
-    const int nw = gather_pf_workgroups(b.geom.nbricks);
+    const int nw = gather_pf_workgroups(b.geom.nbricks, b.geom.gather_wgs);
     if ((b.geom.nbricks + nw - 1) / nw > kGatherMaxBricks) return hipErrorInvalidValue;
     const bool e8 = b.geom.edge[0] == 8 && b.geom.edge[1] == 8 && b.geom.edge[2] == 8;
     if (e8)

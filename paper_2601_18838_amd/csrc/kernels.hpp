@@ -126,6 +126,8 @@ struct BinGeom {
                  // axis (itself and the next) and every tile extent <= K_j
   int sparse;    // few particles per brick: the owner spread also for
                  // orders 4 and up on float grids
+  int gather_wgs; // target workgroup count of the persistent gather (one
+                  // brick per workgroup up to it)
 };
 
 // Device buffers of the binned particle layout.
