@@ -75,6 +75,7 @@ def log(msg):
 # calls (fragments, splits, MFMA wrappers)
 CSRC = os.path.join(ROOT, "paper_2601_18838_amd", "csrc")
 STAGE2_SECTION = ("// Stage 2, split precision.", "// Stage 2, FP32 / FP64 with the 16x16x4 MFMAs.")
+KERNELS_HPP_GRID_SECTION = "// Grid kernels: binning, spread and gather."
 HBM_PEAK_GBS = 8000.0
 
 
@@ -85,8 +86,10 @@ def stage2_source_sha():
     a = text.index(STAGE2_SECTION[0])
     b = text.index(STAGE2_SECTION[1], a)
     h = hashlib.sha256(text[a:b].encode())
-    for f in ("kernels.hpp", "device_common.hpp"):
-        h.update(open(os.path.join(CSRC, f), "rb").read())
+    # the SKP part of the launch header (its argument struct and LDS layout)
+    hdr = open(os.path.join(CSRC, "kernels.hpp"), encoding="utf-8").read()
+    h.update(hdr[:hdr.index(KERNELS_HPP_GRID_SECTION)].encode())
+    h.update(open(os.path.join(CSRC, "device_common.hpp"), "rb").read())
     return h.hexdigest()
 
 

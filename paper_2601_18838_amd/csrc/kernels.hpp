@@ -102,6 +102,8 @@ hipError_t prepare_skp_stage2(const SkpArgs& a);
 hipError_t launch_skp_finalize(const SkpArgs& a, hipStream_t st);
 size_t stage2_lds_bytes(int prec, int K1P, int K2P, int streams);
 
+// Grid kernels: binning, spread and gather.
+
 struct GridGeom {
   int K[3];
   double L[3];
