@@ -246,6 +246,31 @@ def test_empty_and_capacity_edges(prec):
     assert abs(e_a - e_b) < 1e-5 * abs(e_a)
 
 
+@pytest.mark.parametrize("p", [4, 6])
+@pytest.mark.parametrize("form", ["auto", "dense"])
+def test_many_bricks_spread_and_gather(p, form, monkeypatch):
+    """A 128 x 256 x 256 grid (FP32; 16,384 bricks of 8^3, more than the
+    per-workgroup LDS histogram holds): binning counts with one global atomic
+    per particle and the one-workgroup scan takes sixteen counts per thread;
+    spread and gather (on a seeded random potential
+    grid) against the oracle, in the form chosen and forced into the home
+    tiles + combine form."""
+    print(f"[parity] many bricks p={p} {form}", flush=True)
+    if form == "dense":
+        monkeypatch.setenv("KPME_SPARSE", "0")
+    box, grid, beta, n = (64.0, 128.0, 128.0), (128, 256, 256), 0.5, 4000
+    pos, q = systems.uniform_pm1(n, box, 31)
+    pl = kp().Plan(box, grid, p, beta, rank=4, precision="fp32", max_particles=n)
+    P, Qc = dev(pos, "fp32"), dev(q, "fp32")
+    Q_ref = spme.spread(pos, q, box, grid, p)
+    assert relmax(host(pl.spread(P, Qc)), Q_ref) < 2e-6
+    Phi = np.random.default_rng(32).standard_normal(grid)
+    phi_ref, F_ref = spme.gather(pos, q, box, grid, p, Phi)
+    pot, frc = pl.gather(P, Qc, dev(Phi, "fp32"))
+    assert relmax(host(pot), phi_ref) < 1e-5
+    assert relmax(host(frc), F_ref) < 2e-5
+
+
 @pytest.mark.parametrize("case", ["small_pm1", "ragged_noncubic"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16x3"])
 def test_energy_paths_agree(prec, case):
