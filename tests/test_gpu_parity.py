@@ -271,6 +271,28 @@ def test_many_bricks_spread_and_gather(p, form, monkeypatch):
     assert relmax(host(frc), F_ref) < 2e-5
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_large_n_spread_and_gather(prec):
+    """300,000 particles on a 32^3 grid (64 bricks, ~4,700 particles each):
+    the binning count runs its 1024-thread workgroups (from 2^18 particles
+    on) and the scan folds into the scatter; spread and gather (on a seeded
+    random potential grid) against the oracle element by element."""
+    print(f"[parity] large n {prec}", flush=True)
+    box, grid, p, beta, n = (32.0, 32.0, 32.0), (32, 32, 32), 4, 0.5, 300000
+    pos, q = systems.uniform_pm1(n, box, 33)
+    pl = kp().Plan(box, grid, p, beta, rank=4, precision=prec, max_particles=n)
+    P, Qc = dev(pos, prec), dev(q, prec)
+    Q_ref = spme.spread(pos, q, box, grid, p)
+    tol = 1e-12 if prec == "fp64" else 2e-6
+    assert relmax(host(pl.spread(P, Qc)), Q_ref) < tol
+    Phi = np.random.default_rng(34).standard_normal(grid)
+    phi_ref, F_ref = spme.gather(pos, q, box, grid, p, Phi)
+    pot, frc = pl.gather(P, Qc, dev(Phi, prec))
+    tol = 1e-11 if prec == "fp64" else 1e-5
+    assert relmax(host(pot), phi_ref) < tol
+    assert relmax(host(frc), F_ref) < 2 * tol
+
+
 @pytest.mark.parametrize("case", ["small_pm1", "ragged_noncubic"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16x3"])
 def test_energy_paths_agree(prec, case):
